@@ -1,0 +1,215 @@
+/*
+ * rayborn.h - C ABI of the MI355X ray-Born single-step inversion library.
+ *
+ * The library implements one linearised frequency set of Hessian-free
+ * ray-Born inversion for 2-D ring-array sound-speed tomography
+ * (arXiv 2511.16633): ray tracing and ray-to-grid tables for the
+ * high-frequency Green's functions (Forward Problem section, Eqs. 4-7), the
+ * Born forward and weighted adjoint contractions and the diagonally weighted
+ * single step (Inverse Problem section, Eqs. 8-10 and the single-step
+ * paragraph).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers are DEVICE pointers unless marked [host].  The caller owns and
+ *    allocates every buffer; the library allocates no device memory.  Entry
+ *    points that need scratch take a caller workspace `ws` of `ws_bytes`
+ *    (256-byte aligned) sized by the matching *_workspace_bytes function.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is asynchronous unless stated; outputs are valid once the stream has
+ *    drained.  Entry points hold no global mutable state and may be called
+ *    concurrently on different streams with disjoint buffers.
+ *  - Grids are [ny][nx] row-major; pixel (i, j) has its centre at
+ *    (x0 + i h, y0 + j h); N = nx * ny.  Ring element e (0 <= e < m) sits at
+ *    R (cos 2 pi e / m, sin 2 pi e / m).  Outside the grid the medium is
+ *    water: slowness 1 / c_background and no absorption.
+ *  - Complex data are interleaved (re, im) FP64 pairs; data cubes are
+ *    [nf][m (emitter e)][m (receiver r)].
+ *  - SI units: m, s, Hz, m/s; absorption alpha0 in Np / (m MHz^y).
+ *  - Errors: invalid arguments are detected on the host before any work is
+ *    enqueued and return RB_EINVAL; a HIP launch/runtime failure returns
+ *    RB_EHIP; a workspace too small returns RB_ENOMEM.  rb_last_error()
+ *    gives a thread-local message for the last failure.  Nothing aborts.
+ */
+#ifndef RAYBORN_H
+#define RAYBORN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RB_OK = 0,
+    RB_EINVAL = -1,       /* invalid argument */
+    RB_ENOMEM = -2,       /* workspace too small */
+    RB_EHIP = -3,         /* HIP runtime or launch error */
+    RB_EUNSUPPORTED = -4, /* valid but unsupported combination */
+    RB_ENUMERIC = -5      /* 1/c^2 + delta <= 0 somewhere (update refused) */
+} rb_status;
+
+/* Storage type of the Green's tables G and of the contraction operands.
+ * RB_F64 accumulates in FP64; the others accumulate in FP32.  RB_BF16 and
+ * RB_F16 store G scaled by 1/scale[k] per frequency (see rb_build_green). */
+typedef enum { RB_F64 = 0, RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3 } rb_dtype;
+
+typedef struct {
+    int32_t nx, ny;        /* grid size, >= 1 each */
+    double h, x0, y0;      /* spacing (> 0) and centre of pixel (0, 0) */
+    int32_t m;             /* ring elements, 4 <= m <= 4096 */
+    double ring_radius;    /* R > 0 */
+    double support_margin; /* solution support: |x| < R - margin */
+    double c_background;   /* water speed outside the grid, > 0 */
+} rb_geometry;
+
+/* Ray fan options.  Travel time tau is the ray parameter; node n of every ray
+ * has T = n * dtau exactly.  nmax = floor(tau_max / dtau) steps at most; a
+ * ray ends at the first node with |x| > R + 2h.  j_min <= 0 means h / 4. */
+typedef struct {
+    int32_t n_rays;        /* rays per emitter, 3 <= n_rays <= 8192 */
+    double dtau;           /* > 0, s */
+    double tau_max;        /* > dtau, s */
+    double j_min;          /* floor on the ray-tube width J, m */
+} rb_trace_opts;
+
+/* Ray-to-grid tables: travel time T (FP64, NaN where no ray triangle covers
+ * the point), amplitude factor a = sqrt(c / (8 pi J)) and absorption
+ * integral B (FP32, 0 where uncovered).  Pixel tables are [m][N]
+ * (pixel-major per emitter); receiver tables are [m][m] (emitter, element). */
+typedef struct {
+    double *T;
+    float *amp;
+    float *att;
+    double *T_rx;
+    float *amp_rx;
+    float *att_rx;
+} rb_tables;
+
+typedef struct {
+    double recv_fraction;    /* receivers used per emitter, (0, 1]; 0.75 */
+    double outlier_fraction; /* largest-|p_meas| fraction zeroed, [0, 1); 0.01 */
+    double eps;              /* damping, relative to max Hd on the support; 1e-3 */
+    double y_pow;            /* absorption power law exponent y; 1 */
+    rb_dtype dtype;          /* storage/contraction type */
+} rb_invert_opts;
+
+/* Largest number of frequencies one call accepts. */
+#define RB_MAX_NF 16
+
+/*
+ * Ray tracing and ray-to-grid tables (Forward Problem: Eqs. 4-7; Discussion:
+ * "ray tracing", "amplitude computation", "back-propagation of ray
+ * parameters").
+ *
+ * For every emitter e, a fan of n_rays rays is launched into the inward
+ * half-plane (angles theta_e + pi + (j + 1/2 - n_rays/2) pi / n_rays) with
+ * |p| = s(x_e) and integrated by classic RK4 in travel time:
+ *     dx/dtau = p / s^2,  dp/dtau = grad s / s,  dB/dtau = alpha0 / s,
+ * where s and alpha0 are bilinear between pixel centres (water outside).
+ * The spreading J = |dx/dpsi| at equal tau is taken from neighbouring rays
+ * (central chord / (2 sin dpsi), one-sided chord / (2 sin(dpsi/2)) at the
+ * fan edges), giving a = sqrt(c(x) / (8 pi max(J, j_min))).  Each cell of
+ * the wavefront mesh is split into two triangles; pixel centres and ring
+ * elements inside a triangle (barycentrics >= -1e-12) take the barycentric
+ * T, a, B; the smallest T wins (first arrival), exact ties going to the
+ * triangle first in (step, ray, triangle) order.
+ *
+ * slowness: [N] FP64 s = 1/c.  alpha0: [N] FP64 or NULL (no absorption).
+ * out: all six table pointers required.  ws: rb_trace_workspace_bytes().
+ * The work is split into batches of emitters that fit the workspace.
+ */
+size_t rb_trace_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t,
+                                int32_t emitter_batch);
+rb_status rb_trace_rays(const rb_geometry *g, const rb_trace_opts *t,
+                        const double *slowness, const double *alpha0,
+                        const rb_tables *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Green's tables from ray tables (Eqs. 4-5, high-frequency 2-D Green's
+ * function A exp(i[omega T + pi/4]) with A = A_geom A_abs):
+ *     G_e(x, f) = a omega^(-1/2) exp(-B (f / 1 MHz)^y) exp(i 2 pi frac(f T + 1/8)),
+ * zero where T is NaN.  The phase is reduced in FP64 (cycles, not radians).
+ *
+ * freqs_hz: [host][nf], 1 <= nf <= RB_MAX_NF, each > 0.
+ * G_re, G_im: planar [nf][m][N] of `dtype` (double, float, bf16 or fp16).
+ * scale: [nf] FP32 device output (may be NULL for RB_F64 / RB_F32, where it
+ * is 1); for RB_BF16 / RB_F16 the stored value is G / scale[k] with
+ * scale[k] = max(a) omega_k^(-1/2), so every stored |G| <= 1.
+ * ws: rb_green_workspace_bytes() (a few KB, used by the 16-bit types).
+ */
+size_t rb_green_workspace_bytes(void);
+rb_status rb_build_green(const rb_geometry *g, const rb_tables *tab,
+                         const double *freqs_hz, int32_t nf, double y_pow, rb_dtype dtype,
+                         void *G_re, void *G_im, float *scale, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * Born forward operator (linearised Eq. 1 in q = 1/c^2, s(omega) = 1 in
+ * Eq. 2, reciprocity of the Green's function):
+ *     d_er(omega) = omega^2 h^2 sum_x G_e(x, omega) G_r(x, omega) delta(x).
+ * delta: [N] FP64 perturbation of q.  d_out: [nf][m][m] complex (written,
+ * symmetric in e, r).  G as produced by rb_build_green; scale as there
+ * (NULL = 1).  ws: rb_forward_workspace_bytes().
+ */
+size_t rb_forward_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype);
+rb_status rb_born_forward(const rb_geometry *g, const void *G_re, const void *G_im,
+                          const float *scale, rb_dtype dtype, const double *freqs_hz,
+                          int32_t nf, const double *delta, double *d_out,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Weighted adjoint (backprojection) and Hessian diagonal (gradient and
+ * diagonal of the Gauss-Newton Hessian of Eq. 10 under the data weight W):
+ *     grad(x)  += sum_k omega_k^2 h^2 Re sum_{e,r} conj(G_e G_r) W_er d_er,
+ *     hdiag(x) += sum_k omega_k^4 h^4 sum_{e,r} W_er |G_e|^2 |G_r|^2.
+ * d_res: [nf][m][m] complex; w_data: [nf][m][m] real >= 0.  grad, hdiag:
+ * [N] FP64, accumulated into (hdiag may be NULL).  Deterministic: repeated
+ * calls give bitwise-identical results.  ws: rb_adjoint_workspace_bytes().
+ */
+size_t rb_adjoint_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype);
+rb_status rb_born_adjoint_weighted(const rb_geometry *g, const void *G_re, const void *G_im,
+                                   const float *scale, rb_dtype dtype, const double *freqs_hz,
+                                   int32_t nf, const double *d_res, const double *w_data,
+                                   double *grad, double *hdiag, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/*
+ * One linearised frequency set, Hessian-free single step (Inverse Problem
+ * section; Results section for the data handling):
+ *  1. trace rays in c_in and build the tables and the Green's functions;
+ *  2. modelled data p_er = G_e(x_r); residual D = p_meas - p;
+ *  3. data weight W = receiver selection (circular index distance
+ *     >= ceil((1 - recv_fraction) m / 2)) x outlier zeroing (per frequency,
+ *     the floor(outlier_fraction n_valid) selected pairs with the largest
+ *     |p_meas|^2, ties to the smaller e*m + r);
+ *  4. grad = J^T W D and Hd = diag(J^T W J);
+ *  5. v = grad / (Hd + eps max_S Hd) on the support S (|x| < R - margin and
+ *     covered by every emitter), 0 elsewhere;
+ *  6. beta = Re<J v, W D> / <J v, W J v> (0 if the denominator is 0);
+ *  7. c_out = (1/c_in^2 + beta v)^(-1/2) where beta v != 0, c_in elsewhere.
+ * c_in, c_out: [N] FP64 (may alias).  alpha0: [N] FP64 or NULL.  p_meas:
+ * [nf][m][m] complex.  dc_l2: [host] receives sqrt(sum (c_out - c_in)^2);
+ * the call synchronises `stream` to deliver it.  Returns RB_ENUMERIC (and
+ * leaves c_out = c_in) if 1/c^2 + delta <= 0 at any updated pixel.
+ * ws: rb_invert_workspace_bytes().
+ */
+size_t rb_invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int32_t nf,
+                                 rb_dtype dtype, int32_t emitter_batch);
+rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t,
+                                  const rb_invert_opts *o, const double *c_in,
+                                  const double *alpha0, const double *freqs_hz, int32_t nf,
+                                  const double *p_meas, double *c_out, double *dc_l2,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *rb_status_string(rb_status s);
+/* Thread-local detail of the last failure on this thread ("" if none). */
+const char *rb_last_error(void);
+/* Library version string. */
+const char *rb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYBORN_H */

@@ -1,0 +1,244 @@
+"""ctypes binding for librayborn.so: argument marshalling only.
+
+Function names match the C entry points without the ``rb_`` prefix.  Device
+buffers are torch tensors on a HIP device; the stream defaults to torch's
+current stream.  Status codes other than RB_OK raise RayBornError (or its
+subclass NumericError for RB_ENUMERIC) carrying the library's message.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "librayborn.so")
+
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+TORCH_DTYPES = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}
+RB_ENUMERIC = -5
+
+
+class RayBornError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rayborn status {status}: {msg}")
+        self.status = status
+
+
+class NumericError(RayBornError):
+    pass
+
+
+class RbGeometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("m", ctypes.c_int32),
+                ("ring_radius", ctypes.c_double), ("support_margin", ctypes.c_double),
+                ("c_background", ctypes.c_double)]
+
+
+class RbTraceOpts(ctypes.Structure):
+    _fields_ = [("n_rays", ctypes.c_int32), ("dtau", ctypes.c_double),
+                ("tau_max", ctypes.c_double), ("j_min", ctypes.c_double)]
+
+
+class RbTables(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("T", "amp", "att", "T_rx", "amp_rx", "att_rx")]
+
+
+class RbInvertOpts(ctypes.Structure):
+    _fields_ = [("recv_fraction", ctypes.c_double), ("outlier_fraction", ctypes.c_double),
+                ("eps", ctypes.c_double), ("y_pow", ctypes.c_double), ("dtype", ctypes.c_int)]
+
+
+_lib = None
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+
+
+def lib():
+    """Load librayborn.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise RuntimeError(f"{lib_path} is missing: build it with __graft_entry__.build() "
+                           "or python paper_2511_16633_amd/build.py")
+    L = ctypes.CDLL(lib_path)
+    sig = {
+        "rb_trace_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32]),
+        "rb_trace_rays": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _vp, _vp, _P(RbTables), _vp, _sz, _vp]),
+        "rb_green_workspace_bytes": (_sz, []),
+        "rb_build_green": (ctypes.c_int, [_P(RbGeometry), _P(RbTables), _P(_d), _i32, _d, ctypes.c_int,
+                                          _vp, _vp, _vp, _vp, _sz, _vp]),
+        "rb_forward_workspace_bytes": (_sz, [_P(RbGeometry), _i32, ctypes.c_int]),
+        "rb_born_forward": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32, _vp, _vp,
+                                           _vp, _sz, _vp]),
+        "rb_adjoint_workspace_bytes": (_sz, [_P(RbGeometry), _i32, ctypes.c_int]),
+        "rb_born_adjoint_weighted": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32,
+                                                    _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "rb_invert_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int, _i32]),
+        "rb_invert_frequency_set": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp, _vp,
+                                                   _P(_d), _i32, _vp, _vp, _P(_d), _vp, _sz, _vp]),
+        "rb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "rb_last_error": (ctypes.c_char_p, []),
+        "rb_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def version() -> str:
+    return lib().rb_version().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        L = lib()
+        msg = f"{L.rb_status_string(rc).decode()}: {L.rb_last_error().decode()}"
+        if rc == RB_ENUMERIC:
+            raise NumericError(rc, msg)
+        raise RayBornError(rc, msg)
+
+
+def _dt(dtype) -> int:
+    return DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _freqs(freqs: Sequence[float]):
+    arr = (ctypes.c_double * len(freqs))(*[float(f) for f in freqs])
+    return arr, len(freqs)
+
+
+def geometry_struct(g) -> RbGeometry:
+    return RbGeometry(nx=g.nx, ny=g.ny, h=g.h, x0=g.x0, y0=g.y0, m=g.m, ring_radius=g.ring_radius,
+                      support_margin=g.support_margin, c_background=g.c_background)
+
+
+def trace_opts_struct(t) -> RbTraceOpts:
+    return RbTraceOpts(n_rays=t.n_rays, dtau=t.dtau, tau_max=t.tau_max, j_min=t.j_min)
+
+
+def invert_opts_struct(o, dtype) -> RbInvertOpts:
+    return RbInvertOpts(recv_fraction=o.recv_fraction, outlier_fraction=o.outlier_fraction, eps=o.eps,
+                        y_pow=o.y_pow, dtype=_dt(dtype))
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def alloc_tables(g, device) -> dict:
+    N, m = g.nx * g.ny, g.m
+    return {"T": torch.empty((m, N), dtype=torch.float64, device=device),
+            "amp": torch.empty((m, N), dtype=torch.float32, device=device),
+            "att": torch.empty((m, N), dtype=torch.float32, device=device),
+            "T_rx": torch.empty((m, m), dtype=torch.float64, device=device),
+            "amp_rx": torch.empty((m, m), dtype=torch.float32, device=device),
+            "att_rx": torch.empty((m, m), dtype=torch.float32, device=device)}
+
+
+def _tables_struct(tab: dict) -> RbTables:
+    return RbTables(**{k: tab[k].data_ptr() for k in ("T", "amp", "att", "T_rx", "amp_rx", "att_rx")})
+
+
+def trace_workspace_bytes(g, t, emitter_batch: int = 0) -> int:
+    return int(lib().rb_trace_workspace_bytes(ctypes.byref(geometry_struct(g)),
+                                              ctypes.byref(trace_opts_struct(t)), emitter_batch))
+
+
+def green_workspace_bytes() -> int:
+    return int(lib().rb_green_workspace_bytes())
+
+
+def forward_workspace_bytes(g, nf: int, dtype) -> int:
+    return int(lib().rb_forward_workspace_bytes(ctypes.byref(geometry_struct(g)), nf, _dt(dtype)))
+
+
+def adjoint_workspace_bytes(g, nf: int, dtype) -> int:
+    return int(lib().rb_adjoint_workspace_bytes(ctypes.byref(geometry_struct(g)), nf, _dt(dtype)))
+
+
+def invert_workspace_bytes(g, t, nf: int, dtype, emitter_batch: int = 0) -> int:
+    return int(lib().rb_invert_workspace_bytes(ctypes.byref(geometry_struct(g)),
+                                               ctypes.byref(trace_opts_struct(t)), nf, _dt(dtype),
+                                               emitter_batch))
+
+
+def trace_rays(g, t, slowness: torch.Tensor, alpha0: Optional[torch.Tensor], tables: dict,
+               ws: Optional[torch.Tensor] = None, stream=None) -> dict:
+    if ws is None:
+        ws = _ws(trace_workspace_bytes(g, t), slowness.device)
+    _check(lib().rb_trace_rays(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                               _ptr(slowness), _ptr(alpha0), ctypes.byref(_tables_struct(tables)),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+    return tables
+
+
+def build_green(g, tables: dict, freqs, y_pow: float, dtype, G_re: torch.Tensor, G_im: torch.Tensor,
+                scale: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(green_workspace_bytes(), G_re.device)
+    _check(lib().rb_build_green(ctypes.byref(geometry_struct(g)), ctypes.byref(_tables_struct(tables)), fa, nf,
+                                float(y_pow), _dt(dtype), _ptr(G_re), _ptr(G_im), _ptr(scale), _ptr(ws),
+                                ws.numel(), _stream(stream)))
+
+
+def born_forward(g, G_re, G_im, scale, dtype, freqs, delta: torch.Tensor, d_out: torch.Tensor,
+                 ws: Optional[torch.Tensor] = None, stream=None):
+    """d_out: float64 [nf][m][m][2] (or complex128 [nf][m][m])."""
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(forward_workspace_bytes(g, nf, dtype), delta.device)
+    _check(lib().rb_born_forward(ctypes.byref(geometry_struct(g)), _ptr(G_re), _ptr(G_im), _ptr(scale),
+                                 _dt(dtype), fa, nf, _ptr(delta), _ptr(d_out), _ptr(ws), ws.numel(),
+                                 _stream(stream)))
+
+
+def born_adjoint_weighted(g, G_re, G_im, scale, dtype, freqs, d_res: torch.Tensor, w_data: torch.Tensor,
+                          grad: torch.Tensor, hdiag: Optional[torch.Tensor],
+                          ws: Optional[torch.Tensor] = None, stream=None):
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(adjoint_workspace_bytes(g, nf, dtype), grad.device)
+    _check(lib().rb_born_adjoint_weighted(ctypes.byref(geometry_struct(g)), _ptr(G_re), _ptr(G_im), _ptr(scale),
+                                          _dt(dtype), fa, nf, _ptr(d_res), _ptr(w_data), _ptr(grad),
+                                          _ptr(hdiag), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def invert_frequency_set(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[torch.Tensor], freqs,
+                         p_meas: torch.Tensor, c_out: torch.Tensor, ws: Optional[torch.Tensor] = None,
+                         stream=None) -> float:
+    """Returns the update norm sqrt(sum (c_out - c_in)^2); synchronises the stream."""
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(invert_workspace_bytes(g, t, nf, dtype), c_in.device)
+    out = ctypes.c_double(0.0)
+    _check(lib().rb_invert_frequency_set(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                                         ctypes.byref(invert_opts_struct(o, dtype)), _ptr(c_in), _ptr(alpha0),
+                                         fa, nf, _ptr(p_meas), _ptr(c_out), ctypes.byref(out), _ptr(ws),
+                                         ws.numel(), _stream(stream)))
+    return out.value

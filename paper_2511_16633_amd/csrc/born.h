@@ -1,0 +1,33 @@
+// Born contraction kernels: parameters and host entry points shared with the
+// inversion driver.
+#pragma once
+#include "common.h"
+
+namespace rb {
+
+struct AdjParams {
+    int m, mp, nb, nf;
+    int64_t N;
+    double cg[RB_MAX_NF];  // omega^2 h^2
+    double ch[RB_MAX_NF];  // omega^4 h^4
+};
+
+struct FwdParams {
+    int m, mp, nf, ntl, ntri, nsplit;
+    int64_t N, kchunk;
+    double cg[RB_MAX_NF];  // omega^2 h^2
+};
+
+size_t adjoint_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt);
+size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt);
+
+// grad/hdiag += (see rb_born_adjoint_weighted); gscale may be null for 32/64-bit.
+rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
+                       double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st);
+// d_out = J delta, [nf][m][m] complex.
+rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
+                       size_t ws_bytes, hipStream_t st);
+
+}  // namespace rb

@@ -1,0 +1,860 @@
+// Born forward operator and weighted adjoint (backprojection) with the
+// diagonal of the Gauss-Newton Hessian (paper, Inverse Problem section,
+// Eqs. 8-10; linearisation of Eq. 1 in q = 1/c^2 with Green's functions from
+// Eqs. 4-5).
+//
+//   forward:  d_er = omega^2 h^2 sum_x G_e(x) G_r(x) delta(x)
+//   adjoint:  grad(x) = omega^2 h^2 Re sum_e conj(G_e(x)) Y_e(x),
+//             Y_e(x)  = sum_r A_er conj(G_r(x)),      A = W . D
+//   Hessian:  hd(x)   = omega^4 h^4 sum_e |G_e(x)|^2 Z_e(x),
+//             Z_e(x)  = sum_r W_er |G_r(x)|^2
+//
+// Both are dense contractions over emitter x receiver pairs, so they run on
+// the matrix cores.  Complex products are expanded into real MFMAs:
+//   Yr  = Ar.Gr + Ai.Gi,   -Yi = Ar.Gi + (-Ai).Gr,   Z = W.|G|^2
+// and the reduction over e against G_e(x) is fused into the epilogue, so Y
+// and Z never leave registers.  A k-permutation (lane group kk supplies
+// k = 4 kk + s at MFMA step s) lets each lane fetch its A fragment with one
+// vector load.  Blocks of A whose weights are all zero (the receiver
+// selection removes a band around the diagonal) are skipped per 16x16 block.
+// The forward operator is a split-K GEMM over pixels whose symmetric output
+// is computed on upper-triangular tiles only and reduced in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "born.h"
+#include "common.h"
+
+namespace rb {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct MM;
+// Both 16x16x4 forms read A[i][k] from lane i + 16k and B[k][j] from lane
+// j + 16k.  Output element `i` of lane group kk (lanes 16kk..16kk+15, column
+// = lane % 16) holds row 4kk + i for f32 but row kk + 4i for f64 (measured).
+template <>
+struct MM<float> {
+    using acc = f4;
+    __device__ __forceinline__ static acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int out_row(int kk, int i) { return 4 * kk + i; }
+};
+template <>
+struct MM<double> {
+    using acc = d4;
+    __device__ __forceinline__ static acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int out_row(int kk, int i) { return kk + 4 * i; }
+};
+
+// 16-bit storage types and their MFMA (16x16x32, 8 k-values per lane).
+template <typename S>
+struct MM16;
+template <>
+struct MM16<__hip_bfloat16> {
+    using vec = bf8;
+    __device__ __forceinline__ static f4 mma(vec a, vec b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static float to_f(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ __forceinline__ static __bf16 from_f(float v) {
+        __hip_bfloat16 b = __float2bfloat16(v);
+        return *reinterpret_cast<__bf16 *>(&b);
+    }
+};
+template <>
+struct MM16<__half> {
+    using vec = h8;
+    __device__ __forceinline__ static f4 mma(vec a, vec b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static float to_f(__half v) { return __half2float(v); }
+    __device__ __forceinline__ static _Float16 from_f(float v) { return (_Float16)v; }
+};
+
+typedef short s8 __attribute__((ext_vector_type(8)));
+// sign flip of eight 16-bit floats (bf16 and fp16 keep the sign in bit 15)
+template <typename V>
+__device__ __forceinline__ V neg(V v) {
+    s8 b = __builtin_bit_cast(s8, v);
+    b ^= (short)0x8000;
+    return __builtin_bit_cast(V, b);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T *p, bool ok) {
+    return ok ? p[0] : T(0);
+}
+
+// ------------------------------------------------------------------ adjoint
+// WG = 4 waves; wave w owns 16*CB pixels; rows are processed 16*RB at a time.
+template <typename T, int RB, int CB>
+__global__ void __launch_bounds__(256) k_adjoint(AdjParams P, const T *__restrict__ Gr, const T *__restrict__ Gi,
+                                                 const T *__restrict__ Ar, const T *__restrict__ Ai,
+                                                 const T *__restrict__ Wt, const uint8_t *__restrict__ flags,
+                                                 double *__restrict__ grad, double *__restrict__ hd) {
+    using acc_t = typename MM<T>::acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t N = P.N;
+    const int64_t xw = (int64_t)blockIdx.x * (64 * CB) + (int64_t)wave * 16 * CB;
+    double gacc[CB], hacc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) gacc[c] = hacc[c] = 0.0;
+
+    for (int k = 0; k < P.nf; ++k) {
+        const T *gr = Gr + (int64_t)k * P.m * N;
+        const T *gi = Gi + (int64_t)k * P.m * N;
+        const T *ar = Ar + (int64_t)k * P.mp * P.mp;
+        const T *ai = Ai + (int64_t)k * P.mp * P.mp;
+        const T *wt = Wt + (int64_t)k * P.mp * P.mp;
+        const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
+        T gp[CB], hp[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) gp[c] = hp[c] = T(0);
+        for (int ec = 0; ec < P.mp; ec += 16 * RB) {
+            acc_t yr[RB][CB], yn[RB][CB], z[RB][CB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) yr[b][c] = yn[b][c] = z[b][c] = acc_t{0, 0, 0, 0};
+            for (int rc = 0; rc < P.mp; rc += 16) {
+                bool on[RB];
+                bool any = false;
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    const int eb = ec / 16 + b;
+                    on[b] = (eb < P.nb) && fl[eb * P.nb + rc / 16];
+                    any |= on[b];
+                }
+                if (!any) continue;
+                T br[4][CB], bi[4][CB], b2[4][CB];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = rc + 4 * kk + s;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        const int64_t x = xw + 16 * c + row;
+                        const bool ok = (r < P.m) && (x < N);
+                        br[s][c] = ld(gr + (int64_t)r * N + x, ok);
+                        bi[s][c] = ld(gi + (int64_t)r * N + x, ok);
+                        b2[s][c] = br[s][c] * br[s][c] + bi[s][c] * bi[s][c];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    if (!on[b]) continue;
+                    const int64_t off = (int64_t)(ec + 16 * b + row) * P.mp + rc + 4 * kk;
+                    T va[4], vi[4], vw[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        va[s] = ar[off + s];
+                        vi[s] = ai[off + s];
+                        vw[s] = wt[off + s];
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) {
+                            yr[b][c] = MM<T>::mma(va[s], br[s][c], yr[b][c]);
+                            yr[b][c] = MM<T>::mma(vi[s], bi[s][c], yr[b][c]);
+                            yn[b][c] = MM<T>::mma(va[s], bi[s][c], yn[b][c]);
+                            yn[b][c] = MM<T>::mma(-vi[s], br[s][c], yn[b][c]);
+                            z[b][c] = MM<T>::mma(vw[s], b2[s][c], z[b][c]);
+                        }
+                    }
+                }
+            }
+            // fused epilogue: reduce over the e rows of this chunk against G_e
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = ec + 16 * b + MM<T>::out_row(kk, i);
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        const int64_t x = xw + 16 * c + row;
+                        const bool ok = (e < P.m) && (x < N);
+                        const T ge_r = ld(gr + (int64_t)e * N + x, ok);
+                        const T ge_i = ld(gi + (int64_t)e * N + x, ok);
+                        gp[c] += ge_r * yr[b][c][i] - ge_i * yn[b][c][i];
+                        hp[c] += (ge_r * ge_r + ge_i * ge_i) * z[b][c][i];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            gacc[c] += (double)gp[c] * P.cg[k];
+            hacc[c] += (double)hp[c] * P.ch[k];
+        }
+    }
+    // sum the four lane groups that hold the same pixel (fixed order)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        double g = gacc[c], h = hacc[c];
+        g += __shfl_xor(g, 16);
+        h += __shfl_xor(h, 16);
+        g += __shfl_xor(g, 32);
+        h += __shfl_xor(h, 32);
+        const int64_t x = xw + 16 * c + row;
+        if (kk == 0 && x < N) {
+            grad[x] += g;
+            if (hd) hd[x] += h;
+        }
+    }
+}
+
+// 16-bit variant: MFMA 16x16x32 with FP32 accumulation.  Lane group kk
+// supplies k = 8 kk + i (i = 0..7); operands are stored pre-scaled.
+template <typename S, int RB, int CB>
+__global__ void __launch_bounds__(256) k_adjoint16(AdjParams P, const S *__restrict__ Gr, const S *__restrict__ Gi,
+                                                   const S *__restrict__ Ar, const S *__restrict__ Ai,
+                                                   const S *__restrict__ Wt, const uint8_t *__restrict__ flags,
+                                                   const float *__restrict__ gscale,
+                                                   const float *__restrict__ ascale, double *__restrict__ grad,
+                                                   double *__restrict__ hd) {
+    using V = typename MM16<S>::vec;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t N = P.N;
+    const int64_t xw = (int64_t)blockIdx.x * (64 * CB) + (int64_t)wave * 16 * CB;
+    double gacc[CB], hacc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) gacc[c] = hacc[c] = 0.0;
+
+    for (int k = 0; k < P.nf; ++k) {
+        const S *gr = Gr + (int64_t)k * P.m * N;
+        const S *gi = Gi + (int64_t)k * P.m * N;
+        const S *ar = Ar + (int64_t)k * P.mp * P.mp;
+        const S *ai = Ai + (int64_t)k * P.mp * P.mp;
+        const S *wt = Wt + (int64_t)k * P.mp * P.mp;
+        const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
+        float gp[CB], hp[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) gp[c] = hp[c] = 0.0f;
+        for (int ec = 0; ec < P.mp; ec += 16 * RB) {
+            f4 yr[RB][CB], yn[RB][CB], z[RB][CB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
+            for (int rc = 0; rc < P.mp; rc += 32) {
+                bool on[RB];
+                bool any = false;
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    const int eb = ec / 16 + b;
+                    on[b] = (eb < P.nb) && (fl[eb * P.nb + rc / 16] || fl[eb * P.nb + rc / 16 + 1]);
+                    any |= on[b];
+                }
+                if (!any) continue;
+                V br[CB], bi[CB], b2[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const int64_t x = xw + 16 * c + row;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int r = rc + 8 * kk + i;
+                        const bool ok = (r < P.m) && (x < N);
+                        const float fr = ok ? MM16<S>::to_f(gr[(int64_t)r * N + x]) : 0.0f;
+                        const float fi = ok ? MM16<S>::to_f(gi[(int64_t)r * N + x]) : 0.0f;
+                        br[c][i] = MM16<S>::from_f(fr);
+                        bi[c][i] = MM16<S>::from_f(fi);
+                        b2[c][i] = MM16<S>::from_f(fr * fr + fi * fi);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    if (!on[b]) continue;
+                    const int64_t off = (int64_t)(ec + 16 * b + row) * P.mp + rc + 8 * kk;
+                    const V va = *reinterpret_cast<const V *>(ar + off);
+                    const V vi = *reinterpret_cast<const V *>(ai + off);
+                    const V vw = *reinterpret_cast<const V *>(wt + off);
+                    const V vn = neg(vi);
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        yr[b][c] = MM16<S>::mma(va, br[c], yr[b][c]);
+                        yr[b][c] = MM16<S>::mma(vi, bi[c], yr[b][c]);
+                        yn[b][c] = MM16<S>::mma(va, bi[c], yn[b][c]);
+                        yn[b][c] = MM16<S>::mma(vn, br[c], yn[b][c]);
+                        z[b][c] = MM16<S>::mma(vw, b2[c], z[b][c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = ec + 16 * b + 4 * kk + i;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        const int64_t x = xw + 16 * c + row;
+                        const bool ok = (e < P.m) && (x < N);
+                        const float ge_r = ok ? MM16<S>::to_f(gr[(int64_t)e * N + x]) : 0.0f;
+                        const float ge_i = ok ? MM16<S>::to_f(gi[(int64_t)e * N + x]) : 0.0f;
+                        gp[c] += ge_r * yr[b][c][i] - ge_i * yn[b][c][i];
+                        hp[c] += (ge_r * ge_r + ge_i * ge_i) * z[b][c][i];
+                    }
+                }
+            }
+        }
+        const double gs = (double)gscale[k], as = (double)ascale[k];
+        const double g2 = gs * gs;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            gacc[c] += (double)gp[c] * (P.cg[k] * g2 * as);
+            hacc[c] += (double)hp[c] * (P.ch[k] * g2 * g2);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        double g = gacc[c], h = hacc[c];
+        g += __shfl_xor(g, 16);
+        h += __shfl_xor(h, 16);
+        g += __shfl_xor(g, 32);
+        h += __shfl_xor(h, 32);
+        const int64_t x = xw + 16 * c + row;
+        if (kk == 0 && x < N) {
+            grad[x] += g;
+            if (hd) hd[x] += h;
+        }
+    }
+}
+
+// Operands of the adjoint: A = W . D (re, im) and W in the storage type,
+// padded to mp x mp with zeros.  For 16-bit types A is divided by ascale[k]
+// = max |W D| (W is 0/1-valued in the inversion, stored unscaled).
+template <typename T>
+__device__ __forceinline__ T cvt(double v);
+template <>
+__device__ __forceinline__ double cvt<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ float cvt<float>(double v) { return (float)v; }
+template <>
+__device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+template <>
+__device__ __forceinline__ __half cvt<__half>(double v) { return __float2half((float)v); }
+
+__global__ void k_adj_absmax(int m, const double *__restrict__ d, const double *__restrict__ w,
+                             float *__restrict__ ascale) {
+    // one block per frequency
+    __shared__ double sh[256];
+    const int k = blockIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    double best = 0.0;
+    for (int64_t i = threadIdx.x; i < mm; i += 256) {
+        const int64_t q = (int64_t)k * mm + i;
+        const double wv = w[q];
+        const double re = wv * d[2 * q], im = wv * d[2 * q + 1];
+        best = fmax(best, fmax(fabs(re), fabs(im)));
+    }
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ascale[k] = sh[0] > 0.0 ? (float)sh[0] : 1.0f;
+}
+
+template <typename T, bool SCALED>
+__global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, const double *__restrict__ w,
+                           const float *__restrict__ ascale, T *__restrict__ Ar, T *__restrict__ Ai,
+                           T *__restrict__ Wt) {
+    const int64_t per = (int64_t)mp * mp;
+    const int64_t tot = per * nf;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(idx / per);
+        const int64_t rem = idx - (int64_t)k * per;
+        const int e = (int)(rem / mp), r = (int)(rem - (int64_t)e * mp);
+        double re = 0.0, im = 0.0, wv = 0.0;
+        if (e < m && r < m) {
+            const int64_t q = ((int64_t)k * m + e) * m + r;
+            wv = w[q];
+            re = wv * d[2 * q];
+            im = wv * d[2 * q + 1];
+            if (SCALED) {
+                const double inv = 1.0 / (double)ascale[k];
+                re *= inv;
+                im *= inv;
+            }
+        }
+        Ar[idx] = cvt<T>(re);
+        Ai[idx] = cvt<T>(im);
+        Wt[idx] = cvt<T>(wv);
+    }
+}
+
+// flags[k][eb][rb] = 1 if any weight of the 16x16 block is nonzero
+__global__ void k_block_flags(int m, int nb, int nf, const double *__restrict__ w, uint8_t *__restrict__ flags) {
+    const int64_t tot = (int64_t)nf * nb * nb;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int k = (int)(idx / ((int64_t)nb * nb));
+    const int64_t rem = idx - (int64_t)k * nb * nb;
+    const int eb = (int)(rem / nb), rb = (int)(rem - (int64_t)eb * nb);
+    uint8_t any = 0;
+    for (int i = 0; i < 16 && !any; ++i) {
+        const int e = eb * 16 + i;
+        if (e >= m) break;
+        for (int j = 0; j < 16; ++j) {
+            const int r = rb * 16 + j;
+            if (r >= m) break;
+            if (w[((int64_t)k * m + e) * m + r] != 0.0) {
+                any = 1;
+                break;
+            }
+        }
+    }
+    flags[idx] = any;
+}
+
+// ------------------------------------------------------------------ forward
+// Output tile 64x64 (e, r) with tile_e <= tile_r; wave w owns rows 16w..+15
+// and four 16-column blocks; K = pixels [ks, ks + kchunk).
+__device__ __forceinline__ void tri_tile(int t, int ntl, int &te, int &tr) {
+    // enumerate (te, tr) with te <= tr row by row
+    int a = 0;
+    while (t >= ntl - a) {
+        t -= ntl - a;
+        ++a;
+    }
+    te = a;
+    tr = a + t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_forward(FwdParams P, const T *__restrict__ Gr, const T *__restrict__ Gi,
+                                                 const double *__restrict__ delta, T *__restrict__ part) {
+    using acc_t = typename MM<T>::acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const T *gr = Gr + (int64_t)k * P.m * N;
+    const T *gi = Gi + (int64_t)k * P.m * N;
+    const int e = te * 64 + 16 * wave + row;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    acc_t re[4], im[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) re[c] = im[c] = acc_t{0, 0, 0, 0};
+    for (int64_t xc = ks; xc < ke; xc += 16) {
+        T a_r[4], a_i[4], dl[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t x = xc + 4 * kk + s;
+            const bool okx = x < ke;
+            dl[s] = okx ? (T)delta[x] : T(0);
+            a_r[s] = ld(gr + (int64_t)e * N + x, okx && e < P.m);
+            a_i[s] = ld(gi + (int64_t)e * N + x, okx && e < P.m);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int64_t x = xc + 4 * kk + s;
+                const bool ok = (x < ke) && (r < P.m);
+                const T b_r = ld(gr + (int64_t)r * N + x, ok) * dl[s];
+                const T b_i = ld(gi + (int64_t)r * N + x, ok) * dl[s];
+                re[c] = MM<T>::mma(a_r[s], b_r, re[c]);
+                re[c] = MM<T>::mma(-a_i[s], b_i, re[c]);
+                im[c] = MM<T>::mma(a_r[s], b_i, im[c]);
+                im[c] = MM<T>::mma(a_i[s], b_r, im[c]);
+            }
+        }
+    }
+    // partial tile -> part[split][k][e][r][2]
+    T *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ee = te * 64 + 16 * wave + MM<T>::out_row(kk, i);
+            const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+            pp[o] = re[c][i];
+            pp[o + 1] = im[c][i];
+        }
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_forward16(FwdParams P, const S *__restrict__ Gr, const S *__restrict__ Gi,
+                                                   const double *__restrict__ delta,
+                                                   const double *__restrict__ dmax, float *__restrict__ part) {
+    using V = typename MM16<S>::vec;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const S *gr = Gr + (int64_t)k * P.m * N;
+    const S *gi = Gi + (int64_t)k * P.m * N;
+    const int e = te * 64 + 16 * wave + row;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const double inv_d = dmax[0] > 0.0 ? 1.0 / dmax[0] : 0.0;
+    f4 re[4], im[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) re[c] = im[c] = f4{0, 0, 0, 0};
+    for (int64_t xc = ks; xc < ke; xc += 32) {
+        V a_r, a_i, a_n;
+        float dl[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t x = xc + 8 * kk + i;
+            const bool okx = x < ke;
+            dl[i] = okx ? (float)(delta[x] * inv_d) : 0.0f;
+            const bool ok = okx && e < P.m;
+            const float vr = ok ? MM16<S>::to_f(gr[(int64_t)e * N + x]) : 0.0f;
+            const float vi = ok ? MM16<S>::to_f(gi[(int64_t)e * N + x]) : 0.0f;
+            a_r[i] = MM16<S>::from_f(vr);
+            a_i[i] = MM16<S>::from_f(vi);
+            a_n[i] = MM16<S>::from_f(-vi);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = tr * 64 + 16 * c + row;
+            V b_r, b_i;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t x = xc + 8 * kk + i;
+                const bool ok = (x < ke) && (r < P.m);
+                const float vr = ok ? MM16<S>::to_f(gr[(int64_t)r * N + x]) : 0.0f;
+                const float vi = ok ? MM16<S>::to_f(gi[(int64_t)r * N + x]) : 0.0f;
+                b_r[i] = MM16<S>::from_f(vr * dl[i]);
+                b_i[i] = MM16<S>::from_f(vi * dl[i]);
+            }
+            re[c] = MM16<S>::mma(a_r, b_r, re[c]);
+            re[c] = MM16<S>::mma(a_n, b_i, re[c]);
+            im[c] = MM16<S>::mma(a_r, b_i, im[c]);
+            im[c] = MM16<S>::mma(a_i, b_r, im[c]);
+        }
+    }
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ee = te * 64 + 16 * wave + 4 * kk + i;
+            const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+            pp[o] = re[c][i];
+            pp[o + 1] = im[c][i];
+        }
+    }
+}
+
+// d[k][e][r] = c_k * sum_split part (fixed order), read from the upper triangle.
+template <typename T>
+__global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const float *__restrict__ gscale,
+                                 const double *__restrict__ dmax, double *__restrict__ d) {
+    const int64_t mm = (int64_t)P.m * P.m;
+    const int64_t tot = mm * P.nf;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int k = (int)(idx / mm);
+    const int64_t rem = idx - (int64_t)k * mm;
+    int e = (int)(rem / P.m), r = (int)(rem - (int64_t)e * P.m);
+    // d is symmetric: both (e, r) and (r, e) take the upper-triangle element
+    if (e > r) {
+        const int t = e;
+        e = r;
+        r = t;
+    }
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < P.nsplit; ++s) {
+        const T *pp = part + ((int64_t)s * P.nf + k) * P.mp * P.mp * 2 + ((int64_t)e * P.mp + r) * 2;
+        sr += (double)pp[0];
+        si += (double)pp[1];
+    }
+    double c = P.cg[k];
+    if (gscale) {
+        const double g = (double)gscale[k];
+        c *= g * g;
+    }
+    if (dmax) c *= dmax[0];
+    d[2 * idx] = sr * c;
+    d[2 * idx + 1] = si * c;
+}
+
+__global__ void k_absmax_f64(const double *__restrict__ v, int64_t n, double *__restrict__ out) {
+    __shared__ double sh[1024];
+    double best = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) best = fmax(best, fabs(v[i]));
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+// rows/columns of the adjoint operands are padded to a multiple of 32
+static int pad_m(int m) { return (m + 31) / 32 * 32; }
+
+AdjParams adj_params(const rb_geometry *g, const double *freqs, int nf) {
+    AdjParams P;
+    P.m = g->m;
+    P.mp = pad_m(g->m);
+    P.nb = P.mp / 16;
+    P.N = (int64_t)g->nx * g->ny;
+    P.nf = nf;
+    const double dA = g->h * g->h;
+    for (int k = 0; k < nf; ++k) {
+        const double om = 2.0 * M_PI * freqs[k];
+        const double c = om * om * dA;
+        P.cg[k] = c;
+        P.ch[k] = c * c;
+    }
+    return P;
+}
+
+struct AdjWs {
+    void *Ar, *Ai, *Wt;
+    uint8_t *flags;
+    float *ascale;
+};
+
+static AdjWs carve_adj(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
+    const int mp = pad_m(g->m);
+    const size_t per = (size_t)nf * mp * mp;
+    const size_t es = dt == RB_F64 ? 8 : (dt == RB_F32 ? 4 : 2);
+    AdjWs w;
+    w.Ar = c.take<char>(per * es);
+    w.Ai = c.take<char>(per * es);
+    w.Wt = c.take<char>(per * es);
+    w.flags = c.take<uint8_t>((size_t)nf * (mp / 16) * (mp / 16));
+    w.ascale = c.take<float>(RB_MAX_NF);
+    return w;
+}
+
+size_t adjoint_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
+    Carver c(nullptr, 0);
+    carve_adj(c, g, nf, dt);
+    return c.used + 256;
+}
+
+rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
+                       double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (ws_bytes < adjoint_workspace_bytes(g, nf, dt)) {
+        set_error("adjoint workspace too small: need %zu bytes", adjoint_workspace_bytes(g, nf, dt));
+        return RB_ENOMEM;
+    }
+    Carver c(ws, ws_bytes);
+    AdjWs w = carve_adj(c, g, nf, dt);
+    AdjParams P = adj_params(g, freqs, nf);
+    const int64_t tot = (int64_t)nf * P.mp * P.mp;
+    const unsigned bp = (unsigned)std::min<int64_t>(blocks_for(tot, 256), 8192);
+    const bool scaled = (dt == RB_BF16 || dt == RB_F16);
+    if (scaled) {
+        k_adj_absmax<<<nf, 256, 0, st>>>(g->m, d_res, w_data, w.ascale);
+        RB_LAUNCHED();
+    }
+    switch (dt) {
+        case RB_F64:
+            k_adj_prep<double, false><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr, (double *)w.Ar,
+                                                          (double *)w.Ai, (double *)w.Wt);
+            break;
+        case RB_F32:
+            k_adj_prep<float, false><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr, (float *)w.Ar,
+                                                         (float *)w.Ai, (float *)w.Wt);
+            break;
+        case RB_BF16:
+            k_adj_prep<__hip_bfloat16, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, w.ascale,
+                                                                 (__hip_bfloat16 *)w.Ar, (__hip_bfloat16 *)w.Ai,
+                                                                 (__hip_bfloat16 *)w.Wt);
+            break;
+        case RB_F16:
+            k_adj_prep<__half, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, w.ascale, (__half *)w.Ar,
+                                                         (__half *)w.Ai, (__half *)w.Wt);
+            break;
+    }
+    RB_LAUNCHED();
+    const int64_t nfl = (int64_t)nf * P.nb * P.nb;
+    k_block_flags<<<blocks_for(nfl, 256), 256, 0, st>>>(g->m, P.nb, nf, w_data, w.flags);
+    RB_LAUNCHED();
+    switch (dt) {
+        case RB_F64: {
+            const unsigned nb = blocks_for(P.N, 64 * 2);
+            k_adjoint<double, 2, 2><<<nb, 256, 0, st>>>(P, (const double *)G_re, (const double *)G_im,
+                                                        (const double *)w.Ar, (const double *)w.Ai,
+                                                        (const double *)w.Wt, w.flags, grad, hdiag);
+            break;
+        }
+        case RB_F32: {
+            const unsigned nb = blocks_for(P.N, 64 * 2);
+            k_adjoint<float, 4, 2><<<nb, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
+                                                       (const float *)w.Ar, (const float *)w.Ai,
+                                                       (const float *)w.Wt, w.flags, grad, hdiag);
+            break;
+        }
+        case RB_BF16: {
+            const unsigned nb = blocks_for(P.N, 64 * 2);
+            k_adjoint16<__hip_bfloat16, 4, 2><<<nb, 256, 0, st>>>(
+                P, (const __hip_bfloat16 *)G_re, (const __hip_bfloat16 *)G_im, (const __hip_bfloat16 *)w.Ar,
+                (const __hip_bfloat16 *)w.Ai, (const __hip_bfloat16 *)w.Wt, w.flags, gscale, w.ascale, grad, hdiag);
+            break;
+        }
+        case RB_F16: {
+            const unsigned nb = blocks_for(P.N, 64 * 2);
+            k_adjoint16<__half, 4, 2><<<nb, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im,
+                                                          (const __half *)w.Ar, (const __half *)w.Ai,
+                                                          (const __half *)w.Wt, w.flags, gscale, w.ascale, grad,
+                                                          hdiag);
+            break;
+        }
+    }
+    RB_LAUNCHED();
+    return RB_OK;
+}
+
+FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, rb_dtype dt) {
+    FwdParams P;
+    P.m = g->m;
+    P.mp = (g->m + 63) / 64 * 64;
+    P.N = (int64_t)g->nx * g->ny;
+    P.nf = nf;
+    P.ntl = P.mp / 64;
+    const int ntri = P.ntl * (P.ntl + 1) / 2;
+    const int want = 2048;
+    int nsplit = std::max(1, (want + ntri * nf - 1) / (ntri * nf));
+    const int kq = (dt == RB_BF16 || dt == RB_F16) ? 32 : 16;
+    int64_t kchunk = (P.N + nsplit - 1) / nsplit;
+    kchunk = (kchunk + kq - 1) / kq * kq;
+    if (kchunk < kq) kchunk = kq;
+    nsplit = (int)((P.N + kchunk - 1) / kchunk);
+    P.nsplit = nsplit;
+    P.kchunk = kchunk;
+    P.ntri = ntri;
+    const double dA = g->h * g->h;
+    for (int k = 0; k < nf; ++k) {
+        const double om = 2.0 * M_PI * (freqs ? freqs[k] : 1.0);
+        P.cg[k] = om * om * dA;
+    }
+    return P;
+}
+
+size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
+    FwdParams P = fwd_params(g, nullptr, nf, dt);
+    const size_t es = dt == RB_F64 ? 8 : 4;
+    return (size_t)P.nsplit * nf * P.mp * P.mp * 2 * es + 2 * 256 + 256;
+}
+
+rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (ws_bytes < forward_workspace_bytes(g, nf, dt)) {
+        set_error("forward workspace too small: need %zu bytes", forward_workspace_bytes(g, nf, dt));
+        return RB_ENOMEM;
+    }
+    FwdParams P = fwd_params(g, freqs, nf, dt);
+    Carver c(ws, ws_bytes);
+    double *dmax = c.take<double>(1);
+    const size_t es = dt == RB_F64 ? 8 : 4;
+    void *part = c.take<char>((size_t)P.nsplit * nf * P.mp * P.mp * 2 * es);
+    dim3 grid(P.ntri, P.nsplit, nf);
+    const int64_t tot = (int64_t)nf * P.m * P.m;
+    switch (dt) {
+        case RB_F64:
+            k_forward<double><<<grid, 256, 0, st>>>(P, (const double *)G_re, (const double *)G_im, delta,
+                                                    (double *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<double><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const double *)part, nullptr,
+                                                                           nullptr, d_out);
+            break;
+        case RB_F32:
+            k_forward<float><<<grid, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, delta,
+                                                   (float *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, nullptr,
+                                                                          d_out);
+            break;
+        case RB_BF16:
+        case RB_F16:
+            k_absmax_f64<<<1, 1024, 0, st>>>(delta, P.N, dmax);
+            RB_LAUNCHED();
+            if (dt == RB_BF16)
+                k_forward16<__hip_bfloat16><<<grid, 256, 0, st>>>(P, (const __hip_bfloat16 *)G_re,
+                                                                  (const __hip_bfloat16 *)G_im, delta, dmax,
+                                                                  (float *)part);
+            else
+                k_forward16<__half><<<grid, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im, delta,
+                                                          dmax, (float *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, dmax,
+                                                                          d_out);
+            break;
+    }
+    RB_LAUNCHED();
+    return RB_OK;
+}
+
+static rb_status check_contraction(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                                   rb_dtype dt, const double *freqs, int32_t nf) {
+    RB_TRY(check_geometry(g));
+    RB_TRY(check_freqs(freqs, nf));
+    RB_CHECK_ARG(dt >= RB_F64 && dt <= RB_F16, "unknown dtype %d", (int)dt);
+    RB_CHECK_ARG(G_re && G_im, "G_re/G_im are NULL");
+    RB_CHECK_ARG(!(dt == RB_BF16 || dt == RB_F16) || scale, "scale is required for 16-bit storage");
+    return RB_OK;
+}
+
+}  // namespace rb
+
+extern "C" {
+
+size_t rb_forward_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype) {
+    if (rb::check_geometry(g) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
+    return rb::forward_workspace_bytes(g, nf, dtype);
+}
+
+rb_status rb_born_forward(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                          rb_dtype dtype, const double *freqs_hz, int32_t nf, const double *delta, double *d_out,
+                          void *ws, size_t ws_bytes, void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_contraction(g, G_re, G_im, scale, dtype, freqs_hz, nf));
+    RB_CHECK_ARG(delta && d_out, "delta/d_out are NULL");
+    RB_CHECK_ARG(ws, "workspace is NULL");
+    return rb::forward_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, delta, d_out, ws, ws_bytes,
+                            rb::as_stream(stream));
+}
+
+size_t rb_adjoint_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype) {
+    if (rb::check_geometry(g) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
+    return rb::adjoint_workspace_bytes(g, nf, dtype);
+}
+
+rb_status rb_born_adjoint_weighted(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                                   rb_dtype dtype, const double *freqs_hz, int32_t nf, const double *d_res,
+                                   const double *w_data, double *grad, double *hdiag, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_contraction(g, G_re, G_im, scale, dtype, freqs_hz, nf));
+    RB_CHECK_ARG(d_res && w_data && grad, "d_res/w_data/grad are NULL");
+    RB_CHECK_ARG(ws, "workspace is NULL");
+    return rb::adjoint_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, d_res, w_data, grad, hdiag, ws, ws_bytes,
+                            rb::as_stream(stream));
+}
+
+}  // extern "C"

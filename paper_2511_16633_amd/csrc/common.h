@@ -1,0 +1,120 @@
+// Internal helpers shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/rayborn.h"
+
+namespace rb {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define RB_CHECK_ARG(cond, ...)            \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::rb::set_error(__VA_ARGS__);  \
+            return RB_EINVAL;              \
+        }                                  \
+    } while (0)
+
+#define RB_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::rb::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                  \
+            return RB_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+#define RB_LAUNCHED()                                                              \
+    do {                                                                           \
+        hipError_t e_ = hipGetLastError();                                         \
+        if (e_ != hipSuccess) {                                                    \
+            ::rb::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                   \
+            return RB_EHIP;                                                        \
+        }                                                                          \
+    } while (0)
+
+#define RB_TRY(expr)                 \
+    do {                             \
+        rb_status s_ = (expr);       \
+        if (s_ != RB_OK) return s_;  \
+    } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Carves 256-byte aligned sub-buffers out of a caller workspace.  With a
+// null base it only measures.
+struct Carver {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    Carver(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    template <typename T>
+    T *take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+    bool fits() const { return used <= cap; }
+};
+
+inline size_t dtype_size(rb_dtype d) {
+    switch (d) {
+        case RB_F64: return 8;
+        case RB_F32: return 4;
+        case RB_BF16: return 2;
+        case RB_F16: return 2;
+    }
+    return 0;
+}
+
+rb_status check_geometry(const rb_geometry *g);
+rb_status check_trace(const rb_geometry *g, const rb_trace_opts *t);
+rb_status check_freqs(const double *f, int32_t nf);
+int64_t trace_nmax(const rb_trace_opts *t);
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned blocks_for(int64_t n, int threads) {
+    return static_cast<unsigned>((n + threads - 1) / threads);
+}
+
+// Fill kernels are used instead of hipMemsetAsync so that a caller may
+// capture the library's work into a HIP graph.
+rb_status fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+rb_status fill_f64(double *p, double v, int64_t n, hipStream_t st);
+rb_status fill_f32(float *p, float v, int64_t n, hipStream_t st);
+
+// Deterministic reductions (fixed-order two-level trees).
+// out[0] = max over n of in[i] where mask[i] (mask may be null).
+rb_status reduce_max_f64(const double *in, const uint8_t *mask, int64_t n, double *partials,
+                         double *out, hipStream_t st);
+rb_status reduce_max_f32(const float *in, int64_t n, float *partials, float *out,
+                         hipStream_t st);
+
+constexpr int kReduceBlocks = 1024;
+
+// Grid/trace parameters passed by value to kernels.
+struct GridParams {
+    int nx, ny;
+    double h, x0, y0;
+    double s_bg;
+};
+
+// Field value at integer pixel (i, j) with a fixed value outside the grid.
+struct SA {
+    double s, a;
+};
+
+}  // namespace rb

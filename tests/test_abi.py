@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rayborn.h")
+
+rb = pytest.importorskip("paper_2511_16633_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 13
+    L = rb.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert rb.version().startswith("rayborn")
+
+
+def test_status_strings():
+    L = rb.lib()
+    assert L.rb_status_string(0) == b"ok"
+    assert L.rb_status_string(-1) == b"invalid argument"
+    assert L.rb_status_string(-5).startswith(b"non-positive")
+
+
+def _geom(**kw):
+    g = W.centred_grid(16, 1e-3, 8, 6e-3, 1500.0)
+    import dataclasses
+    return dataclasses.replace(g, **kw)
+
+
+def test_workspace_sizes_are_positive_and_monotone():
+    g = _geom()
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5, j_min=0.0)
+    a = rb.trace_workspace_bytes(g, t, 1)
+    b = rb.trace_workspace_bytes(g, t, 8)
+    assert 0 < a < b
+    assert rb.invert_workspace_bytes(g, t, 2, "f32") > b
+    assert rb.adjoint_workspace_bytes(g, 2, "bf16") > 0
+    assert rb.forward_workspace_bytes(g, 2, "f64") > 0
+    bad = W.TraceOpts(n_rays=2, dtau=1e-7, tau_max=2e-5)
+    assert rb.trace_workspace_bytes(g, bad, 1) == 0
+    assert rb.invert_workspace_bytes(_geom(m=2), t, 2, "f32") == 0
+
+
+def _call_trace(g, t, ws_bytes=1 << 20):
+    L = rb.lib()
+    from paper_2511_16633_amd._binding import RbTables, geometry_struct, trace_opts_struct
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    tabs = RbTables(*(0x1000 for _ in range(6)))
+    return L.rb_trace_rays(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)), fake, None,
+                           ctypes.byref(tabs), fake, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw", [{"nx": 0}, {"h": -1.0}, {"m": 3}, {"ring_radius": 0.0}, {"c_background": 0.0}])
+def test_invalid_geometry_is_rejected_on_host(kw):
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5)
+    assert _call_trace(_geom(**kw), t) == -1
+    assert len(rb.lib().rb_last_error()) > 0
+
+
+@pytest.mark.parametrize("t", [W.TraceOpts(n_rays=2, dtau=1e-7, tau_max=2e-5),
+                               W.TraceOpts(n_rays=30, dtau=0.0, tau_max=2e-5),
+                               W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=1e-8)])
+def test_invalid_trace_options_are_rejected_on_host(t):
+    assert _call_trace(_geom(), t) == -1
+
+
+def test_too_small_workspace_is_enomem():
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5)
+    assert _call_trace(_geom(), t, ws_bytes=64) == -2
+    assert b"too small" in rb.lib().rb_last_error()
+
+
+def test_binding_raises_with_message():
+    with pytest.raises(rb.RayBornError) as ei:
+        rb._binding._check(-1)
+    assert "invalid argument" in str(ei.value)
+    with pytest.raises(rb.NumericError):
+        rb._binding._check(-5)
