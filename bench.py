@@ -1,0 +1,199 @@
+"""Throughput of the ray-Born single-step inversion on one MI355X.
+
+One step = the whole hot path over the 256-element / 480x480 workload: for
+each of the 8 frequency sets (3 frequencies each, 0.3-1.25 MHz, low to
+high) trace rays in the current model, build the ray tables and Green's
+functions, form residual and data weights, run the weighted backprojection
+with the Hessian diagonal, the forward operator for the step length, and
+update the model.  Inputs are synthetic and resident in HBM before timing.
+
+Metric: Born backprojection throughput in Gpixel.pair.freq/s =
+N * P * F / t_step / 1e9 (N pixels, P selected emitter-receiver pairs,
+F frequencies).  The roofline entry is for the dominant kernel, the fused
+complex MFMA backprojection, at 10 flop per (pixel, pair, frequency).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0}   # dense MFMA TFLOP/s
+METRIC = "Born backprojection Gpixel·pair·freq/s + recon latency p50/p99 vs plain"
+
+
+def selected_pairs(m: int, recv_fraction: float) -> int:
+    dmin = int(math.ceil((1.0 - recv_fraction) * 0.5 * m - 1e-9))
+    return m * sum(1 for r in range(m) if min(r, m - r) >= dmin)
+
+
+def selection_weights(m: int, recv_fraction: float, nf: int) -> np.ndarray:
+    """Receiver-selection weights [nf][m][m] (timing input for the adjoint)."""
+    dmin = int(math.ceil((1.0 - recv_fraction) * 0.5 * m - 1e-9))
+    e = np.arange(m)[:, None]
+    r = np.arange(m)[None, :]
+    d = np.minimum(np.abs(e - r), m - np.abs(e - r))
+    return np.repeat((d >= dmin).astype(np.float64)[None], nf, axis=0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2511_16633_amd as rb
+    import workload as W
+
+    dev = "cuda:0"
+    t0 = time.time()
+    prob = W.breast_ring256(dtype=args.dtype)
+    g = prob.geom
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    print(f"[bench] inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    c_start = torch.as_tensor(prob.c_start.reshape(-1), device=dev)
+    alpha = torch.as_tensor(prob.alpha0.reshape(-1), device=dev)
+    pms = [torch.as_tensor(np.stack([p.real, p.imag], -1), device=dev) for p in prob.p_meas]
+    nf_max = max(len(f) for f in prob.freq_sets)
+    ws = torch.empty(rb.invert_workspace_bytes(g, topts, nf_max, args.dtype), dtype=torch.uint8, device=dev)
+    c = torch.empty_like(c_start)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        c.copy_(c_start)
+        hist = []
+        for fs, pm in zip(prob.freq_sets, pms):
+            hist.append(rb.invert_frequency_set(g, topts, prob.inv, args.dtype, c, alpha, fs, pm, c, ws=ws,
+                                                stream=stream))
+        return hist
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        hist = step()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms_per_step = (t2 - t1) * 1e3 / args.steps
+    N, P = g.n_pixels, selected_pairs(g.m, prob.inv.recv_fraction)
+    F = sum(len(f) for f in prob.freq_sets)
+    units = N * P * F
+    value = units / (ms_per_step * 1e-3) / 1e9
+    print(f"[bench] {ms_per_step:.1f} ms/step, update norms {['%.2f' % h for h in hist]}", file=sys.stderr,
+          flush=True)
+
+    # ---- dominant kernel: the weighted backprojection, timed per launch with
+    # events on the stream the library launches on.
+    fs = prob.freq_sets[0]
+    nf = len(fs)
+    tabs = rb.alloc_tables(g, dev)
+    s = (1.0 / c_start).contiguous()
+    rb.trace_rays(g, topts, s, alpha, tabs, stream=stream)
+    td = rb._binding.TORCH_DTYPES[rb.DTYPES[args.dtype]]
+    Gr = torch.empty((nf, g.m, N), dtype=td, device=dev)
+    Gi = torch.empty_like(Gr)
+    sc = torch.empty(nf, dtype=torch.float32, device=dev)
+    rb.build_green(g, tabs, fs, prob.inv.y_pow, args.dtype, Gr, Gi, sc, stream=stream)
+    Wd = torch.as_tensor(selection_weights(g.m, prob.inv.recv_fraction, nf), device=dev)
+    grad = torch.zeros(N, dtype=torch.float64, device=dev)
+    hd = torch.zeros(N, dtype=torch.float64, device=dev)
+    aws = torch.empty(rb.adjoint_workspace_bytes(g, nf, args.dtype), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, hd, ws=aws, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.adjoint_reps):
+        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, hd, ws=aws, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    adj_ms = ev0.elapsed_time(ev1) / args.adjoint_reps
+    flops = 10.0 * N * P * nf
+    achieved = flops / (adj_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[args.dtype], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK[args.dtype], 4), "traffic": None,
+                "kernel": "k_adjoint (fused complex backprojection + Hessian diagonal)",
+                "launch_ms": round(adj_ms, 4), "algorithmic_flop_per_launch": flops}
+
+    # ---- stage times for one set (events, same stream)
+    def timed(fn, reps=3):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    tws = torch.empty(rb.trace_workspace_bytes(g, topts), dtype=torch.uint8, device=dev)
+    fws = torch.empty(rb.forward_workspace_bytes(g, nf, args.dtype), dtype=torch.uint8, device=dev)
+    dout = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=dev)
+    stages = {
+        "trace_rays": timed(lambda: rb.trace_rays(g, topts, s, alpha, tabs, ws=tws, stream=stream)),
+        "build_green": timed(lambda: rb.build_green(g, tabs, fs, prob.inv.y_pow, args.dtype, Gr, Gi, sc,
+                                                    stream=stream)),
+        "born_adjoint_weighted": adj_ms,
+        "born_forward": timed(lambda: rb.born_forward(g, Gr, Gi, sc, args.dtype, fs, grad, dout, ws=fws,
+                                                      stream=stream)),
+    }
+    stages = {k: round(v, 3) for k, v in stages.items()}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpixel·pair·freq/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+           "data": "synthetic (seeded breast phantom, straight-ray measured-data stand-in)",
+           "config": {"workload": "ring256_grid480: 256-element ring R=110 mm, 480x480 grid at 0.5 mm, "
+                                  "8 sets x 3 frequencies 0.3-1.25 MHz low to high, 720 rays/emitter, "
+                                  "FP64 rays/phase, " + args.dtype + " contractions",
+                      "pixels": N, "selected_pairs": P, "frequencies": F, "pixel_pair_freq_per_step": units},
+           "roofline": roofline, "stages_ms_per_set": stages}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, topts, P)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(prob, topts, P):
+    """The FP64 oracle, as it stands, on one frequency set of the same workload."""
+    from oracle import invert
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        blas = 1
+    omp = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fs = prob.freq_sets[0]
+    t = time.perf_counter()
+    invert.invert_frequency_set(prob.geom, topts, prob.inv, prob.c_start, prob.alpha0, fs, prob.p_meas[0])
+    dt = time.perf_counter() - t
+    units = prob.geom.n_pixels * P * len(fs)
+    return {"value": round(units / dt / 1e9, 4), "unit": "Gpixel·pair·freq/s",
+            "cores": max(blas, omp), "kind": "oracle",
+            "sample": f"one frequency set (3 of 24 frequencies) of the same workload, full grid and ring; "
+                      f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()
