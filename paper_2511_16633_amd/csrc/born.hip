@@ -366,7 +366,9 @@ __global__ void k_adj_absmax(int m, const double *__restrict__ d, const double *
     if (threadIdx.x == 0) ascale[k] = sh[0] > 0.0 ? (float)sh[0] : 1.0f;
 }
 
-template <typename T, bool SCALED>
+// PERMUTE: within every 32-column chunk, receiver 4 s + kk is stored at
+// column 8 kk + s (the operand order of k_adjoint_f32).
+template <typename T, bool SCALED, bool PERMUTE = false>
 __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, const double *__restrict__ w,
                            const float *__restrict__ ascale, T *__restrict__ Ar, T *__restrict__ Ai,
                            T *__restrict__ Wt) {
@@ -389,9 +391,14 @@ __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, 
                 im *= inv;
             }
         }
-        Ar[idx] = cvt<T>(re);
-        Ai[idx] = cvt<T>(im);
-        Wt[idx] = cvt<T>(wv);
+        int64_t o = idx;
+        if (PERMUTE) {
+            const int kr = r & 31;
+            o = idx - kr + 8 * (kr & 3) + (kr >> 2);
+        }
+        Ar[o] = cvt<T>(re);
+        Ai[o] = cvt<T>(im);
+        Wt[o] = cvt<T>(wv);
     }
 }
 
@@ -606,6 +613,368 @@ __global__ void k_absmax_f64(const double *__restrict__ v, int64_t n, double *__
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// ------------------------------------------------------------------ FP32, LDS-staged
+// Backprojection.  The workgroup owns 64 pixels; its four waves are 2
+// (emitter halves) x 2 (pixel halves), each computing 32 e x 32 px of Y, Z
+// per chunk of 64 emitters.  Receivers are consumed 32 at a time: the G tile
+// [32 r][64 px] is staged in LDS, double buffered, with a row stride of 80
+// floats so the four lane groups (rows 4 s + kk) fall on disjoint banks.  A
+// is stored k-permuted, so a lane's eight A values of a chunk are two float4
+// loads (served from L2: A is shared by every workgroup).
+constexpr int kAdjNT = 64, kAdjKC = 32, kAdjLD = 80;
+
+__device__ __forceinline__ void adj_stage_load(const float *__restrict__ gr, const float *__restrict__ gi, int m,
+                                               int64_t N, int rc, int64_t x0, bool vec, f4 (&v)[4]) {
+    const int t = threadIdx.x;
+    const int rr = t >> 3, c4 = (t & 7) * 4;
+    const int r = rc + rr;
+    if (vec) {
+        if (r < m) {
+            const float *pr = gr + (int64_t)r * N + x0 + c4;
+            const float *pi = gi + (int64_t)r * N + x0 + c4;
+            v[0] = *reinterpret_cast<const f4 *>(pr);
+            v[1] = *reinterpret_cast<const f4 *>(pr + 32);
+            v[2] = *reinterpret_cast<const f4 *>(pi);
+            v[3] = *reinterpret_cast<const f4 *>(pi + 32);
+        } else {
+            v[0] = v[1] = v[2] = v[3] = f4{0, 0, 0, 0};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t xa = x0 + c4 + q, xb = xa + 32;
+            const bool oka = r < m && xa < N, okb = r < m && xb < N;
+            v[0][q] = oka ? gr[(int64_t)r * N + xa] : 0.0f;
+            v[1][q] = okb ? gr[(int64_t)r * N + xb] : 0.0f;
+            v[2][q] = oka ? gi[(int64_t)r * N + xa] : 0.0f;
+            v[3][q] = okb ? gi[(int64_t)r * N + xb] : 0.0f;
+        }
+    }
+}
+
+__device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], const f4 (&v)[4]) {
+    const int t = threadIdx.x;
+    const int rr = t >> 3, c4 = (t & 7) * 4;
+    *reinterpret_cast<f4 *>(&sB[0][rr][c4]) = v[0];
+    *reinterpret_cast<f4 *>(&sB[0][rr][c4 + 32]) = v[1];
+    *reinterpret_cast<f4 *>(&sB[1][rr][c4]) = v[2];
+    *reinterpret_cast<f4 *>(&sB[1][rr][c4 + 32]) = v[3];
+}
+
+// NB row blocks starting at b0: for each step, first the Ar.Gr, Ar.Gi and
+// W.|G|^2 products of every (row block, column block), then the Ai terms.
+template <int NB>
+__device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&vi)[2][2], const f4 (&vw)[2][2],
+                                              const float (&br)[8][2], const float (&bi)[8][2], f4 (&yr)[2][2],
+                                              f4 (&yn)[2][2], f4 (&z)[2][2], int b0) {
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+        float b2[8][2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) b2[s8][cb] = br[s8][cb] * br[s8][cb] + bi[s8][cb] * bi[s8][cb];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = b0 + q;
+            const float a_r = va[b][s8 >> 2][s8 & 3], a_w = vw[b][s8 >> 2][s8 & 3];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                yr[b][cb] = MM<float>::mma(a_r, br[s8][cb], yr[b][cb]);
+                yn[b][cb] = MM<float>::mma(a_r, bi[s8][cb], yn[b][cb]);
+                z[b][cb] = MM<float>::mma(a_w, b2[s8][cb], z[b][cb]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = b0 + q;
+            const float a_i = vi[b][s8 >> 2][s8 & 3];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                yr[b][cb] = MM<float>::mma(a_i, bi[s8][cb], yr[b][cb]);
+                yn[b][cb] = MM<float>::mma(-a_i, br[s8][cb], yn[b][cb]);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
+                                                        const float *__restrict__ Gi, const float *__restrict__ Ar,
+                                                        const float *__restrict__ Ai, const float *__restrict__ Wt,
+                                                        const uint8_t *__restrict__ flags, double *__restrict__ grad,
+                                                        double *__restrict__ hd) {
+    __shared__ float sB[2][2][kAdjKC][kAdjLD];
+    __shared__ double sred[2][2][kAdjNT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wp = wave & 1;
+    const int64_t N = P.N;
+    const int64_t x0 = (int64_t)blockIdx.x * kAdjNT;
+    const bool vec = ((N & 3) == 0) && (x0 + kAdjNT <= N);
+    const int nch = P.mp / kAdjKC;
+    double gacc[2] = {0.0, 0.0}, hacc[2] = {0.0, 0.0};
+
+    for (int k = 0; k < P.nf; ++k) {
+        const float *gr = Gr + (int64_t)k * P.m * N;
+        const float *gi = Gi + (int64_t)k * P.m * N;
+        const float *ar = Ar + (int64_t)k * P.mp * P.mp;
+        const float *ai = Ai + (int64_t)k * P.mp * P.mp;
+        const float *wt = Wt + (int64_t)k * P.mp * P.mp;
+        const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
+        float gp[2] = {0.0f, 0.0f}, hp[2] = {0.0f, 0.0f};
+        for (int ec = 0; ec < P.mp; ec += 64) {
+            f4 yr[2][2], yn[2][2], z[2][2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
+            f4 stg[4];
+            adj_stage_load(gr, gi, P.m, N, 0, x0, vec, stg);
+            adj_stage_store(sB[0], stg);
+            __syncthreads();
+            for (int c = 0; c < nch; ++c) {
+                const int rc = c * kAdjKC, buf = c & 1;
+                if (c + 1 < nch) adj_stage_load(gr, gi, P.m, N, rc + kAdjKC, x0, vec, stg);
+                bool on[2];
+                f4 va[2][2], vi[2][2], vw[2][2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int eb = (ec >> 4) + 2 * we + b;
+                    on[b] = (eb < P.nb) && (fl[eb * P.nb + (rc >> 4)] | fl[eb * P.nb + (rc >> 4) + 1]);
+                    if (on[b]) {
+                        const int64_t off = (int64_t)(ec + 32 * we + 16 * b + row) * P.mp + rc + 8 * kk;
+                        va[b][0] = *reinterpret_cast<const f4 *>(ar + off);
+                        va[b][1] = *reinterpret_cast<const f4 *>(ar + off + 4);
+                        vi[b][0] = *reinterpret_cast<const f4 *>(ai + off);
+                        vi[b][1] = *reinterpret_cast<const f4 *>(ai + off + 4);
+                        vw[b][0] = *reinterpret_cast<const f4 *>(wt + off);
+                        vw[b][1] = *reinterpret_cast<const f4 *>(wt + off + 4);
+                    }
+                }
+                if (on[0] || on[1]) {
+                    // all B fragments of the chunk first (one LDS wait), then
+                    // the MFMAs ordered so no accumulator is hit twice in a row
+                    float br[8][2], bi[8][2];
+#pragma unroll
+                    for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            const int xc = 32 * wp + 16 * cb + row;
+                            br[s8][cb] = sB[buf][0][4 * s8 + kk][xc];
+                            bi[s8][cb] = sB[buf][1][4 * s8 + kk][xc];
+                        }
+                    if (on[0] && on[1]) {
+                        adj_mma_steps<2>(va, vi, vw, br, bi, yr, yn, z, 0);
+                    } else if (on[0]) {
+                        adj_mma_steps<1>(va, vi, vw, br, bi, yr, yn, z, 0);
+                    } else {
+                        adj_mma_steps<1>(va, vi, vw, br, bi, yr, yn, z, 1);
+                    }
+                }
+                if (c + 1 < nch) adj_stage_store(sB[buf ^ 1], stg);
+                __syncthreads();
+            }
+            // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = ec + 32 * we + 16 * b + MM<float>::out_row(kk, i);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        const int64_t x = x0 + 32 * wp + 16 * cb + row;
+                        const bool ok = (e < P.m) && (x < N);
+                        const float ge_r = ok ? gr[(int64_t)e * N + x] : 0.0f;
+                        const float ge_i = ok ? gi[(int64_t)e * N + x] : 0.0f;
+                        gp[cb] += ge_r * yr[b][cb][i] - ge_i * yn[b][cb][i];
+                        hp[cb] += (ge_r * ge_r + ge_i * ge_i) * z[b][cb][i];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            gacc[cb] += (double)gp[cb] * P.cg[k];
+            hacc[cb] += (double)hp[cb] * P.ch[k];
+        }
+    }
+    // lanes of a column (four groups), then the two emitter halves, in a fixed order
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        double g = gacc[cb], h = hacc[cb];
+        g += __shfl_xor(g, 16);
+        h += __shfl_xor(h, 16);
+        g += __shfl_xor(g, 32);
+        h += __shfl_xor(h, 32);
+        if (kk == 0) {
+            sred[we][0][32 * wp + 16 * cb + row] = g;
+            sred[we][1][32 * wp + 16 * cb + row] = h;
+        }
+    }
+    __syncthreads();
+    if (tid < kAdjNT) {
+        const int64_t x = x0 + tid;
+        if (x < N) {
+            grad[x] += sred[0][0][tid] + sred[1][0][tid];
+            if (hd) hd[x] += sred[0][1][tid] + sred[1][1][tid];
+        }
+    }
+}
+
+// Forward.  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
+// over a split of the pixels; waves are 2 x 2, each 32 e x 32 r.  Pixels are
+// consumed 32 at a time: G_e and G_r delta for the tile's rows are staged in
+// LDS as [row][32 px] (stride 36: conflict-free b128 reads), double
+// buffered; a lane reads its eight k values of a row as two b128 reads.
+constexpr int kFwdKC = 32, kFwdLD = 36;
+
+struct FwdStage {
+    f4 ar[2], ai[2], br[2], bi[2];
+};
+
+__device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, const float *__restrict__ gi,
+                                               const double *__restrict__ delta, int m, int64_t N, int e_row,
+                                               int r_row, int64_t xc, int64_t ke, bool vec, FwdStage &v) {
+    const int c8 = (threadIdx.x & 3) * 8;
+    const int64_t xs = xc + c8;
+    if (vec) {
+        double dl[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dl[q] = delta[xs + q];
+        if (e_row < m) {
+            const float *pr = gr + (int64_t)e_row * N + xs;
+            const float *pi = gi + (int64_t)e_row * N + xs;
+            v.ar[0] = *reinterpret_cast<const f4 *>(pr);
+            v.ar[1] = *reinterpret_cast<const f4 *>(pr + 4);
+            v.ai[0] = *reinterpret_cast<const f4 *>(pi);
+            v.ai[1] = *reinterpret_cast<const f4 *>(pi + 4);
+        } else {
+            v.ar[0] = v.ar[1] = v.ai[0] = v.ai[1] = f4{0, 0, 0, 0};
+        }
+        if (r_row < m) {
+            const float *pr = gr + (int64_t)r_row * N + xs;
+            const float *pi = gi + (int64_t)r_row * N + xs;
+            f4 t0 = *reinterpret_cast<const f4 *>(pr), t1 = *reinterpret_cast<const f4 *>(pr + 4);
+            f4 u0 = *reinterpret_cast<const f4 *>(pi), u1 = *reinterpret_cast<const f4 *>(pi + 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v.br[0][q] = t0[q] * (float)dl[q];
+                v.br[1][q] = t1[q] * (float)dl[q + 4];
+                v.bi[0][q] = u0[q] * (float)dl[q];
+                v.bi[1][q] = u1[q] * (float)dl[q + 4];
+            }
+        } else {
+            v.br[0] = v.br[1] = v.bi[0] = v.bi[1] = f4{0, 0, 0, 0};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t x = xs + q;
+            const bool okx = x < ke;
+            const float dl = okx ? (float)delta[x] : 0.0f;
+            const bool oka = okx && e_row < m, okb = okx && r_row < m;
+            v.ar[q >> 2][q & 3] = oka ? gr[(int64_t)e_row * N + x] : 0.0f;
+            v.ai[q >> 2][q & 3] = oka ? gi[(int64_t)e_row * N + x] : 0.0f;
+            v.br[q >> 2][q & 3] = okb ? gr[(int64_t)r_row * N + x] * dl : 0.0f;
+            v.bi[q >> 2][q & 3] = okb ? gi[(int64_t)r_row * N + x] * dl : 0.0f;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float *__restrict__ Gr,
+                                                        const float *__restrict__ Gi,
+                                                        const double *__restrict__ delta, float *__restrict__ part) {
+    __shared__ float sA[2][2][64][kFwdLD];
+    __shared__ float sBm[2][2][64][kFwdLD];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wr = wave & 1;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const float *gr = Gr + (int64_t)k * P.m * N;
+    const float *gi = Gi + (int64_t)k * P.m * N;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const int nch = (int)((ke - ks + kFwdKC - 1) / kFwdKC);
+    const int srow = tid >> 2, c8 = (tid & 3) * 8;
+    const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
+    f4 re[2][2], im[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) re[b][c] = im[b][c] = f4{0, 0, 0, 0};
+    FwdStage stg;
+    auto vec_ok = [&](int64_t xc) { return ((N & 3) == 0) && (xc + kFwdKC <= ke); };
+    auto store = [&](int buf) {
+        *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8]) = stg.ar[0];
+        *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8 + 4]) = stg.ar[1];
+        *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8]) = stg.ai[0];
+        *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8 + 4]) = stg.ai[1];
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8]) = stg.br[0];
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8 + 4]) = stg.br[1];
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8]) = stg.bi[0];
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8 + 4]) = stg.bi[1];
+    };
+    if (nch > 0) {
+        fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, ks, ke, vec_ok(ks), stg);
+        store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        const int64_t xn = ks + (int64_t)(c + 1) * kFwdKC;
+        if (c + 1 < nch) fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, xn, ke, vec_ok(xn), stg);
+        f4 a_r[2][2], a_i[2][2], b_r[2][2], b_i[2][2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ra = 32 * we + 16 * b + row;
+            a_r[b][0] = *reinterpret_cast<const f4 *>(&sA[buf][0][ra][8 * kk]);
+            a_r[b][1] = *reinterpret_cast<const f4 *>(&sA[buf][0][ra][8 * kk + 4]);
+            a_i[b][0] = *reinterpret_cast<const f4 *>(&sA[buf][1][ra][8 * kk]);
+            a_i[b][1] = *reinterpret_cast<const f4 *>(&sA[buf][1][ra][8 * kk + 4]);
+            const int rb = 32 * wr + 16 * b + row;
+            b_r[b][0] = *reinterpret_cast<const f4 *>(&sBm[buf][0][rb][8 * kk]);
+            b_r[b][1] = *reinterpret_cast<const f4 *>(&sBm[buf][0][rb][8 * kk + 4]);
+            b_i[b][0] = *reinterpret_cast<const f4 *>(&sBm[buf][1][rb][8 * kk]);
+            b_i[b][1] = *reinterpret_cast<const f4 *>(&sBm[buf][1][rb][8 * kk + 4]);
+        }
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const float xr = a_r[b][s8 >> 2][s8 & 3], xi = a_i[b][s8 >> 2][s8 & 3];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const float yr_ = b_r[cb][s8 >> 2][s8 & 3], yi_ = b_i[cb][s8 >> 2][s8 & 3];
+                    re[b][cb] = MM<float>::mma(xr, yr_, re[b][cb]);
+                    re[b][cb] = MM<float>::mma(-xi, yi_, re[b][cb]);
+                    im[b][cb] = MM<float>::mma(xr, yi_, im[b][cb]);
+                    im[b][cb] = MM<float>::mma(xi, yr_, im[b][cb]);
+                }
+            }
+        }
+        if (c + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int r = tr * 64 + 32 * wr + 16 * cb + row;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ee = te * 64 + 32 * we + 16 * b + MM<float>::out_row(kk, i);
+                const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+                pp[o] = re[b][cb][i];
+                pp[o + 1] = im[b][cb][i];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -677,8 +1046,8 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
                                                           (double *)w.Ai, (double *)w.Wt);
             break;
         case RB_F32:
-            k_adj_prep<float, false><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr, (float *)w.Ar,
-                                                         (float *)w.Ai, (float *)w.Wt);
+            k_adj_prep<float, false, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr,
+                                                               (float *)w.Ar, (float *)w.Ai, (float *)w.Wt);
             break;
         case RB_BF16:
             k_adj_prep<__hip_bfloat16, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, w.ascale,
@@ -703,10 +1072,9 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
         }
         case RB_F32: {
-            const unsigned nb = blocks_for(P.N, 64 * 2);
-            k_adjoint<float, 4, 2><<<nb, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
-                                                       (const float *)w.Ar, (const float *)w.Ai,
-                                                       (const float *)w.Wt, w.flags, grad, hdiag);
+            k_adjoint_f32<<<blocks_for(P.N, kAdjNT), 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
+                                                                  (const float *)w.Ar, (const float *)w.Ai,
+                                                                  (const float *)w.Wt, w.flags, grad, hdiag);
             break;
         }
         case RB_BF16: {
@@ -784,8 +1152,7 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
                                                                            nullptr, d_out);
             break;
         case RB_F32:
-            k_forward<float><<<grid, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, delta,
-                                                   (float *)part);
+            k_forward_f32<<<grid, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, delta, (float *)part);
             RB_LAUNCHED();
             k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, nullptr,
                                                                           d_out);

@@ -39,7 +39,8 @@ rb_status check_trace(const rb_geometry *g, const rb_trace_opts *t) {
     RB_CHECK_ARG(std::isfinite(t->dtau) && t->dtau > 0.0, "dtau must be positive");
     RB_CHECK_ARG(std::isfinite(t->tau_max) && t->tau_max > t->dtau, "tau_max must exceed dtau");
     int64_t nmax = trace_nmax(t);
-    RB_CHECK_ARG(nmax >= 1 && nmax <= (1 << 20), "tau_max/dtau gives %lld steps (max 2^20)",
+    // steps are a launch-grid dimension (4 per block, at most 65535 blocks)
+    RB_CHECK_ARG(nmax >= 1 && nmax <= 4 * 65535 - 4, "tau_max/dtau gives %lld steps (max 262136)",
                  (long long)nmax);
     RB_CHECK_ARG(std::isfinite(t->j_min), "j_min must be finite");
     return RB_OK;

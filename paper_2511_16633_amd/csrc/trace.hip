@@ -29,6 +29,7 @@ namespace {
 struct TP {
     int nx, ny;
     double h, x0, y0;
+    double inv_h;      // 1 / h
     int m;
     double R, s_bg;
     int nr;            // rays per emitter
@@ -38,6 +39,7 @@ struct TP {
     double j_min;
     double bary_tol;
     double two_sin_full, two_sin_half;
+    double ring2_lo, ring2_hi;  // (R (1 -+ 2e-9))^2: conservative ring test on squares
     int e0, ne;        // emitter batch
 };
 
@@ -49,8 +51,8 @@ __device__ __forceinline__ double2 corner(const double2 *__restrict__ sa, const 
 // Bilinear slowness s with its exact patch gradient, and bilinear alpha0.
 __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &P, double x, double y,
                                       double &s, double &gx, double &gy, double &a) {
-    double u = (x - P.x0) / P.h;
-    double v = (y - P.y0) / P.h;
+    double u = (x - P.x0) * P.inv_h;
+    double v = (y - P.y0) * P.inv_h;
     double fi = floor(u), fj = floor(v);
     if (!(fi >= -1.0 && fi <= (double)P.nx && fj >= -1.0 && fj <= (double)P.ny)) {
         s = P.s_bg; gx = 0.0; gy = 0.0; a = 0.0;
@@ -58,14 +60,25 @@ __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &
     }
     long i = (long)fi, j = (long)fj;
     double fu = u - fi, fv = v - fj;
-    double2 c00 = corner(sa, P, i, j), c10 = corner(sa, P, i + 1, j);
-    double2 c01 = corner(sa, P, i, j + 1), c11 = corner(sa, P, i + 1, j + 1);
+    double2 c00, c10, c01, c11;
+    if (i >= 0 && j >= 0 && i + 1 < P.nx && j + 1 < P.ny) {  // all four corners inside
+        const double2 *q = sa + (size_t)j * (size_t)P.nx + (size_t)i;
+        c00 = q[0];
+        c10 = q[1];
+        c01 = q[P.nx];
+        c11 = q[P.nx + 1];
+    } else {
+        c00 = corner(sa, P, i, j);
+        c10 = corner(sa, P, i + 1, j);
+        c01 = corner(sa, P, i, j + 1);
+        c11 = corner(sa, P, i + 1, j + 1);
+    }
     double dx0 = c10.x - c00.x, dx1 = c11.x - c01.x;
     double s0 = c00.x + fu * dx0;
     double s1 = c01.x + fu * dx1;
     s = s0 + fv * (s1 - s0);
-    gx = (dx0 + fv * (dx1 - dx0)) / P.h;
-    gy = (s1 - s0) / P.h;
+    gx = (dx0 + fv * (dx1 - dx0)) * P.inv_h;
+    gy = (s1 - s0) * P.inv_h;
     double a0 = c00.y + fu * (c10.y - c00.y);
     double a1 = c01.y + fu * (c11.y - c01.y);
     a = a0 + fv * (a1 - a0);
@@ -75,12 +88,13 @@ __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P,
                                     double d[5]) {
     double s, gx, gy, a;
     field(sa, P, st[0], st[1], s, gx, gy, a);
-    double s2 = s * s;
-    d[0] = st[2] / s2;
-    d[1] = st[3] / s2;
-    d[2] = gx / s;
-    d[3] = gy / s;
-    d[4] = a / s;
+    const double is = 1.0 / s;     // one division per stage
+    const double is2 = is * is;
+    d[0] = st[2] * is2;
+    d[1] = st[3] * is2;
+    d[2] = gx * is;
+    d[3] = gy * is;
+    d[4] = a * is;
 }
 
 __global__ void k_pack(const double *__restrict__ s, const double *__restrict__ alpha, int64_t n,
@@ -89,13 +103,24 @@ __global__ void k_pack(const double *__restrict__ s, const double *__restrict__ 
     if (i < n) sa[i] = make_double2(s[i], alpha ? alpha[i] : 0.0);
 }
 
-// One lane per ray: RK4 in travel time, nodes stored [eb][n][j].
-__global__ void __launch_bounds__(128) k_trace(TP P, const double2 *__restrict__ sa, double *__restrict__ X,
-                                               double *__restrict__ Y, double *__restrict__ Bn,
-                                               int *__restrict__ L) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Rays of one emitter are traced a wave at a time in lockstep: lanes 1..62
+// own rays j0 .. j0+61 and lanes 0 and 63 trace the neighbouring rays as a
+// halo, so the ray-tube width J at every node of an owned ray comes from
+// lane shuffles at equal travel time.  The slowness at a node is the first
+// RK4 stage of the step that leaves it, so the amplitude factor
+// a = sqrt(c / (8 pi max(J, j_min))) costs no extra field evaluation.
+// Nodes are stored [eb][n][j] (positions and (a, B) as double2 pairs).
+constexpr int kOwn = 62;
+
+__global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__ sa, double2 *__restrict__ XY,
+                                               double2 *__restrict__ AB, int *__restrict__ L) {
+    const int lane = threadIdx.x & 63;
+    const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int eb = blockIdx.y;
-    if (j >= P.nr || eb >= P.ne) return;
+    if (wv * kOwn >= P.nr || eb >= P.ne) return;  // wave-uniform
+    const int j = wv * kOwn + lane - 1;
+    const bool valid = j >= 0 && j < P.nr;
+    const bool own = valid && lane >= 1 && lane <= kOwn;
     const int e = P.e0 + eb;
     const double theta = 2.0 * M_PI * (double)e / (double)P.m;
     const double xe = P.R * cos(theta), ye = P.R * sin(theta);
@@ -104,75 +129,69 @@ __global__ void __launch_bounds__(128) k_trace(TP P, const double2 *__restrict__
     field(sa, P, xe, ye, se, gx, gy, av);
     const double psi = theta + M_PI + ((double)j + 0.5 - 0.5 * (double)P.nr) * dpsi;
     double st[5] = {xe, ye, se * cos(psi), se * sin(psi), 0.0};
-    const size_t base = (size_t)eb * (size_t)(P.nmax + 1) * P.nr + j;
-    X[base] = st[0];
-    Y[base] = st[1];
-    Bn[base] = 0.0;
+    const size_t base = (size_t)eb * (size_t)(P.nmax + 1) * P.nr + (valid ? j : 0);
     const double dt = P.dtau, hdt = 0.5 * dt, sixth = dt / 6.0;
-    int last = P.nmax;
-    for (int n = 0; n < P.nmax; ++n) {
-        double k1[5], k2[5], k3[5], k4[5], t[5];
-        rhs(sa, P, st, k1);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k1[q];
-        rhs(sa, P, t, k2);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k2[q];
-        rhs(sa, P, t, k3);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) t[q] = st[q] + dt * k3[q];
-        rhs(sa, P, t, k4);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) st[q] = st[q] + sixth * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
-        size_t k = base + (size_t)(n + 1) * P.nr;
-        X[k] = st[0];
-        Y[k] = st[1];
-        Bn[k] = st[4];
-        if (st[0] * st[0] + st[1] * st[1] > P.rdie2) {
-            last = n + 1;
-            break;
-        }
-    }
-    L[(size_t)eb * P.nr + j] = last;
-}
-
-// Ray-tube width from neighbouring rays at equal travel time, and the
-// amplitude factor a = sqrt(c / (8 pi max(J, j_min))).
-__global__ void k_spread(TP P, const double2 *__restrict__ sa, const double *__restrict__ X,
-                         const double *__restrict__ Y, const int *__restrict__ L,
-                         double *__restrict__ AMP) {
-    const int64_t per = (int64_t)(P.nmax + 1) * P.nr;
-    const int64_t tot = per * P.ne;
     const double eight_pi = 8.0 * M_PI;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int eb = (int)(idx / per);
-        const int64_t rem = idx - (int64_t)eb * per;
-        const int n = (int)(rem / P.nr);
-        const int j = (int)(rem - (int64_t)n * P.nr);
-        const int *Le = L + (size_t)eb * P.nr;
-        if (n > Le[j]) continue;
-        const size_t k = (size_t)idx;
-        const bool lo = (j > 0 && n <= Le[j - 1]);
-        const bool hi = (j + 1 < P.nr && n <= Le[j + 1]);
-        double Jv = 0.0, dx, dy;
-        if (lo && hi) {
-            dx = X[k + 1] - X[k - 1];
-            dy = Y[k + 1] - Y[k - 1];
-            Jv = sqrt(dx * dx + dy * dy) / P.two_sin_full;
-        } else if (hi) {
-            dx = X[k + 1] - X[k];
-            dy = Y[k + 1] - Y[k];
-            Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
-        } else if (lo) {
-            dx = X[k] - X[k - 1];
-            dy = Y[k] - Y[k - 1];
-            Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
+    bool alive = valid;   // alive at the current node n
+    bool last = false;    // the current node is the ray's last
+    for (int n = 0; n <= P.nmax; ++n) {
+        if (!__any(alive)) break;
+        // field at the node (first RK4 stage of the next step)
+        double s0 = 1.0, g0x = 0.0, g0y = 0.0, a0 = 0.0;
+        if (alive) field(sa, P, st[0], st[1], s0, g0x, g0y, a0);
+        // neighbours at equal travel time
+        const double xl = __shfl_up(st[0], 1), yl = __shfl_up(st[1], 1);
+        const double xr = __shfl_down(st[0], 1), yr = __shfl_down(st[1], 1);
+        const int al = __shfl_up((int)alive, 1), ar = __shfl_down((int)alive, 1);
+        if (own && alive) {
+            const bool lo = j > 0 && al;
+            const bool hi = j + 1 < P.nr && ar;
+            double Jv = 0.0, dx, dy;
+            if (lo && hi) {
+                dx = xr - xl;
+                dy = yr - yl;
+                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_full;
+            } else if (hi) {
+                dx = xr - st[0];
+                dy = yr - st[1];
+                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
+            } else if (lo) {
+                dx = st[0] - xl;
+                dy = st[1] - yl;
+                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
+            }
+            if (Jv < P.j_min) Jv = P.j_min;
+            const size_t k = base + (size_t)n * P.nr;
+            XY[k] = make_double2(st[0], st[1]);
+            AB[k] = make_double2(sqrt((1.0 / s0) / (eight_pi * Jv)), st[4]);
         }
-        if (Jv < P.j_min) Jv = P.j_min;
-        double s, gx, gy, av;
-        field(sa, P, X[k], Y[k], s, gx, gy, av);
-        AMP[k] = sqrt((1.0 / s) / (eight_pi * Jv));
+        if (alive && (last || n == P.nmax)) {
+            if (own) L[(size_t)eb * P.nr + j] = n;
+            alive = false;
+        }
+        if (alive) {
+            double k1[5], k2[5], k3[5], k4[5], t[5];
+            {
+                const double is = 1.0 / s0, is2 = is * is;
+                k1[0] = st[2] * is2;
+                k1[1] = st[3] * is2;
+                k1[2] = g0x * is;
+                k1[3] = g0y * is;
+                k1[4] = a0 * is;
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k1[q];
+            rhs(sa, P, t, k2);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k2[q];
+            rhs(sa, P, t, k3);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) t[q] = st[q] + dt * k3[q];
+            rhs(sa, P, t, k4);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) st[q] = st[q] + sixth * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+            last = st[0] * st[0] + st[1] * st[1] > P.rdie2;
+        }
     }
 }
 
@@ -184,7 +203,7 @@ __device__ __forceinline__ uint64_t order_key(double t) {
 }
 
 struct Tri {
-    double ax, ay, e1x, e1y, e2x, e2y, det;
+    double ax, ay, e1x, e1y, e2x, e2y, det, inv_det;
     double xmin, xmax, ymin, ymax;
 };
 
@@ -195,6 +214,7 @@ __device__ __forceinline__ bool make_tri(double ax, double ay, double bx, double
     t.e2x = cx - ax; t.e2y = cy - ay;
     t.det = t.e1x * t.e2y - t.e1y * t.e2x;
     if (t.det == 0.0) return false;
+    t.inv_det = 1.0 / t.det;
     t.xmin = fmin(ax, fmin(bx, cx)); t.xmax = fmax(ax, fmax(bx, cx));
     t.ymin = fmin(ay, fmin(by, cy)); t.ymax = fmax(ay, fmax(by, cy));
     return true;
@@ -204,8 +224,8 @@ __device__ __forceinline__ bool make_tri(double ax, double ay, double bx, double
 __device__ __forceinline__ bool bary(const Tri &t, double px, double py, double tol, double &la, double &lb,
                                      double &lc) {
     double qx = px - t.ax, qy = py - t.ay;
-    lb = (qx * t.e2y - qy * t.e2x) / t.det;
-    lc = (t.e1x * qy - t.e1y * qx) / t.det;
+    lb = (qx * t.e2y - qy * t.e2x) * t.inv_det;
+    lc = (t.e1x * qy - t.e1y * qx) * t.inv_det;
     la = (1.0 - lb) - lc;
     return !(la < tol || lb < tol || lc < tol);
 }
@@ -223,7 +243,9 @@ __device__ __forceinline__ void tri_nodes(int64_t base, int n, int j, int nr, in
 }
 
 // Receivers that may lie in a triangle's bounding box: a conservative index
-// range around the ring, or the whole ring when the box contains the centre.
+// range around the ring (the box lies in a disc of radius hd around its
+// centre c, which subtends at most asin(hd/|c|) <= hd/(|c| - hd) from the
+// origin), or the whole ring when that bound does not apply.
 __device__ __forceinline__ bool rx_range(const TP &P, const Tri &t, int &rlo, int &rhi) {
     double dxm = t.xmin > 0.0 ? t.xmin : (t.xmax < 0.0 ? -t.xmax : 0.0);
     double dym = t.ymin > 0.0 ? t.ymin : (t.ymax < 0.0 ? -t.ymax : 0.0);
@@ -231,24 +253,17 @@ __device__ __forceinline__ bool rx_range(const TP &P, const Tri &t, int &rlo, in
     double dmax = sqrt(fmax(t.xmin * t.xmin, t.xmax * t.xmax) + fmax(t.ymin * t.ymin, t.ymax * t.ymax));
     if (!(dmin >= 0.0) || !(dmax >= 0.0)) return false;  // NaN nodes: nothing to test
     if (dmin > P.R * (1.0 + 1e-9) || dmax < P.R * (1.0 - 1e-9)) return false;
-    if (dmin <= 0.0) {
+    const double cx = 0.5 * (t.xmin + t.xmax), cy = 0.5 * (t.ymin + t.ymax);
+    const double wx = t.xmax - t.xmin, wy = t.ymax - t.ymin;
+    const double hd = 0.5 * sqrt(wx * wx + wy * wy);
+    const double rc = sqrt(cx * cx + cy * cy);
+    if (!(rc > 2.0 * hd)) {
         rlo = 0; rhi = P.m - 1;
         return true;
     }
-    double cx = 0.5 * (t.xmin + t.xmax), cy = 0.5 * (t.ymin + t.ymax);
-    double th = atan2(cy, cx);
-    double lo = 0.0, hi = 0.0;
-    double xs[2] = {t.xmin, t.xmax}, ys[2] = {t.ymin, t.ymax};
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            double rel = atan2(cx * ys[b] - cy * xs[a], cx * xs[a] + cy * ys[b]);
-            lo = fmin(lo, rel);
-            hi = fmax(hi, rel);
-        }
-    double w = 2.0 * M_PI / (double)P.m;
-    const double flo = floor((th + lo) / w) - 1.0, fhi = ceil((th + hi) / w) + 1.0;
+    const double th = atan2(cy, cx), dth = hd / (rc - hd);
+    const double w = 2.0 * M_PI / (double)P.m;
+    const double flo = floor((th - dth) / w) - 1.0, fhi = ceil((th + dth) / w) + 1.0;
     if (!(fhi - flo + 1.0 < (double)P.m) || !(flo >= -2.0 * P.m) || !(fhi <= 2.0 * P.m)) {
         rlo = 0; rhi = P.m - 1;   // whole ring (also catches non-finite angles)
         return true;
@@ -258,34 +273,150 @@ __device__ __forceinline__ bool rx_range(const TP &P, const Tri &t, int &rlo, in
     return true;
 }
 
-__device__ __forceinline__ void rx_pos(const TP &P, int r, double &x, double &y) {
-    double th = 2.0 * M_PI * (double)r / (double)P.m;
-    x = P.R * cos(th);
-    y = P.R * sin(th);
+// Element positions, computed once per call.
+__global__ void k_rx_pos(TP P, double2 *__restrict__ rxy) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P.m) return;
+    const double th = 2.0 * M_PI * (double)r / (double)P.m;
+    rxy[r] = make_double2(P.R * cos(th), P.R * sin(th));
 }
 
-// Pass 1 (mode 0): atomicMin of the T key.  Pass 2 (mode 1): atomicMin of
-// the triangle index among candidates whose key equals the minimum.
+// Cell ids: (batch emitter << 31) | (step << 13) | ray.
+__device__ __forceinline__ uint64_t cell_id(int eb, int n, int j) {
+    return ((uint64_t)eb << 31) | ((uint64_t)n << 13) | (uint64_t)j;
+}
+__device__ __forceinline__ void cell_decode(uint64_t id, int &eb, int &n, int &j) {
+    j = (int)(id & 8191u);
+    n = (int)((id >> 13) & 262143u);
+    eb = (int)(id >> 31);
+}
+
+// Pass 0: classify every live cell of the wavefront mesh.  A cell whose
+// bounding box holds a pixel centre goes to the pixel list, one whose box
+// straddles the ring to the ring list (tests conservative: each triangle's
+// box lies inside its cell's).  Every wave owns a private segment of each
+// list (64 entries per iteration of its loop) and appends with ballot
+// prefixes, so there is no contended counter; the loop runs until the
+// wave's last live cell, with the finished lanes idle.
+__global__ void __launch_bounds__(256) k_cells(TP P, const double2 *__restrict__ XY, const int *__restrict__ L,
+                                               int cap, uint64_t *__restrict__ list_px, uint64_t *__restrict__ list_rx,
+                                               int *__restrict__ seg_px, int *__restrict__ seg_rx) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = blockIdx.x * 64 + lane;
+    const int eb = blockIdx.z;
+    const int64_t seg = (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 + wave;
+    uint64_t *lp = list_px + seg * cap;
+    uint64_t *lr = list_rx + seg * cap;
+    const int *Le = L + (size_t)eb * P.nr;
+    const int nlast = j < P.nr - 1 ? min(min(Le[j], Le[j + 1]) - 1, P.nmax - 1) : -1;
+    const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int cp = 0, cr = 0;   // wave-uniform counts
+    for (int n = blockIdx.y * 4 + wave;; n += gridDim.y * 4) {
+        const bool act = n <= nlast;
+        if (!__any(act)) break;
+        bool pix = false, ring = false;
+        if (act) {
+            const int64_t k00 = base + (int64_t)n * P.nr + j;
+            const double2 q00 = XY[k00], q10 = XY[k00 + 1], q01 = XY[k00 + P.nr], q11 = XY[k00 + P.nr + 1];
+            const double cxmin = fmin(fmin(q00.x, q10.x), fmin(q01.x, q11.x));
+            const double cxmax = fmax(fmax(q00.x, q10.x), fmax(q01.x, q11.x));
+            const double cymin = fmin(fmin(q00.y, q10.y), fmin(q01.y, q11.y));
+            const double cymax = fmax(fmax(q00.y, q10.y), fmax(q01.y, q11.y));
+            pix = ceil((cxmin - P.x0) * P.inv_h) <= fmin(floor((cxmax - P.x0) * P.inv_h), (double)(P.nx - 1)) &&
+                  ceil((cymin - P.y0) * P.inv_h) <= fmin(floor((cymax - P.y0) * P.inv_h), (double)(P.ny - 1)) &&
+                  cxmax >= P.x0 && cymax >= P.y0;
+            const double dxm = cxmin > 0.0 ? cxmin : (cxmax < 0.0 ? -cxmax : 0.0);
+            const double dym = cymin > 0.0 ? cymin : (cymax < 0.0 ? -cymax : 0.0);
+            const double dmin2 = dxm * dxm + dym * dym;
+            const double dmax2 = fmax(cxmin * cxmin, cxmax * cxmax) + fmax(cymin * cymin, cymax * cymax);
+            ring = dmin2 <= P.ring2_hi && dmax2 >= P.ring2_lo;
+        }
+        const uint64_t mp = __ballot(pix), mr = __ballot(ring);
+        const uint64_t id = cell_id(eb, n, j);
+        if (pix) lp[cp + __popcll(mp & below)] = id;
+        if (ring) lr[cr + __popcll(mr & below)] = id;
+        cp += __popcll(mp);
+        cr += __popcll(mr);
+    }
+    if (lane == 0) {
+        seg_px[seg] = cp;
+        seg_rx[seg] = cr;
+    }
+}
+
+// Pass 1 (MODE 0): atomicMin of the T key.  Pass 2 (MODE 1): atomicMin of
+// the triangle index among candidates whose key equals the minimum.  Each
+// wave walks one list segment.  Per triangle, the candidate pixel range
+// comes first and the determinant only when the range is not empty.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_raster(TP P, const double *__restrict__ X, const double *__restrict__ Y,
-                                                const int *__restrict__ L, uint64_t *__restrict__ tkey,
-                                                uint64_t *__restrict__ ikey, uint64_t *__restrict__ tkey_rx,
-                                                uint64_t *__restrict__ ikey_rx) {
-    const int64_t cells_per = (int64_t)P.nmax * (P.nr - 1);
-    const int64_t tot = cells_per * P.ne;
+__global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restrict__ XY, int nseg, int cap,
+                                                   const uint64_t *__restrict__ list, const int *__restrict__ segn,
+                                                   uint64_t *__restrict__ tkey, uint64_t *__restrict__ ikey) {
     const int64_t N = (int64_t)P.nx * P.ny;
     const double tol = -P.bary_tol;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int eb = (int)(idx / cells_per);
-        const int64_t rem = idx - (int64_t)eb * cells_per;
-        const int n = (int)(rem / (P.nr - 1));
-        const int j = (int)(rem - (int64_t)n * (P.nr - 1));
-        const int *Le = L + (size_t)eb * P.nr;
-        if (n + 1 > Le[j] || n + 1 > Le[j + 1]) continue;
+    const int lane = threadIdx.x & 63;
+    const int64_t seg = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (seg >= nseg) return;
+    const int cnt = segn[seg];
+    for (int i = lane; i < cnt; i += 64) {
+        int eb, n, j;
+        cell_decode(list[seg * cap + i], eb, n, j);
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
         uint64_t *tk = tkey + eb * N;
         uint64_t *ik = ikey + eb * N;
+        for (int tri = 0; tri < 2; ++tri) {
+            int64_t ka, kb, kc;
+            int na, nb, nc;
+            tri_nodes(base, n, j, P.nr, tri, ka, kb, kc, na, nb, nc);
+            const double2 pa = XY[ka], pb = XY[kb], pc = XY[kc];
+            const double xmin = fmin(pa.x, fmin(pb.x, pc.x)), xmax = fmax(pa.x, fmax(pb.x, pc.x));
+            const double ymin = fmin(pa.y, fmin(pb.y, pc.y)), ymax = fmax(pa.y, fmax(pb.y, pc.y));
+            double ilo = ceil((xmin - P.x0) * P.inv_h), ihi = floor((xmax - P.x0) * P.inv_h);
+            double jlo = ceil((ymin - P.y0) * P.inv_h), jhi = floor((ymax - P.y0) * P.inv_h);
+            if (ilo < 0.0) ilo = 0.0;
+            if (jlo < 0.0) jlo = 0.0;
+            if (ihi > (double)(P.nx - 1)) ihi = (double)(P.nx - 1);
+            if (jhi > (double)(P.ny - 1)) jhi = (double)(P.ny - 1);
+            if (!(ilo <= ihi && jlo <= jhi)) continue;
+            Tri t;
+            if (!make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t)) continue;
+            const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
+            const uint64_t my = ((((uint64_t)n * P.nr) + j) << 1) | (uint64_t)tri;
+            for (long jj = (long)jlo; jj <= (long)jhi; ++jj) {
+                for (long ii = (long)ilo; ii <= (long)ihi; ++ii) {
+                    double la, lb, lc;
+                    if (!bary(t, P.x0 + (double)ii * P.h, P.y0 + (double)jj * P.h, tol, la, lb, lc)) continue;
+                    const double tv = la * ta + lb * tb + lc * tc;
+                    const uint64_t key = order_key(tv);
+                    const int64_t p = (int64_t)jj * P.nx + ii;
+                    if (MODE == 0) {
+                        atomicMin((unsigned long long *)&tk[p], (unsigned long long)key);
+                    } else if (key == tk[p]) {
+                        atomicMin((unsigned long long *)&ik[p], (unsigned long long)my);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The same two passes over the ring list, for the ring elements.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restrict__ XY, int nseg, int cap,
+                                                   const uint64_t *__restrict__ list, const int *__restrict__ segn,
+                                                   const double2 *__restrict__ rxy, uint64_t *__restrict__ tkey_rx,
+                                                   uint64_t *__restrict__ ikey_rx) {
+    const double tol = -P.bary_tol;
+    const int lane = threadIdx.x & 63;
+    const int64_t seg = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (seg >= nseg) return;
+    const int cnt = segn[seg];
+    for (int i = lane; i < cnt; i += 64) {
+        int eb, n, j;
+        cell_decode(list[seg * cap + i], eb, n, j);
+        const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
         uint64_t *tkr = tkey_rx + (int64_t)eb * P.m;
         uint64_t *ikr = ikey_rx + (int64_t)eb * P.m;
         for (int tri = 0; tri < 2; ++tri) {
@@ -293,50 +424,24 @@ __global__ void __launch_bounds__(256) k_raster(TP P, const double *__restrict__
             int na, nb, nc;
             tri_nodes(base, n, j, P.nr, tri, ka, kb, kc, na, nb, nc);
             Tri t;
-            if (!make_tri(X[ka], Y[ka], X[kb], Y[kb], X[kc], Y[kc], t)) continue;
+            const double2 pa = XY[ka], pb = XY[kb], pc = XY[kc];
+            if (!make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t)) continue;
+            int rlo, rhi;
+            if (!rx_range(P, t, rlo, rhi)) continue;
             const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
             const uint64_t my = ((((uint64_t)n * P.nr) + j) << 1) | (uint64_t)tri;
-            // pixel centres inside the closed bounding box
-            double ilo = ceil((t.xmin - P.x0) / P.h), ihi = floor((t.xmax - P.x0) / P.h);
-            double jlo = ceil((t.ymin - P.y0) / P.h), jhi = floor((t.ymax - P.y0) / P.h);
-            if (ilo < 0.0) ilo = 0.0;
-            if (jlo < 0.0) jlo = 0.0;
-            if (ihi > (double)(P.nx - 1)) ihi = (double)(P.nx - 1);
-            if (jhi > (double)(P.ny - 1)) jhi = (double)(P.ny - 1);
-            if (ilo <= ihi && jlo <= jhi) {
-                for (long jj = (long)jlo; jj <= (long)jhi; ++jj) {
-                    for (long ii = (long)ilo; ii <= (long)ihi; ++ii) {
-                        double la, lb, lc;
-                        if (!bary(t, P.x0 + (double)ii * P.h, P.y0 + (double)jj * P.h, tol, la, lb, lc))
-                            continue;
-                        const double tv = la * ta + lb * tb + lc * tc;
-                        const uint64_t key = order_key(tv);
-                        const int64_t p = (int64_t)jj * P.nx + ii;
-                        if (MODE == 0) {
-                            atomicMin((unsigned long long *)&tk[p], (unsigned long long)key);
-                        } else if (key == tk[p]) {
-                            atomicMin((unsigned long long *)&ik[p], (unsigned long long)my);
-                        }
-                    }
-                }
-            }
-            // ring elements
-            int rlo, rhi;
-            if (rx_range(P, t, rlo, rhi)) {
-                for (int rr = rlo; rr <= rhi; ++rr) {
-                    const int r = ((rr % P.m) + P.m) % P.m;
-                    double px, py;
-                    rx_pos(P, r, px, py);
-                    if (px < t.xmin || px > t.xmax || py < t.ymin || py > t.ymax) continue;
-                    double la, lb, lc;
-                    if (!bary(t, px, py, tol, la, lb, lc)) continue;
-                    const double tv = la * ta + lb * tb + lc * tc;
-                    const uint64_t key = order_key(tv);
-                    if (MODE == 0) {
-                        atomicMin((unsigned long long *)&tkr[r], (unsigned long long)key);
-                    } else if (key == tkr[r]) {
-                        atomicMin((unsigned long long *)&ikr[r], (unsigned long long)my);
-                    }
+            for (int rr = rlo; rr <= rhi; ++rr) {
+                const int r = ((rr % P.m) + P.m) % P.m;
+                const double2 q = rxy[r];
+                if (q.x < t.xmin || q.x > t.xmax || q.y < t.ymin || q.y > t.ymax) continue;
+                double la, lb, lc;
+                if (!bary(t, q.x, q.y, tol, la, lb, lc)) continue;
+                const double tv = la * ta + lb * tb + lc * tc;
+                const uint64_t key = order_key(tv);
+                if (MODE == 0) {
+                    atomicMin((unsigned long long *)&tkr[r], (unsigned long long)key);
+                } else if (key == tkr[r]) {
+                    atomicMin((unsigned long long *)&ikr[r], (unsigned long long)my);
                 }
             }
         }
@@ -347,23 +452,23 @@ __global__ void __launch_bounds__(256) k_raster(TP P, const double *__restrict__
 // writes T (in place of the key), a and B.  Points are pixels (RX = false)
 // or ring elements (RX = true).
 template <bool RX>
-__global__ void k_raster_write(TP P, const double *__restrict__ X, const double *__restrict__ Y,
-                               const double *__restrict__ Bn, const double *__restrict__ AMP,
-                               uint64_t *__restrict__ tkey, const uint64_t *__restrict__ ikey,
-                               float *__restrict__ amp_out, float *__restrict__ att_out) {
+__global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const double2 *__restrict__ AB,
+                               const double2 *__restrict__ rxy, uint64_t *__restrict__ tkey,
+                               const uint64_t *__restrict__ ikey, float *__restrict__ amp_out,
+                               float *__restrict__ att_out) {
     const int64_t npts = RX ? (int64_t)P.m : (int64_t)P.nx * P.ny;
-    const int64_t tot = npts * P.ne;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int eb = (int)(idx / npts);
-        const int64_t p = idx - (int64_t)eb * npts;
+    {
+        const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int eb = blockIdx.y;
+        if (p >= npts) return;
+        const int64_t idx = (int64_t)eb * npts + p;
         const uint64_t key = tkey[idx];
         double *Tout = reinterpret_cast<double *>(tkey);
         if (key == ~0ull) {
             Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
             amp_out[idx] = 0.0f;
             att_out[idx] = 0.0f;
-            continue;
+            return;
         }
         const uint64_t w = ikey[idx];
         const int tri = (int)(w & 1ull);
@@ -374,7 +479,7 @@ __global__ void k_raster_write(TP P, const double *__restrict__ X, const double 
             Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
             amp_out[idx] = 0.0f;
             att_out[idx] = 0.0f;
-            continue;
+            return;
         }
         const int n = (int)n64;
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
@@ -382,12 +487,15 @@ __global__ void k_raster_write(TP P, const double *__restrict__ X, const double 
         int na, nb, nc;
         tri_nodes(base, n, j, P.nr, tri, ka, kb, kc, na, nb, nc);
         Tri t;
-        make_tri(X[ka], Y[ka], X[kb], Y[kb], X[kc], Y[kc], t);
+        const double2 pa = XY[ka], pb = XY[kb], pc = XY[kc];
+        make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t);
         double px, py;
         if (RX) {
-            rx_pos(P, (int)p, px, py);
+            const double2 q = rxy[p];
+            px = q.x;
+            py = q.y;
         } else {
-            const int64_t jj = p / P.nx, ii = p - jj * P.nx;
+            const int jj = (int)((uint32_t)p / (uint32_t)P.nx), ii = (int)(p - (int64_t)jj * P.nx);
             px = P.x0 + (double)ii * P.h;
             py = P.y0 + (double)jj * P.h;
         }
@@ -395,22 +503,41 @@ __global__ void k_raster_write(TP P, const double *__restrict__ X, const double 
         bary(t, px, py, -P.bary_tol, la, lb, lc);
         const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
         Tout[idx] = la * ta + lb * tb + lc * tc;
-        amp_out[idx] = (float)(la * AMP[ka] + lb * AMP[kb] + lc * AMP[kc]);
-        att_out[idx] = (float)(la * Bn[ka] + lb * Bn[kb] + lc * Bn[kc]);
+        const double2 qa = AB[ka], qb = AB[kb], qc = AB[kc];
+        amp_out[idx] = (float)(la * qa.x + lb * qb.x + lc * qc.x);
+        att_out[idx] = (float)(la * qa.y + lb * qb.y + lc * qc.y);
     }
 }
 
+// Launch shape of the cell passes: x = 64-ray column blocks, y = step
+// groups (4 waves each), z = emitters; each wave owns a list segment of
+// 64 entries per loop iteration.
+constexpr int kCellGroupsY = 8;
+inline int cell_iters(const rb_trace_opts *t) {
+    const int stride = kCellGroupsY * 4;
+    return (int)((trace_nmax(t) + stride - 1) / stride);
+}
+inline int cell_seg_cap(const rb_trace_opts *t) { return 64 * cell_iters(t); }
+inline size_t cell_segments(const rb_geometry *g, const rb_trace_opts *t, int batch) {
+    (void)g;
+    return (size_t)((t->n_rays - 1 + 63) / 64) * kCellGroupsY * 4 * batch;
+}
+
 struct TraceWs {
-    double2 *sa;
-    double *X, *Y, *Bn, *AMP;
+    double2 *sa, *rxy;
+    double2 *XY, *AB;   // node position (x, y) and (amplitude factor, absorption)
     int *L;
     uint64_t *ikey, *ikey_rx;
+    uint64_t *list_px, *list_rx;  // candidate cells (pixel / ring), one segment per wave
+    int *seg_px, *seg_rx;         // segment lengths
 };
 
 size_t per_emitter_bytes(const rb_geometry *g, const rb_trace_opts *t) {
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays;
-    return nodes * 4 * sizeof(double) + (size_t)t->n_rays * sizeof(int) +
-           (size_t)g->nx * g->ny * sizeof(uint64_t) + (size_t)g->m * sizeof(uint64_t) + 8 * 256;
+    const size_t segs = cell_segments(g, t, 1);
+    return nodes * 2 * sizeof(double2) + (size_t)t->n_rays * sizeof(int) +
+           (size_t)g->nx * g->ny * sizeof(uint64_t) + (size_t)g->m * sizeof(uint64_t) +
+           2 * segs * (cell_seg_cap(t) * sizeof(uint64_t) + sizeof(int)) + 12 * 256;
 }
 
 TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int batch) {
@@ -418,13 +545,17 @@ TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int
     const size_t N = (size_t)g->nx * g->ny;
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays * batch;
     w.sa = c.take<double2>(N);
-    w.X = c.take<double>(nodes);
-    w.Y = c.take<double>(nodes);
-    w.Bn = c.take<double>(nodes);
-    w.AMP = c.take<double>(nodes);
+    w.rxy = c.take<double2>((size_t)g->m);
+    w.XY = c.take<double2>(nodes);
+    w.AB = c.take<double2>(nodes);
     w.L = c.take<int>((size_t)t->n_rays * batch);
     w.ikey = c.take<uint64_t>(N * batch);
     w.ikey_rx = c.take<uint64_t>((size_t)g->m * batch);
+    const size_t segs = cell_segments(g, t, batch);
+    w.list_px = c.take<uint64_t>(segs * cell_seg_cap(t));
+    w.list_rx = c.take<uint64_t>(segs * cell_seg_cap(t));
+    w.seg_px = c.take<int>(segs);
+    w.seg_rx = c.take<int>(segs);
     return w;
 }
 
@@ -451,7 +582,8 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         set_error("trace workspace too small: need >= %zu bytes, got %zu", one, ws_bytes);
         return RB_ENOMEM;
     }
-    int batch = (int)std::min<size_t>((size_t)g->m, 1 + (ws_bytes - one) / per_emitter_bytes(g, t));
+    // largest batch whose carve fits (estimate from above, then step down)
+    int batch = (int)std::min<size_t>((size_t)g->m, 2 + (ws_bytes - one) / (per_emitter_bytes(g, t) - 12 * 256));
     while (batch > 1) {
         Carver c2(nullptr, 0);
         carve_trace(c2, g, t, batch);
@@ -464,6 +596,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
 
     TP P;
     P.nx = g->nx; P.ny = g->ny; P.h = g->h; P.x0 = g->x0; P.y0 = g->y0;
+    P.inv_h = 1.0 / g->h;
     P.m = g->m; P.R = g->ring_radius; P.s_bg = 1.0 / g->c_background;
     P.nr = t->n_rays; P.dtau = t->dtau; P.nmax = (int)trace_nmax(t);
     const double r_die = g->ring_radius + 2.0 * g->h;
@@ -473,8 +606,12 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     const double dpsi = M_PI / (double)t->n_rays;
     P.two_sin_full = 2.0 * std::sin(dpsi);
     P.two_sin_half = 2.0 * std::sin(0.5 * dpsi);
+    P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
+    P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
 
     k_pack<<<blocks_for(N, 256), 256, 0, st>>>(slowness, alpha0, N, w.sa);
+    RB_LAUNCHED();
+    k_rx_pos<<<blocks_for(g->m, 256), 256, 0, st>>>(P, w.rxy);
     RB_LAUNCHED();
     for (int e0 = 0; e0 < g->m; e0 += batch) {
         P.e0 = e0;
@@ -485,27 +622,31 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         RB_TRY(fill_u64(w.ikey, ~0ull, (int64_t)P.ne * N, st));
         RB_TRY(fill_u64(tkey_rx, ~0ull, (int64_t)P.ne * g->m, st));
         RB_TRY(fill_u64(w.ikey_rx, ~0ull, (int64_t)P.ne * g->m, st));
-        dim3 gt(blocks_for(P.nr, 128), P.ne);
-        k_trace<<<gt, 128, 0, st>>>(P, w.sa, w.X, w.Y, w.Bn, w.L);
+        const int waves = (P.nr + kOwn - 1) / kOwn;
+        dim3 gt((waves + 3) / 4, P.ne);
+        k_trace<<<gt, 256, 0, st>>>(P, w.sa, w.XY, w.AB, w.L);
         RB_LAUNCHED();
-        const int64_t nodes = (int64_t)(P.nmax + 1) * P.nr * P.ne;
-        unsigned bs = (unsigned)std::min<int64_t>(blocks_for(nodes, 256), 1 << 20);
-        k_spread<<<bs, 256, 0, st>>>(P, w.sa, w.X, w.Y, w.L, w.AMP);
+        const int cap = cell_seg_cap(t);
+        const int nseg = (int)cell_segments(g, t, P.ne);
+        dim3 gc(blocks_for(P.nr - 1, 64), kCellGroupsY, P.ne);
+        k_cells<<<gc, 256, 0, st>>>(P, w.XY, w.L, cap, w.list_px, w.list_rx, w.seg_px, w.seg_rx);
         RB_LAUNCHED();
-        const int64_t cells = (int64_t)P.nmax * (P.nr - 1) * P.ne;
-        unsigned bc = (unsigned)std::min<int64_t>(blocks_for(cells, 256), 1 << 20);
-        k_raster<0><<<bc, 256, 0, st>>>(P, w.X, w.Y, w.L, tkey, w.ikey, tkey_rx, w.ikey_rx);
+        const unsigned nbl = blocks_for(nseg, 4);
+        k_raster_px<0><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, tkey, w.ikey);
         RB_LAUNCHED();
-        k_raster<1><<<bc, 256, 0, st>>>(P, w.X, w.Y, w.L, tkey, w.ikey, tkey_rx, w.ikey_rx);
+        k_raster_rx<0><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, tkey_rx, w.ikey_rx);
         RB_LAUNCHED();
-        const int64_t npx = N * P.ne;
-        k_raster_write<false><<<(unsigned)std::min<int64_t>(blocks_for(npx, 256), 1 << 20), 256, 0, st>>>(
-            P, w.X, w.Y, w.Bn, w.AMP, tkey, w.ikey, out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
+        k_raster_px<1><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, tkey, w.ikey);
         RB_LAUNCHED();
-        const int64_t nrx = (int64_t)g->m * P.ne;
-        k_raster_write<true><<<blocks_for(nrx, 256), 256, 0, st>>>(
-            P, w.X, w.Y, w.Bn, w.AMP, tkey_rx, w.ikey_rx, out->amp_rx + (int64_t)e0 * g->m,
-            out->att_rx + (int64_t)e0 * g->m);
+        k_raster_rx<1><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, tkey_rx, w.ikey_rx);
+        RB_LAUNCHED();
+        dim3 gw(blocks_for(N, 256), P.ne);
+        k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey, w.ikey,
+                                                  out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
+        RB_LAUNCHED();
+        dim3 gr(blocks_for(g->m, 256), P.ne);
+        k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey_rx, w.ikey_rx,
+                                                 out->amp_rx + (int64_t)e0 * g->m, out->att_rx + (int64_t)e0 * g->m);
         RB_LAUNCHED();
     }
     return RB_OK;
