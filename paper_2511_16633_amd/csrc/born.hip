@@ -371,7 +371,7 @@ __global__ void k_adj_absmax(int m, const double *__restrict__ d, const double *
 template <typename T, bool SCALED, bool PERMUTE = false>
 __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, const double *__restrict__ w,
                            const float *__restrict__ ascale, T *__restrict__ Ar, T *__restrict__ Ai,
-                           T *__restrict__ Wt) {
+                           T *__restrict__ Wt, T *__restrict__ As = nullptr) {
     const int64_t per = (int64_t)mp * mp;
     const int64_t tot = per * nf;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
@@ -399,6 +399,7 @@ __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, 
         Ar[o] = cvt<T>(re);
         Ai[o] = cvt<T>(im);
         Wt[o] = cvt<T>(wv);
+        if (As) As[o] = cvt<T>(re + im);
     }
 }
 
@@ -661,46 +662,58 @@ __device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], con
     *reinterpret_cast<f4 *>(&sB[1][rr][c4 + 32]) = v[3];
 }
 
-// NB row blocks starting at b0: for each step, first the Ar.Gr, Ar.Gi and
-// W.|G|^2 products of every (row block, column block), then the Ai terms.
+// NB row blocks starting at b0.  The complex product Y = A conj(G) uses
+// three real products, P1 = Ar Gr, P2 = Ai Gi, P3 = (Ar + Ai)(Gr - Gi), so
+// Yr = P1 + P2 and Yi = P3 - P1 + P2; with the Hessian term Z = W |G|^2 that
+// is four MFMAs per block and step, each on a different accumulator.
 template <int NB>
-__device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&vi)[2][2], const f4 (&vw)[2][2],
-                                              const float (&br)[8][2], const float (&bi)[8][2], f4 (&yr)[2][2],
-                                              f4 (&yn)[2][2], f4 (&z)[2][2], int b0) {
+__device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&vi)[2][2], const f4 (&vs)[2][2],
+                                              const f4 (&vw)[2][2], float (*sBr)[kAdjLD], float (*sBi)[kAdjLD],
+                                              int kk, int xc0, f4 (&p1)[2][2], f4 (&p2)[2][2], f4 (&p3)[2][2],
+                                              f4 (&z)[2][2], int b0) {
 #pragma unroll
-    for (int s8 = 0; s8 < 8; ++s8) {
-        float b2[8][2];
+    for (int half = 0; half < 2; ++half) {
+        // B fragments for four steps at a time (one LDS wait per half chunk)
+        float br[4][2], bi[4][2];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) b2[s8][cb] = br[s8][cb] * br[s8][cb] + bi[s8][cb] * bi[s8][cb];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = b0 + q;
-            const float a_r = va[b][s8 >> 2][s8 & 3], a_w = vw[b][s8 >> 2][s8 & 3];
+        for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                yr[b][cb] = MM<float>::mma(a_r, br[s8][cb], yr[b][cb]);
-                yn[b][cb] = MM<float>::mma(a_r, bi[s8][cb], yn[b][cb]);
-                z[b][cb] = MM<float>::mma(a_w, b2[s8][cb], z[b][cb]);
+                br[q4][cb] = sBr[4 * (4 * half + q4) + kk][xc0 + 16 * cb];
+                bi[q4][cb] = sBi[4 * (4 * half + q4) + kk][xc0 + 16 * cb];
             }
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+        const int s8 = 4 * half + q4;
+        float b2[2], bd[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            b2[cb] = br[q4][cb] * br[q4][cb] + bi[q4][cb] * bi[q4][cb];
+            bd[cb] = br[q4][cb] - bi[q4][cb];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int b = b0 + q;
-            const float a_i = vi[b][s8 >> 2][s8 & 3];
+            const float a_r = va[b][s8 >> 2][s8 & 3], a_i = vi[b][s8 >> 2][s8 & 3];
+            const float a_s = vs[b][s8 >> 2][s8 & 3], a_w = vw[b][s8 >> 2][s8 & 3];
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                yr[b][cb] = MM<float>::mma(a_i, bi[s8][cb], yr[b][cb]);
-                yn[b][cb] = MM<float>::mma(-a_i, br[s8][cb], yn[b][cb]);
+                p1[b][cb] = MM<float>::mma(a_r, br[q4][cb], p1[b][cb]);
+                p2[b][cb] = MM<float>::mma(a_i, bi[q4][cb], p2[b][cb]);
+                p3[b][cb] = MM<float>::mma(a_s, bd[cb], p3[b][cb]);
+                z[b][cb] = MM<float>::mma(a_w, b2[cb], z[b][cb]);
             }
         }
+    }
     }
 }
 
 __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
                                                         const float *__restrict__ Gi, const float *__restrict__ Ar,
-                                                        const float *__restrict__ Ai, const float *__restrict__ Wt,
-                                                        const uint8_t *__restrict__ flags, double *__restrict__ grad,
-                                                        double *__restrict__ hd) {
+                                                        const float *__restrict__ Ai, const float *__restrict__ As,
+                                                        const float *__restrict__ Wt,
+                                                        const uint8_t *__restrict__ flags, double *__restrict__ pg,
+                                                        double *__restrict__ ph) {
     __shared__ float sB[2][2][kAdjKC][kAdjLD];
     __shared__ double sred[2][2][kAdjNT];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -713,20 +726,22 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
     const int nch = P.mp / kAdjKC;
     double gacc[2] = {0.0, 0.0}, hacc[2] = {0.0, 0.0};
 
-    for (int k = 0; k < P.nf; ++k) {
+    {
+        const int k = blockIdx.y;   // one frequency per workgroup (finer work units)
         const float *gr = Gr + (int64_t)k * P.m * N;
         const float *gi = Gi + (int64_t)k * P.m * N;
         const float *ar = Ar + (int64_t)k * P.mp * P.mp;
         const float *ai = Ai + (int64_t)k * P.mp * P.mp;
+        const float *as = As + (int64_t)k * P.mp * P.mp;
         const float *wt = Wt + (int64_t)k * P.mp * P.mp;
         const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
         float gp[2] = {0.0f, 0.0f}, hp[2] = {0.0f, 0.0f};
         for (int ec = 0; ec < P.mp; ec += 64) {
-            f4 yr[2][2], yn[2][2], z[2][2];
+            f4 p1[2][2], p2[2][2], p3[2][2], z[2][2];
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
+                for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = z[b][c] = f4{0, 0, 0, 0};
             f4 stg[4];
             adj_stage_load(gr, gi, P.m, N, 0, x0, vec, stg);
             adj_stage_store(sB[0], stg);
@@ -735,40 +750,30 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                 const int rc = c * kAdjKC, buf = c & 1;
                 if (c + 1 < nch) adj_stage_load(gr, gi, P.m, N, rc + kAdjKC, x0, vec, stg);
                 bool on[2];
-                f4 va[2][2], vi[2][2], vw[2][2];
+                f4 va[2][2], vi[2][2], vs[2][2], vw[2][2];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     const int eb = (ec >> 4) + 2 * we + b;
                     on[b] = (eb < P.nb) && (fl[eb * P.nb + (rc >> 4)] | fl[eb * P.nb + (rc >> 4) + 1]);
-                    if (on[b]) {
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    if (on[0] || on[1]) {
                         const int64_t off = (int64_t)(ec + 32 * we + 16 * b + row) * P.mp + rc + 8 * kk;
                         va[b][0] = *reinterpret_cast<const f4 *>(ar + off);
                         va[b][1] = *reinterpret_cast<const f4 *>(ar + off + 4);
                         vi[b][0] = *reinterpret_cast<const f4 *>(ai + off);
                         vi[b][1] = *reinterpret_cast<const f4 *>(ai + off + 4);
+                        vs[b][0] = *reinterpret_cast<const f4 *>(as + off);
+                        vs[b][1] = *reinterpret_cast<const f4 *>(as + off + 4);
                         vw[b][0] = *reinterpret_cast<const f4 *>(wt + off);
                         vw[b][1] = *reinterpret_cast<const f4 *>(wt + off + 4);
                     }
                 }
                 if (on[0] || on[1]) {
-                    // all B fragments of the chunk first (one LDS wait), then
-                    // the MFMAs ordered so no accumulator is hit twice in a row
-                    float br[8][2], bi[8][2];
-#pragma unroll
-                    for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb) {
-                            const int xc = 32 * wp + 16 * cb + row;
-                            br[s8][cb] = sB[buf][0][4 * s8 + kk][xc];
-                            bi[s8][cb] = sB[buf][1][4 * s8 + kk][xc];
-                        }
-                    if (on[0] && on[1]) {
-                        adj_mma_steps<2>(va, vi, vw, br, bi, yr, yn, z, 0);
-                    } else if (on[0]) {
-                        adj_mma_steps<1>(va, vi, vw, br, bi, yr, yn, z, 0);
-                    } else {
-                        adj_mma_steps<1>(va, vi, vw, br, bi, yr, yn, z, 1);
-                    }
+                    // a block that is off holds exact zeros in A and W, so it
+                    // may be computed along with the other one
+                    adj_mma_steps<2>(va, vi, vs, vw, sB[buf][0], sB[buf][1], kk, 32 * wp + row, p1, p2, p3, z, 0);
                 }
                 if (c + 1 < nch) adj_stage_store(sB[buf ^ 1], stg);
                 __syncthreads();
@@ -785,7 +790,9 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                         const bool ok = (e < P.m) && (x < N);
                         const float ge_r = ok ? gr[(int64_t)e * N + x] : 0.0f;
                         const float ge_i = ok ? gi[(int64_t)e * N + x] : 0.0f;
-                        gp[cb] += ge_r * yr[b][cb][i] - ge_i * yn[b][cb][i];
+                        const float yr = p1[b][cb][i] + p2[b][cb][i];
+                        const float yi = (p3[b][cb][i] - p1[b][cb][i]) + p2[b][cb][i];
+                        gp[cb] += ge_r * yr + ge_i * yi;
                         hp[cb] += (ge_r * ge_r + ge_i * ge_i) * z[b][cb][i];
                     }
                 }
@@ -814,10 +821,24 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
     if (tid < kAdjNT) {
         const int64_t x = x0 + tid;
         if (x < N) {
-            grad[x] += sred[0][0][tid] + sred[1][0][tid];
-            if (hd) hd[x] += sred[0][1][tid] + sred[1][1][tid];
+            pg[(int64_t)blockIdx.y * N + x] = sred[0][0][tid] + sred[1][0][tid];
+            ph[(int64_t)blockIdx.y * N + x] = sred[0][1][tid] + sred[1][1][tid];
         }
     }
+}
+
+// grad += sum_k pg[k], hd += sum_k ph[k] in frequency order.
+__global__ void k_adj_sum(int64_t N, int nf, const double *__restrict__ pg, const double *__restrict__ ph,
+                          double *__restrict__ grad, double *__restrict__ hd) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    double g = 0.0, h = 0.0;
+    for (int k = 0; k < nf; ++k) {
+        g += pg[(int64_t)k * N + x];
+        h += ph[(int64_t)k * N + x];
+    }
+    grad[x] += g;
+    if (hd) hd[x] += h;
 }
 
 // Forward.  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
@@ -978,6 +999,20 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+// Compute units of the current device (cached per device; 256 on MI355X).
+static int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
 // rows/columns of the adjoint operands are padded to a multiple of 32
 static int pad_m(int m) { return (m + 31) / 32 * 32; }
 
@@ -999,9 +1034,10 @@ AdjParams adj_params(const rb_geometry *g, const double *freqs, int nf) {
 }
 
 struct AdjWs {
-    void *Ar, *Ai, *Wt;
+    void *Ar, *Ai, *Wt, *As;
     uint8_t *flags;
     float *ascale;
+    double *pg, *ph;  // per-frequency partials of the f32 backprojection
 };
 
 static AdjWs carve_adj(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
@@ -1012,8 +1048,11 @@ static AdjWs carve_adj(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
     w.Ar = c.take<char>(per * es);
     w.Ai = c.take<char>(per * es);
     w.Wt = c.take<char>(per * es);
+    w.As = c.take<char>(per * es);
     w.flags = c.take<uint8_t>((size_t)nf * (mp / 16) * (mp / 16));
     w.ascale = c.take<float>(RB_MAX_NF);
+    w.pg = c.take<double>((size_t)nf * g->nx * g->ny);
+    w.ph = c.take<double>((size_t)nf * g->nx * g->ny);
     return w;
 }
 
@@ -1047,7 +1086,8 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
         case RB_F32:
             k_adj_prep<float, false, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr,
-                                                               (float *)w.Ar, (float *)w.Ai, (float *)w.Wt);
+                                                               (float *)w.Ar, (float *)w.Ai, (float *)w.Wt,
+                                                               (float *)w.As);
             break;
         case RB_BF16:
             k_adj_prep<__hip_bfloat16, true><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, w.ascale,
@@ -1072,9 +1112,12 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
         }
         case RB_F32: {
-            k_adjoint_f32<<<blocks_for(P.N, kAdjNT), 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
-                                                                  (const float *)w.Ar, (const float *)w.Ai,
-                                                                  (const float *)w.Wt, w.flags, grad, hdiag);
+            dim3 ga(blocks_for(P.N, kAdjNT), nf);
+            k_adjoint_f32<<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, (const float *)w.Ar,
+                                              (const float *)w.Ai, (const float *)w.As, (const float *)w.Wt, w.flags,
+                                              w.pg, w.ph);
+            RB_LAUNCHED();
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
             break;
         }
         case RB_BF16: {
@@ -1105,8 +1148,10 @@ FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, rb_dtype
     P.nf = nf;
     P.ntl = P.mp / 64;
     const int ntri = P.ntl * (P.ntl + 1) / 2;
-    const int want = 2048;
-    int nsplit = std::max(1, (want + ntri * nf - 1) / (ntri * nf));
+    // about four rounds of resident workgroups (two per CU), rounded down so
+    // the last round is full
+    const int want = 4 * 2 * device_cus();
+    int nsplit = std::max(1, want / (ntri * nf));
     const int kq = (dt == RB_BF16 || dt == RB_F16) ? 32 : 16;
     int64_t kchunk = (P.N + nsplit - 1) / nsplit;
     kchunk = (kchunk + kq - 1) / kq * kq;
