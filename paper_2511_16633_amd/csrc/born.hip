@@ -921,11 +921,13 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
     const int nch = (int)((ke - ks + kFwdKC - 1) / kFwdKC);
     const int srow = tid >> 2, c8 = (tid & 3) * 8;
     const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
-    f4 re[2][2], im[2][2];
+    // (a + ib)(c + id) with three real products: P1 = ac, P2 = bd,
+    // P3 = (a + b)(c + d); re = P1 - P2, im = P3 - P1 - P2
+    f4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) re[b][c] = im[b][c] = f4{0, 0, 0, 0};
+        for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = f4{0, 0, 0, 0};
     FwdStage stg;
     auto vec_ok = [&](int64_t xc) { return ((N & 3) == 0) && (xc + kFwdKC <= ke); };
     auto store = [&](int buf) {
@@ -963,16 +965,18 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
         }
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8) {
+            float ys[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) ys[cb] = b_r[cb][s8 >> 2][s8 & 3] + b_i[cb][s8 >> 2][s8 & 3];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const float xr = a_r[b][s8 >> 2][s8 & 3], xi = a_i[b][s8 >> 2][s8 & 3];
+                const float xs = xr + xi;
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    const float yr_ = b_r[cb][s8 >> 2][s8 & 3], yi_ = b_i[cb][s8 >> 2][s8 & 3];
-                    re[b][cb] = MM<float>::mma(xr, yr_, re[b][cb]);
-                    re[b][cb] = MM<float>::mma(-xi, yi_, re[b][cb]);
-                    im[b][cb] = MM<float>::mma(xr, yi_, im[b][cb]);
-                    im[b][cb] = MM<float>::mma(xi, yr_, im[b][cb]);
+                    p1[b][cb] = MM<float>::mma(xr, b_r[cb][s8 >> 2][s8 & 3], p1[b][cb]);
+                    p2[b][cb] = MM<float>::mma(xi, b_i[cb][s8 >> 2][s8 & 3], p2[b][cb]);
+                    p3[b][cb] = MM<float>::mma(xs, ys[cb], p3[b][cb]);
                 }
             }
         }
@@ -989,8 +993,8 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
             for (int i = 0; i < 4; ++i) {
                 const int ee = te * 64 + 32 * we + 16 * b + MM<float>::out_row(kk, i);
                 const int64_t o = ((int64_t)ee * P.mp + r) * 2;
-                pp[o] = re[b][cb][i];
-                pp[o + 1] = im[b][cb][i];
+                pp[o] = p1[b][cb][i] - p2[b][cb][i];
+                pp[o + 1] = (p3[b][cb][i] - p1[b][cb][i]) - p2[b][cb][i];
             }
         }
     }

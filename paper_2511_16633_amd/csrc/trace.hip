@@ -43,36 +43,26 @@ struct TP {
     int e0, ne;        // emitter batch
 };
 
-__device__ __forceinline__ double2 corner(const double2 *__restrict__ sa, const TP &P, long i, long j) {
-    if (i < 0 || j < 0 || i >= P.nx || j >= P.ny) return make_double2(P.s_bg, 0.0);
-    return sa[(size_t)j * (size_t)P.nx + (size_t)i];
-}
-
 // Bilinear slowness s with its exact patch gradient, and bilinear alpha0.
+// `sa` is the (s, alpha0) grid padded with one ring of water cells, row
+// stride nx + 2, so every cell that touches the grid has its four corners in
+// memory and needs no per-corner test; cells farther out are pure water.
 __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &P, double x, double y,
                                       double &s, double &gx, double &gy, double &a) {
     double u = (x - P.x0) * P.inv_h;
     double v = (y - P.y0) * P.inv_h;
     double fi = floor(u), fj = floor(v);
-    if (!(fi >= -1.0 && fi <= (double)P.nx && fj >= -1.0 && fj <= (double)P.ny)) {
+    // cells with i <= -2, i >= nx, j <= -2 or j >= ny have all four corners
+    // outside the grid: pure water (value s_bg, zero gradient, no absorption)
+    if (!(fi >= -1.0 && fi <= (double)(P.nx - 1) && fj >= -1.0 && fj <= (double)(P.ny - 1))) {
         s = P.s_bg; gx = 0.0; gy = 0.0; a = 0.0;
         return;
     }
-    long i = (long)fi, j = (long)fj;
+    const int i = (int)fi + 1, j = (int)fj + 1;   // padded indices, 0 .. n; corners up to n + 1
     double fu = u - fi, fv = v - fj;
-    double2 c00, c10, c01, c11;
-    if (i >= 0 && j >= 0 && i + 1 < P.nx && j + 1 < P.ny) {  // all four corners inside
-        const double2 *q = sa + (size_t)j * (size_t)P.nx + (size_t)i;
-        c00 = q[0];
-        c10 = q[1];
-        c01 = q[P.nx];
-        c11 = q[P.nx + 1];
-    } else {
-        c00 = corner(sa, P, i, j);
-        c10 = corner(sa, P, i + 1, j);
-        c01 = corner(sa, P, i, j + 1);
-        c11 = corner(sa, P, i + 1, j + 1);
-    }
+    const int ld = P.nx + 2;
+    const double2 *q = sa + (j * ld + i);
+    const double2 c00 = q[0], c10 = q[1], c01 = q[ld], c11 = q[ld + 1];
     double dx0 = c10.x - c00.x, dx1 = c11.x - c01.x;
     double s0 = c00.x + fu * dx0;
     double s1 = c01.x + fu * dx1;
@@ -84,11 +74,20 @@ __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &
     a = a0 + fv * (a1 - a0);
 }
 
+// 1/s from the hardware reciprocal refined by two Newton steps (to within
+// an ulp of the correctly rounded quotient).
+__device__ __forceinline__ double recip(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = r * (2.0 - s * r);
+    r = r * (2.0 - s * r);
+    return r;
+}
+
 __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P, const double st[5],
                                     double d[5]) {
     double s, gx, gy, a;
     field(sa, P, st[0], st[1], s, gx, gy, a);
-    const double is = 1.0 / s;     // one division per stage
+    const double is = recip(s);
     const double is2 = is * is;
     d[0] = st[2] * is2;
     d[1] = st[3] * is2;
@@ -97,10 +96,19 @@ __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P,
     d[4] = a * is;
 }
 
-__global__ void k_pack(const double *__restrict__ s, const double *__restrict__ alpha, int64_t n,
+__global__ void k_pack(int nx, int ny, double s_bg, const double *__restrict__ s, const double *__restrict__ alpha,
                        double2 *__restrict__ sa) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) sa[i] = make_double2(s[i], alpha ? alpha[i] : 0.0);
+    const int64_t np = (int64_t)(nx + 2) * (ny + 2);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= np) return;
+    const int jp = (int)(q / (nx + 2)), ip = (int)(q - (int64_t)jp * (nx + 2));
+    const int i = ip - 1, j = jp - 1;
+    if (i < 0 || j < 0 || i >= nx || j >= ny) {
+        sa[q] = make_double2(s_bg, 0.0);
+    } else {
+        const int64_t p = (int64_t)j * nx + i;
+        sa[q] = make_double2(s[p], alpha ? alpha[p] : 0.0);
+    }
 }
 
 // Rays of one emitter are traced a wave at a time in lockstep: lanes 1..62
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
         if (alive) {
             double k1[5], k2[5], k3[5], k4[5], t[5];
             {
-                const double is = 1.0 / s0, is2 = is * is;
+                const double is = recip(s0), is2 = is * is;
                 k1[0] = st[2] * is2;
                 k1[1] = st[3] * is2;
                 k1[2] = g0x * is;
@@ -544,7 +552,7 @@ TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int
     TraceWs w;
     const size_t N = (size_t)g->nx * g->ny;
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays * batch;
-    w.sa = c.take<double2>(N);
+    w.sa = c.take<double2>((size_t)(g->nx + 2) * (g->ny + 2));
     w.rxy = c.take<double2>((size_t)g->m);
     w.XY = c.take<double2>(nodes);
     w.AB = c.take<double2>(nodes);
@@ -609,7 +617,8 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
     P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
 
-    k_pack<<<blocks_for(N, 256), 256, 0, st>>>(slowness, alpha0, N, w.sa);
+    const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
+    k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, 1.0 / g->c_background, slowness, alpha0, w.sa);
     RB_LAUNCHED();
     k_rx_pos<<<blocks_for(g->m, 256), 256, 0, st>>>(P, w.rxy);
     RB_LAUNCHED();
