@@ -1,0 +1,147 @@
+"""GPU parity at the bench workload's full size (256 elements, 480 x 480
+grid, 720 rays per element, 3 frequencies per set), in the launch
+configuration bench.py times.  The oracle checks sampled outputs it can
+compute one by one (tables of sampled emitters, the backprojection at
+sampled pixels, forward data at sampled pairs) and one whole frequency set.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import born, invert, rays
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_16633_amd as rbm
+    rbm.lib()
+    return rbm
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return W.breast_ring256()
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def test_fullsize_tables_sampled_emitters(rb, prob):
+    g = prob.geom
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    _say("full-size trace, all 256 emitters")
+    tabs = rb.alloc_tables(g, DEV)
+    rb.trace_rays(g, topts, _t(1.0 / prob.c_start.reshape(-1)), _t(prob.alpha0.reshape(-1)), tabs)
+    torch.cuda.synchronize()
+    for e in (0, 37, 128, 201):
+        T, A, B, Tr, Ar, Br = rays.tables(g, topts, 1.0 / prob.c_start, prob.alpha0, e, e + 1)
+        Tg = tabs["T"][e].cpu().numpy()
+        cg, co = np.isfinite(Tg), np.isfinite(T[0])
+        assert int((cg != co).sum()) <= 5
+        both = cg & co
+        assert both.sum() > 0.5 * Tg.size
+        assert np.max(np.abs(Tg[both] - T[0][both])) <= 1e-9
+        ag = tabs["amp"][e].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(ag[both] - A[0][both]) / A[0][both]) <= 2e-6
+        bg = tabs["att"][e].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(bg[both] - B[0][both])) <= 1e-6
+        Trg = tabs["T_rx"][e].cpu().numpy()
+        msk = invert.receiver_mask(g.m)[e]
+        assert np.all(np.isfinite(Trg[msk])) and np.all(np.isfinite(Tr[0][msk]))
+        assert np.max(np.abs(Trg[msk] - Tr[0][msk])) <= 1e-9
+
+
+def test_fullsize_backprojection_sampled_pixels(rb, prob):
+    g = prob.geom
+    nf = 3
+    T, A, B, _, _, _ = W.random_tables(g, seed=77)
+    freqs = list(prob.freq_sets[0])
+    D = W.random_residual(nf, g.m, 78)
+    mask = invert.receiver_mask(g.m).astype(np.float64)
+    rng = np.random.default_rng(79)
+    Wd = np.stack([mask * (rng.uniform(size=mask.shape) > 0.01) for _ in range(nf)])
+    _say("full-size backprojection f32 (random tables)")
+    tabs = {"T": _t(T), "amp": _t(A, torch.float32), "att": _t(B, torch.float32),
+            "T_rx": _t(np.zeros((g.m, g.m))), "amp_rx": _t(np.zeros((g.m, g.m)), torch.float32),
+            "att_rx": _t(np.zeros((g.m, g.m)), torch.float32)}
+    Gr = torch.empty((nf, g.m, g.n_pixels), dtype=torch.float32, device=DEV)
+    Gi = torch.empty_like(Gr)
+    rb.build_green(g, tabs, freqs, 1.0, "f32", Gr, Gi, None)
+    grad = torch.zeros(g.n_pixels, dtype=torch.float64, device=DEV)
+    hd = torch.zeros_like(grad)
+    rb.born_adjoint_weighted(g, Gr, Gi, None, "f32", freqs, _t(np.stack([D.real, D.imag], -1)), _t(Wd), grad, hd)
+    torch.cuda.synchronize()
+    gg, hg = grad.cpu().numpy(), hd.cpu().numpy()
+    xs = rng.choice(g.n_pixels, 300, replace=False)
+    go, ho = np.zeros(xs.size), np.zeros(xs.size)
+    for k, f in enumerate(freqs):
+        G = born.green(T[:, xs], A[:, xs].astype(np.float64), B[:, xs].astype(np.float64), f)
+        go += born.born_adjoint(G, Wd[k] * D[k], f, g.h ** 2)
+        ho += born.hessian_diag(G, Wd[k], f, g.h ** 2)
+    assert np.linalg.norm(gg[xs] - go) / np.linalg.norm(go) <= 1e-5
+    assert np.linalg.norm(hg[xs] - ho) / np.linalg.norm(ho) <= 1e-5
+
+
+def test_fullsize_forward_sampled_pairs(rb, prob):
+    g = prob.geom
+    nf = 3
+    T, A, B, _, _, _ = W.random_tables(g, seed=87)
+    freqs = list(prob.freq_sets[-1])
+    delta = W.random_delta(g.n_pixels, 88)
+    _say("full-size forward f32 (random tables)")
+    tabs = {"T": _t(T), "amp": _t(A, torch.float32), "att": _t(B, torch.float32),
+            "T_rx": _t(np.zeros((g.m, g.m))), "amp_rx": _t(np.zeros((g.m, g.m)), torch.float32),
+            "att_rx": _t(np.zeros((g.m, g.m)), torch.float32)}
+    Gr = torch.empty((nf, g.m, g.n_pixels), dtype=torch.float32, device=DEV)
+    Gi = torch.empty_like(Gr)
+    rb.build_green(g, tabs, freqs, 1.0, "f32", Gr, Gi, None)
+    d = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=DEV)
+    rb.born_forward(g, Gr, Gi, None, "f32", freqs, _t(delta), d)
+    torch.cuda.synchronize()
+    dg = d.cpu().numpy()
+    rng = np.random.default_rng(89)
+    pairs = [(int(a), int(b)) for a, b in zip(rng.integers(0, g.m, 60), rng.integers(0, g.m, 60))]
+    es = sorted({e for e, _ in pairs} | {r for _, r in pairs})
+    for k, f in enumerate(freqs):
+        G = dict(zip(es, born.green(T[es], A[es].astype(np.float64), B[es].astype(np.float64), f)))
+        om2 = (2 * math.pi * f) ** 2 * g.h ** 2
+        ref = np.array([om2 * np.sum(G[e] * G[r] * delta) for e, r in pairs])
+        got = np.array([dg[k, e, r, 0] + 1j * dg[k, e, r, 1] for e, r in pairs])
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_fullsize_one_frequency_set_end_to_end(rb, prob):
+    """The first set of the bench sweep, f32 contractions, against the oracle."""
+    g = prob.geom
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    f = prob.freq_sets[0]
+    _say("full-size invert_frequency_set f32, set 0 (oracle ~10-30 s on the host)")
+    ref = invert.invert_frequency_set(g, topts, prob.inv, prob.c_start, prob.alpha0, f, prob.p_meas[0],
+                                      return_parts=True)
+    c_in = _t(prob.c_start.reshape(-1))
+    c_out = torch.empty_like(c_in)
+    pm = _t(np.stack([prob.p_meas[0].real, prob.p_meas[0].imag], -1))
+    l2 = rb.invert_frequency_set(g, topts, prob.inv, "f32", c_in, _t(prob.alpha0.reshape(-1)), f, pm, c_out)
+    dc_g = c_out.cpu().numpy() - prob.c_start.reshape(-1)
+    dc_o = ref["c_new"].reshape(-1) - prob.c_start.reshape(-1)
+    rel = np.linalg.norm(dc_g - dc_o) / np.linalg.norm(dc_o)
+    print(f"[gpu-case] full-size set 0: rel-L2 {rel:.3e}, max|dc diff| {np.abs(dc_g - dc_o).max():.3e} m/s, "
+          f"norms {l2:.4f} vs {ref['dc_l2']:.4f}", flush=True)
+    assert rel <= 1e-3
+    assert np.abs(dc_g - dc_o).max() <= 0.1
+    assert abs(l2 - ref["dc_l2"]) <= 1e-3 * ref["dc_l2"]
