@@ -17,6 +17,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0}   # dense MFMA TFLOP/s
+# HBM traffic of the backprojection kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a copy of known size.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_k_adjoint_f32_ring256_grid480.md")
+ADJOINT_SOURCES = ["adjoint.hip", "mma.h", "born.h", "common.h"]
+COPY_BYTES = 256 << 20   # calibration copy: reads and writes this many bytes once
 METRIC = "Born backprojection Gpixel·pair·freq/s + recon latency p50/p99 vs plain"
 
 
@@ -44,6 +50,31 @@ def selection_weights(m: int, recv_fraction: float, nf: int) -> np.ndarray:
     r = np.arange(m)[None, :]
     d = np.minimum(np.abs(e - r), m - np.abs(e - r))
     return np.repeat((d >= dmin).astype(np.float64)[None], nf, axis=0)
+
+
+def adjoint_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ADJOINT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_16633_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype: str):
+    """HBM bytes per backprojection launch from the committed counter summary,
+    or None when it is missing, for another dtype, or the kernel's sources
+    have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict(line[2:].split(": ", 1) for line in f.read().splitlines() if line.startswith("- ") and ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != adjoint_source_hash() or kv.get("dtype", "").strip() != dtype:
+        return None
+    try:
+        return int(kv["hbm_bytes_per_launch"].split()[0])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -131,10 +162,20 @@ def main():
     adj_ms = ev0.elapsed_time(ev1) / args.adjoint_reps
     flops = 10.0 * N * P * nf
     achieved = flops / (adj_ms * 1e-3) / 1e12
+    esize = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
+    alg_bytes = 2 * nf * g.m * N * esize + 2 * nf * N * 8   # G (re, im) once + per-frequency partials
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[args.dtype], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK[args.dtype], 4), "traffic": None,
+                "frac": round(achieved / PEAK[args.dtype], 4), "traffic": measured_traffic(args.dtype),
                 "kernel": "k_adjoint (fused complex backprojection + Hessian diagonal)",
-                "launch_ms": round(adj_ms, 4), "algorithmic_flop_per_launch": flops}
+                "launch_ms": round(adj_ms, 4), "algorithmic_flop_per_launch": flops,
+                "algorithmic_bytes_per_launch": alg_bytes}
+
+    # ---- calibration copy for the traffic counters (outside every timed region)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
     # ---- stage times for one set (events, same stream)
     def timed(fn, reps=3):

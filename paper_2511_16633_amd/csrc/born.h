@@ -1,5 +1,5 @@
-// Born contraction kernels: parameters and host entry points shared with the
-// inversion driver.
+// Born contraction kernels (adjoint.hip, forward.hip): parameters and host
+// entry points shared with the inversion driver.
 #pragma once
 #include "common.h"
 
@@ -29,5 +29,9 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
 rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
                        rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
                        size_t ws_bytes, hipStream_t st);
+
+// Argument checks shared by the two contraction entry points.
+rb_status check_contraction(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                            rb_dtype dt, const double *freqs, int32_t nf);
 
 }  // namespace rb

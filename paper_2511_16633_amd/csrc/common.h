@@ -90,6 +90,14 @@ inline unsigned blocks_for(int64_t n, int threads) {
     return static_cast<unsigned>((n + threads - 1) / threads);
 }
 
+// Workgroups of a launch go to the eight XCDs round-robin by flat id.  This
+// bijection on [0, nblk) gives each XCD one contiguous range of logical ids,
+// so that workgroups that touch neighbouring data share one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
+    const int64_t q = nblk >> 3, r = nblk & 7, x = b & 7, s = b >> 3;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // Fill kernels are used instead of hipMemsetAsync so that a caller may
 // capture the library's work into a HIP graph.
 rb_status fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);

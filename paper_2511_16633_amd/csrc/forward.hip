@@ -1,0 +1,494 @@
+// Born forward operator (paper, Inverse Problem section, Eqs. 8-9;
+// linearisation of Eq. 1 in q = 1/c^2 with Green's functions from Eqs. 4-5).
+//
+//   d_er = omega^2 h^2 sum_x G_e(x) G_r(x) delta(x)
+//
+// A split-K complex GEMM over pixels on the matrix cores.  The output is
+// symmetric in (e, r), so only upper-triangular tiles are computed; the
+// split partials are reduced in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "born.h"
+#include "common.h"
+#include "mma.h"
+
+namespace rb {
+namespace {
+
+// ------------------------------------------------------------------ forward
+// Output tile 64x64 (e, r) with tile_e <= tile_r; wave w owns rows 16w..+15
+// and four 16-column blocks; K = pixels [ks, ks + kchunk).
+__device__ __forceinline__ void tri_tile(int t, int ntl, int &te, int &tr) {
+    // enumerate (te, tr) with te <= tr row by row
+    int a = 0;
+    while (t >= ntl - a) {
+        t -= ntl - a;
+        ++a;
+    }
+    te = a;
+    tr = a + t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_forward(FwdParams P, const T *__restrict__ Gr, const T *__restrict__ Gi,
+                                                 const double *__restrict__ delta, T *__restrict__ part) {
+    using acc_t = typename MM<T>::acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const T *gr = Gr + (int64_t)k * P.m * N;
+    const T *gi = Gi + (int64_t)k * P.m * N;
+    const int e = te * 64 + 16 * wave + row;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    acc_t re[4], im[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) re[c] = im[c] = acc_t{0, 0, 0, 0};
+    for (int64_t xc = ks; xc < ke; xc += 16) {
+        T a_r[4], a_i[4], dl[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t x = xc + 4 * kk + s;
+            const bool okx = x < ke;
+            dl[s] = okx ? (T)delta[x] : T(0);
+            a_r[s] = ld(gr + (int64_t)e * N + x, okx && e < P.m);
+            a_i[s] = ld(gi + (int64_t)e * N + x, okx && e < P.m);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int64_t x = xc + 4 * kk + s;
+                const bool ok = (x < ke) && (r < P.m);
+                const T b_r = ld(gr + (int64_t)r * N + x, ok) * dl[s];
+                const T b_i = ld(gi + (int64_t)r * N + x, ok) * dl[s];
+                re[c] = MM<T>::mma(a_r[s], b_r, re[c]);
+                re[c] = MM<T>::mma(-a_i[s], b_i, re[c]);
+                im[c] = MM<T>::mma(a_r[s], b_i, im[c]);
+                im[c] = MM<T>::mma(a_i[s], b_r, im[c]);
+            }
+        }
+    }
+    // partial tile -> part[split][k][e][r][2]
+    T *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ee = te * 64 + 16 * wave + MM<T>::out_row(kk, i);
+            const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+            pp[o] = re[c][i];
+            pp[o + 1] = im[c][i];
+        }
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_forward16(FwdParams P, const S *__restrict__ Gr, const S *__restrict__ Gi,
+                                                   const double *__restrict__ delta,
+                                                   const double *__restrict__ dmax, float *__restrict__ part) {
+    using V = typename MM16<S>::vec;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const S *gr = Gr + (int64_t)k * P.m * N;
+    const S *gi = Gi + (int64_t)k * P.m * N;
+    const int e = te * 64 + 16 * wave + row;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const double inv_d = dmax[0] > 0.0 ? 1.0 / dmax[0] : 0.0;
+    f4 re[4], im[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) re[c] = im[c] = f4{0, 0, 0, 0};
+    for (int64_t xc = ks; xc < ke; xc += 32) {
+        V a_r, a_i, a_n;
+        float dl[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t x = xc + 8 * kk + i;
+            const bool okx = x < ke;
+            dl[i] = okx ? (float)(delta[x] * inv_d) : 0.0f;
+            const bool ok = okx && e < P.m;
+            const float vr = ok ? MM16<S>::to_f(gr[(int64_t)e * N + x]) : 0.0f;
+            const float vi = ok ? MM16<S>::to_f(gi[(int64_t)e * N + x]) : 0.0f;
+            a_r[i] = MM16<S>::from_f(vr);
+            a_i[i] = MM16<S>::from_f(vi);
+            a_n[i] = MM16<S>::from_f(-vi);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = tr * 64 + 16 * c + row;
+            V b_r, b_i;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t x = xc + 8 * kk + i;
+                const bool ok = (x < ke) && (r < P.m);
+                const float vr = ok ? MM16<S>::to_f(gr[(int64_t)r * N + x]) : 0.0f;
+                const float vi = ok ? MM16<S>::to_f(gi[(int64_t)r * N + x]) : 0.0f;
+                b_r[i] = MM16<S>::from_f(vr * dl[i]);
+                b_i[i] = MM16<S>::from_f(vi * dl[i]);
+            }
+            re[c] = MM16<S>::mma(a_r, b_r, re[c]);
+            re[c] = MM16<S>::mma(a_n, b_i, re[c]);
+            im[c] = MM16<S>::mma(a_r, b_i, im[c]);
+            im[c] = MM16<S>::mma(a_i, b_r, im[c]);
+        }
+    }
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int r = tr * 64 + 16 * c + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ee = te * 64 + 16 * wave + 4 * kk + i;
+            const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+            pp[o] = re[c][i];
+            pp[o + 1] = im[c][i];
+        }
+    }
+}
+
+// d[k][e][r] = c_k * sum_split part (fixed order), read from the upper triangle.
+template <typename T>
+__global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const float *__restrict__ gscale,
+                                 const double *__restrict__ dmax, double *__restrict__ d) {
+    const int64_t mm = (int64_t)P.m * P.m;
+    const int64_t tot = mm * P.nf;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int k = (int)(idx / mm);
+    const int64_t rem = idx - (int64_t)k * mm;
+    int e = (int)(rem / P.m), r = (int)(rem - (int64_t)e * P.m);
+    // d is symmetric: both (e, r) and (r, e) take the upper-triangle element
+    if (e > r) {
+        const int t = e;
+        e = r;
+        r = t;
+    }
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < P.nsplit; ++s) {
+        const T *pp = part + ((int64_t)s * P.nf + k) * P.mp * P.mp * 2 + ((int64_t)e * P.mp + r) * 2;
+        sr += (double)pp[0];
+        si += (double)pp[1];
+    }
+    double c = P.cg[k];
+    if (gscale) {
+        const double g = (double)gscale[k];
+        c *= g * g;
+    }
+    if (dmax) c *= dmax[0];
+    d[2 * idx] = sr * c;
+    d[2 * idx + 1] = si * c;
+}
+
+__global__ void k_absmax_f64(const double *__restrict__ v, int64_t n, double *__restrict__ out) {
+    __shared__ double sh[1024];
+    double best = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) best = fmax(best, fabs(v[i]));
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Forward.  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
+// over a split of the pixels; waves are 2 x 2, each 32 e x 32 r.  Pixels are
+// consumed 32 at a time: G_e and G_r delta for the tile's rows are staged in
+// LDS as [row][32 px] (stride 36: conflict-free b128 reads), double
+// buffered; a lane reads its eight k values of a row as two b128 reads.
+constexpr int kFwdKC = 32, kFwdLD = 36;
+
+struct FwdStage {
+    f4 ar[2], ai[2], br[2], bi[2];
+};
+
+__device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, const float *__restrict__ gi,
+                                               const double *__restrict__ delta, int m, int64_t N, int e_row,
+                                               int r_row, int64_t xc, int64_t ke, bool vec, FwdStage &v) {
+    const int c8 = (threadIdx.x & 3) * 8;
+    const int64_t xs = xc + c8;
+    if (vec) {
+        double dl[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dl[q] = delta[xs + q];
+        if (e_row < m) {
+            const float *pr = gr + (int64_t)e_row * N + xs;
+            const float *pi = gi + (int64_t)e_row * N + xs;
+            v.ar[0] = *reinterpret_cast<const f4 *>(pr);
+            v.ar[1] = *reinterpret_cast<const f4 *>(pr + 4);
+            v.ai[0] = *reinterpret_cast<const f4 *>(pi);
+            v.ai[1] = *reinterpret_cast<const f4 *>(pi + 4);
+        } else {
+            v.ar[0] = v.ar[1] = v.ai[0] = v.ai[1] = f4{0, 0, 0, 0};
+        }
+        if (r_row < m) {
+            const float *pr = gr + (int64_t)r_row * N + xs;
+            const float *pi = gi + (int64_t)r_row * N + xs;
+            f4 t0 = *reinterpret_cast<const f4 *>(pr), t1 = *reinterpret_cast<const f4 *>(pr + 4);
+            f4 u0 = *reinterpret_cast<const f4 *>(pi), u1 = *reinterpret_cast<const f4 *>(pi + 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v.br[0][q] = t0[q] * (float)dl[q];
+                v.br[1][q] = t1[q] * (float)dl[q + 4];
+                v.bi[0][q] = u0[q] * (float)dl[q];
+                v.bi[1][q] = u1[q] * (float)dl[q + 4];
+            }
+        } else {
+            v.br[0] = v.br[1] = v.bi[0] = v.bi[1] = f4{0, 0, 0, 0};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t x = xs + q;
+            const bool okx = x < ke;
+            const float dl = okx ? (float)delta[x] : 0.0f;
+            const bool oka = okx && e_row < m, okb = okx && r_row < m;
+            v.ar[q >> 2][q & 3] = oka ? gr[(int64_t)e_row * N + x] : 0.0f;
+            v.ai[q >> 2][q & 3] = oka ? gi[(int64_t)e_row * N + x] : 0.0f;
+            v.br[q >> 2][q & 3] = okb ? gr[(int64_t)r_row * N + x] * dl : 0.0f;
+            v.bi[q >> 2][q & 3] = okb ? gi[(int64_t)r_row * N + x] * dl : 0.0f;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float *__restrict__ Gr,
+                                                        const float *__restrict__ Gi,
+                                                        const double *__restrict__ delta, float *__restrict__ part) {
+    __shared__ float sA[2][2][64][kFwdLD];
+    __shared__ float sBm[2][2][64][kFwdLD];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wr = wave & 1;
+    int te, tr;
+    tri_tile(blockIdx.x, P.ntl, te, tr);
+    const int split = blockIdx.y, k = blockIdx.z;
+    const int64_t N = P.N;
+    const float *gr = Gr + (int64_t)k * P.m * N;
+    const float *gi = Gi + (int64_t)k * P.m * N;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const int nch = (int)((ke - ks + kFwdKC - 1) / kFwdKC);
+    const int srow = tid >> 2, c8 = (tid & 3) * 8;
+    const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
+    // (a + ib)(c + id) with three real products: P1 = ac, P2 = bd,
+    // P3 = (a + b)(c + d); re = P1 - P2, im = P3 - P1 - P2
+    f4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = f4{0, 0, 0, 0};
+    FwdStage stg;
+    auto vec_ok = [&](int64_t xc) { return ((N & 3) == 0) && (xc + kFwdKC <= ke); };
+    auto store = [&](int buf) {
+        *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8]) = stg.ar[0];
+        *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8 + 4]) = stg.ar[1];
+        *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8]) = stg.ai[0];
+        *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8 + 4]) = stg.ai[1];
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8]) = stg.br[0];
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8 + 4]) = stg.br[1];
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8]) = stg.bi[0];
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8 + 4]) = stg.bi[1];
+    };
+    if (nch > 0) {
+        fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, ks, ke, vec_ok(ks), stg);
+        store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        const int64_t xn = ks + (int64_t)(c + 1) * kFwdKC;
+        if (c + 1 < nch) fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, xn, ke, vec_ok(xn), stg);
+        f4 a_r[2][2], a_i[2][2], b_r[2][2], b_i[2][2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ra = 32 * we + 16 * b + row;
+            a_r[b][0] = *reinterpret_cast<const f4 *>(&sA[buf][0][ra][8 * kk]);
+            a_r[b][1] = *reinterpret_cast<const f4 *>(&sA[buf][0][ra][8 * kk + 4]);
+            a_i[b][0] = *reinterpret_cast<const f4 *>(&sA[buf][1][ra][8 * kk]);
+            a_i[b][1] = *reinterpret_cast<const f4 *>(&sA[buf][1][ra][8 * kk + 4]);
+            const int rb = 32 * wr + 16 * b + row;
+            b_r[b][0] = *reinterpret_cast<const f4 *>(&sBm[buf][0][rb][8 * kk]);
+            b_r[b][1] = *reinterpret_cast<const f4 *>(&sBm[buf][0][rb][8 * kk + 4]);
+            b_i[b][0] = *reinterpret_cast<const f4 *>(&sBm[buf][1][rb][8 * kk]);
+            b_i[b][1] = *reinterpret_cast<const f4 *>(&sBm[buf][1][rb][8 * kk + 4]);
+        }
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+            float ys[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) ys[cb] = b_r[cb][s8 >> 2][s8 & 3] + b_i[cb][s8 >> 2][s8 & 3];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const float xr = a_r[b][s8 >> 2][s8 & 3], xi = a_i[b][s8 >> 2][s8 & 3];
+                const float xs = xr + xi;
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    p1[b][cb] = MM<float>::mma(xr, b_r[cb][s8 >> 2][s8 & 3], p1[b][cb]);
+                    p2[b][cb] = MM<float>::mma(xi, b_i[cb][s8 >> 2][s8 & 3], p2[b][cb]);
+                    p3[b][cb] = MM<float>::mma(xs, ys[cb], p3[b][cb]);
+                }
+            }
+        }
+        if (c + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int r = tr * 64 + 32 * wr + 16 * cb + row;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ee = te * 64 + 32 * we + 16 * b + MM<float>::out_row(kk, i);
+                const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+                pp[o] = p1[b][cb][i] - p2[b][cb][i];
+                pp[o + 1] = (p3[b][cb][i] - p1[b][cb][i]) - p2[b][cb][i];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+// Compute units of the current device (cached per device; 256 on MI355X).
+static int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, rb_dtype dt) {
+    FwdParams P;
+    P.m = g->m;
+    P.mp = (g->m + 63) / 64 * 64;
+    P.N = (int64_t)g->nx * g->ny;
+    P.nf = nf;
+    P.ntl = P.mp / 64;
+    const int ntri = P.ntl * (P.ntl + 1) / 2;
+    // about four rounds of resident workgroups (two per CU), rounded down so
+    // the last round is full
+    const int want = 4 * 2 * device_cus();
+    int nsplit = std::max(1, want / (ntri * nf));
+    const int kq = (dt == RB_BF16 || dt == RB_F16) ? 32 : 16;
+    int64_t kchunk = (P.N + nsplit - 1) / nsplit;
+    kchunk = (kchunk + kq - 1) / kq * kq;
+    if (kchunk < kq) kchunk = kq;
+    nsplit = (int)((P.N + kchunk - 1) / kchunk);
+    P.nsplit = nsplit;
+    P.kchunk = kchunk;
+    P.ntri = ntri;
+    const double dA = g->h * g->h;
+    for (int k = 0; k < nf; ++k) {
+        const double om = 2.0 * M_PI * (freqs ? freqs[k] : 1.0);
+        P.cg[k] = om * om * dA;
+    }
+    return P;
+}
+
+size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
+    FwdParams P = fwd_params(g, nullptr, nf, dt);
+    const size_t es = dt == RB_F64 ? 8 : 4;
+    return (size_t)P.nsplit * nf * P.mp * P.mp * 2 * es + 2 * 256 + 256;
+}
+
+rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (ws_bytes < forward_workspace_bytes(g, nf, dt)) {
+        set_error("forward workspace too small: need %zu bytes", forward_workspace_bytes(g, nf, dt));
+        return RB_ENOMEM;
+    }
+    FwdParams P = fwd_params(g, freqs, nf, dt);
+    Carver c(ws, ws_bytes);
+    double *dmax = c.take<double>(1);
+    const size_t es = dt == RB_F64 ? 8 : 4;
+    void *part = c.take<char>((size_t)P.nsplit * nf * P.mp * P.mp * 2 * es);
+    dim3 grid(P.ntri, P.nsplit, nf);
+    const int64_t tot = (int64_t)nf * P.m * P.m;
+    switch (dt) {
+        case RB_F64:
+            k_forward<double><<<grid, 256, 0, st>>>(P, (const double *)G_re, (const double *)G_im, delta,
+                                                    (double *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<double><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const double *)part, nullptr,
+                                                                           nullptr, d_out);
+            break;
+        case RB_F32:
+            k_forward_f32<<<grid, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, delta, (float *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, nullptr,
+                                                                          d_out);
+            break;
+        case RB_BF16:
+        case RB_F16:
+            k_absmax_f64<<<1, 1024, 0, st>>>(delta, P.N, dmax);
+            RB_LAUNCHED();
+            if (dt == RB_BF16)
+                k_forward16<__hip_bfloat16><<<grid, 256, 0, st>>>(P, (const __hip_bfloat16 *)G_re,
+                                                                  (const __hip_bfloat16 *)G_im, delta, dmax,
+                                                                  (float *)part);
+            else
+                k_forward16<__half><<<grid, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im, delta,
+                                                          dmax, (float *)part);
+            RB_LAUNCHED();
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, dmax,
+                                                                          d_out);
+            break;
+    }
+    RB_LAUNCHED();
+    return RB_OK;
+}
+
+rb_status check_contraction(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                                   rb_dtype dt, const double *freqs, int32_t nf) {
+    RB_TRY(check_geometry(g));
+    RB_TRY(check_freqs(freqs, nf));
+    RB_CHECK_ARG(dt >= RB_F64 && dt <= RB_F16, "unknown dtype %d", (int)dt);
+    RB_CHECK_ARG(G_re && G_im, "G_re/G_im are NULL");
+    RB_CHECK_ARG(!(dt == RB_BF16 || dt == RB_F16) || scale, "scale is required for 16-bit storage");
+    return RB_OK;
+}
+
+}  // namespace rb
+
+extern "C" {
+
+size_t rb_forward_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype) {
+    if (rb::check_geometry(g) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
+    return rb::forward_workspace_bytes(g, nf, dtype);
+}
+
+rb_status rb_born_forward(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                          rb_dtype dtype, const double *freqs_hz, int32_t nf, const double *delta, double *d_out,
+                          void *ws, size_t ws_bytes, void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_contraction(g, G_re, G_im, scale, dtype, freqs_hz, nf));
+    RB_CHECK_ARG(delta && d_out, "delta/d_out are NULL");
+    RB_CHECK_ARG(ws, "workspace is NULL");
+    return rb::forward_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, delta, d_out, ws, ws_bytes,
+                            rb::as_stream(stream));
+}
+
+}  // extern "C"

@@ -299,6 +299,11 @@ __device__ __forceinline__ void cell_decode(uint64_t id, int &eb, int &n, int &j
     eb = (int)(id >> 31);
 }
 
+// Launch shape of the cell passes: logical workgroups are (64-ray column
+// block, step group of 4 waves, emitter); each wave owns a list segment of
+// 64 entries per loop iteration.
+constexpr int kCellGroupsY = 8;
+
 // Pass 0: classify every live cell of the wavefront mesh.  A cell whose
 // bounding box holds a pixel centre goes to the pixel list, one whose box
 // straddles the ring to the ring list (tests conservative: each triangle's
@@ -311,9 +316,13 @@ __global__ void __launch_bounds__(256) k_cells(TP P, const double2 *__restrict__
                                                int *__restrict__ seg_px, int *__restrict__ seg_rx) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = blockIdx.x * 64 + lane;
-    const int eb = blockIdx.z;
-    const int64_t seg = (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 + wave;
+    // logical workgroup (column block, step group, emitter), x fastest
+    const int gx = (P.nr - 1 + 63) / 64;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % gx), by = (int)((lb / gx) % kCellGroupsY);
+    const int j = bx * 64 + lane;
+    const int eb = (int)(lb / ((int64_t)gx * kCellGroupsY));
+    const int64_t seg = lb * 4 + wave;
     uint64_t *lp = list_px + seg * cap;
     uint64_t *lr = list_rx + seg * cap;
     const int *Le = L + (size_t)eb * P.nr;
@@ -321,7 +330,7 @@ __global__ void __launch_bounds__(256) k_cells(TP P, const double2 *__restrict__
     const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
     const uint64_t below = (1ull << lane) - 1ull;
     int cp = 0, cr = 0;   // wave-uniform counts
-    for (int n = blockIdx.y * 4 + wave;; n += gridDim.y * 4) {
+    for (int n = by * 4 + wave;; n += kCellGroupsY * 4) {
         const bool act = n <= nlast;
         if (!__any(act)) break;
         bool pix = false, ring = false;
@@ -466,8 +475,11 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
                                float *__restrict__ att_out) {
     const int64_t npts = RX ? (int64_t)P.m : (int64_t)P.nx * P.ny;
     {
-        const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        const int eb = blockIdx.y;
+        // one flat grid over (emitter, point block), XCD-contiguous
+        const int64_t bpe = (npts + 255) / 256;
+        const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+        const int eb = (int)(wg / bpe);
+        const int64_t p = (wg - (int64_t)eb * bpe) * 256 + threadIdx.x;
         if (p >= npts) return;
         const int64_t idx = (int64_t)eb * npts + p;
         const uint64_t key = tkey[idx];
@@ -517,10 +529,6 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
     }
 }
 
-// Launch shape of the cell passes: x = 64-ray column blocks, y = step
-// groups (4 waves each), z = emitters; each wave owns a list segment of
-// 64 entries per loop iteration.
-constexpr int kCellGroupsY = 8;
 inline int cell_iters(const rb_trace_opts *t) {
     const int stride = kCellGroupsY * 4;
     return (int)((trace_nmax(t) + stride - 1) / stride);
@@ -637,7 +645,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         RB_LAUNCHED();
         const int cap = cell_seg_cap(t);
         const int nseg = (int)cell_segments(g, t, P.ne);
-        dim3 gc(blocks_for(P.nr - 1, 64), kCellGroupsY, P.ne);
+        const unsigned gc = blocks_for(P.nr - 1, 64) * kCellGroupsY * P.ne;
         k_cells<<<gc, 256, 0, st>>>(P, w.XY, w.L, cap, w.list_px, w.list_rx, w.seg_px, w.seg_rx);
         RB_LAUNCHED();
         const unsigned nbl = blocks_for(nseg, 4);
@@ -649,11 +657,11 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         RB_LAUNCHED();
         k_raster_rx<1><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, tkey_rx, w.ikey_rx);
         RB_LAUNCHED();
-        dim3 gw(blocks_for(N, 256), P.ne);
+        const unsigned gw = blocks_for(N, 256) * P.ne;
         k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey, w.ikey,
                                                   out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
         RB_LAUNCHED();
-        dim3 gr(blocks_for(g->m, 256), P.ne);
+        const unsigned gr = blocks_for(g->m, 256) * P.ne;
         k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey_rx, w.ikey_rx,
                                                  out->amp_rx + (int64_t)e0 * g->m, out->att_rx + (int64_t)e0 * g->m);
         RB_LAUNCHED();
