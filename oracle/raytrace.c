@@ -27,8 +27,11 @@
  * n, n+1 and is split into the triangles (P[n][j], P[n][j+1], P[n+1][j+1])
  * and (P[n][j], P[n+1][j+1], P[n+1][j]); a point inside a triangle takes
  * the barycentric interpolation of T, a and B; over all covering triangles
- * the smallest T (first arrival) wins, exact ties going to the first
- * triangle in (n, j, triangle) order.
+ * the first arrival wins.  Arrivals are ordered by the interpolated step
+ * index u = T / dtau = la n_a + lb n_b + lc n_c held in fixed point,
+ * u_q = floor(max(u, 0) 2^F) with F = 64 - bits(2 nmax n_rays - 1) -
+ * bits(nmax) (u_q and the triangle index then fill one 64-bit word), and
+ * equal u_q go to the first triangle in (n, j, triangle) order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -177,12 +180,27 @@ int orc_trace_fan(const orc_params *P, const double *s, const double *alpha, int
 }
 
 /* One triangle: evaluate at the candidate points inside its closed bounding
- * box; keep the smallest T per point (strict <, so earlier triangles keep
- * exact ties). */
-typedef struct { double x, y, t, a, b; } vtx;
+ * box; keep the smallest u_q per point (strict <, so earlier triangles keep
+ * ties). */
+typedef struct { double x, y, t, a, b, u; } vtx;   /* u: step index of the node */
 
-static void raster_grid(const orc_params *P, const vtx *A, const vtx *B, const vtx *C,
-                        double *T, double *Am, double *Bt)
+static int bit_length(uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; }
+
+/* Fraction bits of the fixed-point arrival order (see the file header). */
+int orc_order_bits(const orc_params *P)
+{
+    const uint64_t nidx = 2ull * (uint64_t)P->nmax * (uint64_t)P->n_rays;
+    return 64 - bit_length(nidx > 0 ? nidx - 1 : 0) - bit_length((uint64_t)P->nmax);
+}
+
+static uint64_t order_u(double u, double scale)
+{
+    if (!(u > 0.0)) return 0;
+    return (uint64_t)floor(u * scale);
+}
+
+static void raster_grid(const orc_params *P, double scale, const vtx *A, const vtx *B, const vtx *C,
+                        uint64_t *Q, double *T, double *Am, double *Bt)
 {
     double e1x = B->x - A->x, e1y = B->y - A->y;
     double e2x = C->x - A->x, e2y = C->y - A->y;
@@ -206,10 +224,11 @@ static void raster_grid(const orc_params *P, const vtx *A, const vtx *B, const v
             double lc = (e1x * qy - e1y * qx) / det;
             double la = (1.0 - lb) - lc;
             if (la < tol || lb < tol || lc < tol) continue;
-            double t = la * A->t + lb * B->t + lc * C->t;
+            uint64_t q = order_u(la * A->u + lb * B->u + lc * C->u, scale);
             size_t p = (size_t)jj * (size_t)P->nx + (size_t)ii;
-            if (t < T[p]) {
-                T[p] = t;
+            if (q < Q[p]) {
+                Q[p] = q;
+                T[p] = la * A->t + lb * B->t + lc * C->t;
                 Am[p] = la * A->a + lb * B->a + lc * C->a;
                 Bt[p] = la * A->b + lb * B->b + lc * C->b;
             }
@@ -217,9 +236,9 @@ static void raster_grid(const orc_params *P, const vtx *A, const vtx *B, const v
     }
 }
 
-static void raster_points(const orc_params *P, const vtx *A, const vtx *B, const vtx *C,
+static void raster_points(const orc_params *P, double scale, const vtx *A, const vtx *B, const vtx *C,
                           int npts, const double *px, const double *py,
-                          double *T, double *Am, double *Bt)
+                          uint64_t *Q, double *T, double *Am, double *Bt)
 {
     double e1x = B->x - A->x, e1y = B->y - A->y;
     double e2x = C->x - A->x, e2y = C->y - A->y;
@@ -241,9 +260,10 @@ static void raster_points(const orc_params *P, const vtx *A, const vtx *B, const
         double lc = (e1x * qy - e1y * qx) / det;
         double la = (1.0 - lb) - lc;
         if (la < tol || lb < tol || lc < tol) continue;
-        double t = la * A->t + lb * B->t + lc * C->t;
-        if (t < T[r]) {
-            T[r] = t;
+        uint64_t q = order_u(la * A->u + lb * B->u + lc * C->u, scale);
+        if (q < Q[r]) {
+            Q[r] = q;
+            T[r] = la * A->t + lb * B->t + lc * C->t;
             Am[r] = la * A->a + lb * B->a + lc * C->a;
             Bt[r] = la * A->b + lb * B->b + lc * C->b;
         }
@@ -267,40 +287,42 @@ int orc_tables(const orc_params *P, const double *s, const double *alpha, int e0
         double th = 2.0 * M_PI * (double)r / (double)m;
         px[r] = P->R * cos(th); py[r] = P->R * sin(th);
     }
+    const double scale = ldexp(1.0, orc_order_bits(P));
     int status = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int e = e0; e < e1; ++e) {
         size_t nn = (size_t)(P->nmax + 1) * nr;
         double *X = (double *)malloc(sizeof(double) * nn * 6);
         int32_t *L = (int32_t *)malloc(sizeof(int32_t) * nr);
-        if (!X || !L) { status = -2; free(X); free(L); continue; }
+        uint64_t *Q = (uint64_t *)malloc(sizeof(uint64_t) * (N + (size_t)m));
+        if (!X || !L || !Q) { status = -2; free(X); free(L); free(Q); continue; }
+        uint64_t *Qr = Q + N;
         double *Y = X + nn, *PX = Y + nn, *PY = PX + nn, *Bn = PY + nn, *AMP = Bn + nn;
         orc_trace_fan(P, s, alpha, e, X, Y, PX, PY, Bn, AMP, L);
         double *Te = T + (size_t)(e - e0) * N, *Ae = Am + (size_t)(e - e0) * N;
         double *Be = Bt + (size_t)(e - e0) * N;
         double *Tr = Trx + (size_t)(e - e0) * m, *Ar = Arx + (size_t)(e - e0) * m;
         double *Br = Brx + (size_t)(e - e0) * m;
-        for (size_t p = 0; p < N; ++p) { Te[p] = INFINITY; Ae[p] = 0.0; Be[p] = 0.0; }
-        for (int r = 0; r < m; ++r) { Tr[r] = INFINITY; Ar[r] = 0.0; Br[r] = 0.0; }
+        for (size_t p = 0; p < N; ++p) { Q[p] = UINT64_MAX; Te[p] = NAN; Ae[p] = 0.0; Be[p] = 0.0; }
+        for (int r = 0; r < m; ++r) { Qr[r] = UINT64_MAX; Tr[r] = NAN; Ar[r] = 0.0; Br[r] = 0.0; }
         for (int n = 0; n < P->nmax; ++n) {
             for (int j = 0; j + 1 < nr; ++j) {
                 if (n + 1 > L[j] || n + 1 > L[j + 1]) continue;
                 size_t k00 = (size_t)n * nr + j, k10 = k00 + 1;
                 size_t k01 = k00 + nr, k11 = k01 + 1;
                 double t0 = (double)n * P->dtau, t1 = (double)(n + 1) * P->dtau;
-                vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00]};
-                vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10]};
-                vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11]};
-                vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01]};
-                raster_grid(P, &p00, &p10, &p11, Te, Ae, Be);
-                raster_points(P, &p00, &p10, &p11, m, px, py, Tr, Ar, Br);
-                raster_grid(P, &p00, &p11, &p01, Te, Ae, Be);
-                raster_points(P, &p00, &p11, &p01, m, px, py, Tr, Ar, Br);
+                const double u0 = (double)n, u1 = (double)(n + 1);
+                vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00], u0};
+                vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10], u0};
+                vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11], u1};
+                vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01], u1};
+                raster_grid(P, scale, &p00, &p10, &p11, Q, Te, Ae, Be);
+                raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, Tr, Ar, Br);
+                raster_grid(P, scale, &p00, &p11, &p01, Q, Te, Ae, Be);
+                raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, Tr, Ar, Br);
             }
         }
-        for (size_t p = 0; p < N; ++p) if (isinf(Te[p])) Te[p] = NAN;
-        for (int r = 0; r < m; ++r) if (isinf(Tr[r])) Tr[r] = NAN;
-        free(X); free(L);
+        free(X); free(L); free(Q);
     }
     free(px); free(py);
     return status;

@@ -204,11 +204,13 @@ def test_bilinear_interpolation_properties():
 
 def _brute_tables(g, to, fan, pts):
     """Pure-Python first-arrival interpolation over every triangle (no
-    bounding boxes), barycentrics from a 2x2 solve."""
+    bounding boxes), barycentrics from a 2x2 solve; arrivals ordered by the
+    fixed-point step index floor(u 2^F), u = T / dtau, then triangle order."""
     L = fan["L"]
     nr = to.n_rays
     tau = fan["tau"]
-    best = [(math.inf, None, 0.0, 0.0)] * len(pts)
+    scale = 2.0 ** rays.order_bits(g, to)
+    best = [(math.inf, None, 0.0, 0.0, math.inf)] * len(pts)
     for n in range(len(tau) - 1):
         for j in range(nr - 1):
             if n + 1 > L[j] or n + 1 > L[j + 1]:
@@ -226,11 +228,13 @@ def _brute_tables(g, to, fan, pts):
                     if min(la, lb, lc) < -1e-12:
                         continue
                     lam = (la, lb, lc)
-                    t = sum(l * tau[a] for l, (a, b) in zip(lam, V))
-                    if t < best[q][0]:
+                    u = sum(l * a for l, (a, b) in zip(lam, V))
+                    uq = math.floor(max(u, 0.0) * scale)
+                    if uq < best[q][4]:
+                        t = sum(l * tau[a] for l, (a, b) in zip(lam, V))
                         am = sum(l * fan["amp"][a, b] for l, (a, b) in zip(lam, V))
                         bb = sum(l * fan["b"][a, b] for l, (a, b) in zip(lam, V))
-                        best[q] = (t, (n, j, tri), am, bb)
+                        best[q] = (t, (n, j, tri), am, bb, uq)
     return best
 
 
@@ -250,7 +254,7 @@ def test_rasterisation_brute_force_tiny_fan():
     Aall = np.concatenate([A[0], Ar[0]])
     Ball = np.concatenate([B[0], Br[0]])
     n_cov = 0
-    for q, (t, who, am, bb) in enumerate(best):
+    for q, (t, who, am, bb, _) in enumerate(best):
         if who is None:
             assert np.isnan(Tall[q])
             continue
