@@ -41,6 +41,8 @@ struct TP {
     double two_sin_full, two_sin_half;
     double ring2_lo, ring2_hi;  // (R (1 -+ 2e-9))^2: conservative ring test on squares
     int e0, ne;        // emitter batch
+    int idx_bits;      // bits of the triangle index in an arrival key
+    double qscale;     // 2^F: fixed-point scale of the step index in an arrival key
 };
 
 // Bilinear slowness s with its exact patch gradient, and bilinear alpha0.
@@ -203,11 +205,15 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
     }
 }
 
-// Order-preserving image of a double in uint64 (after turning -0 into +0).
-__device__ __forceinline__ uint64_t order_key(double t) {
-    t = t + 0.0;
-    uint64_t b = (uint64_t)__double_as_longlong(t);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+// Arrival key of a candidate: the interpolated step index u = T / dtau in
+// fixed point, floor(max(u, 0) 2^F), above the triangle index
+// idx = 2 (n nr + j) + tri.  The minimum key is the first arrival, equal
+// fixed-point values going to the first triangle in (n, j, tri) order.
+// ~0 marks an uncovered point (no key reaches it: the fixed-point part
+// stays below 2^(64 - idx_bits) - 2^F).
+__device__ __forceinline__ uint64_t arrival_key(const TP &P, double u, uint32_t idx) {
+    const uint64_t q = u > 0.0 ? (uint64_t)floor(u * P.qscale) : 0ull;
+    return (q << P.idx_bits) | (uint64_t)idx;
 }
 
 struct Tri {
@@ -248,6 +254,26 @@ __device__ __forceinline__ void tri_nodes(int64_t base, int n, int j, int nr, in
     } else {
         ka = k00; kb = k11; kc = k01; na = n; nb = n + 1; nc = n + 1;
     }
+}
+
+// Pixel-centre index range of the bounding box of triangle (a, b, c),
+// clamped to the grid; false when the box holds no pixel centre.
+__device__ __forceinline__ bool px_range(const TP &P, const double2 &pa, const double2 &pb, const double2 &pc,
+                                         int &ilo, int &ihi, int &jlo, int &jhi) {
+    const double xmin = fmin(pa.x, fmin(pb.x, pc.x)), xmax = fmax(pa.x, fmax(pb.x, pc.x));
+    const double ymin = fmin(pa.y, fmin(pb.y, pc.y)), ymax = fmax(pa.y, fmax(pb.y, pc.y));
+    double flo = ceil((xmin - P.x0) * P.inv_h), fhi = floor((xmax - P.x0) * P.inv_h);
+    double glo = ceil((ymin - P.y0) * P.inv_h), ghi = floor((ymax - P.y0) * P.inv_h);
+    if (flo < 0.0) flo = 0.0;
+    if (glo < 0.0) glo = 0.0;
+    if (fhi > (double)(P.nx - 1)) fhi = (double)(P.nx - 1);
+    if (ghi > (double)(P.ny - 1)) ghi = (double)(P.ny - 1);
+    if (!(flo <= fhi && glo <= ghi)) return false;
+    ilo = (int)flo;
+    ihi = (int)fhi;
+    jlo = (int)glo;
+    jhi = (int)ghi;
+    return true;
 }
 
 // Receivers that may lie in a triangle's bounding box: a conservative index
@@ -363,14 +389,13 @@ __global__ void __launch_bounds__(256) k_cells(TP P, const double2 *__restrict__
     }
 }
 
-// Pass 1 (MODE 0): atomicMin of the T key.  Pass 2 (MODE 1): atomicMin of
-// the triangle index among candidates whose key equals the minimum.  Each
-// wave walks one list segment.  Per triangle, the candidate pixel range
-// comes first and the determinant only when the range is not empty.
-template <int MODE>
+// Pixel pass: every candidate (triangle, pixel) pair takes the atomic
+// minimum of its arrival key.  Each wave walks one list segment.  Per
+// triangle, the candidate pixel range comes first and the determinant only
+// when the range is not empty.
 __global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restrict__ XY, int nseg, int cap,
                                                    const uint64_t *__restrict__ list, const int *__restrict__ segn,
-                                                   uint64_t *__restrict__ tkey, uint64_t *__restrict__ ikey) {
+                                                   uint64_t *__restrict__ akey) {
     const int64_t N = (int64_t)P.nx * P.ny;
     const double tol = -P.bary_tol;
     const int lane = threadIdx.x & 63;
@@ -381,50 +406,34 @@ __global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restri
         int eb, n, j;
         cell_decode(list[seg * cap + i], eb, n, j);
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
-        uint64_t *tk = tkey + eb * N;
-        uint64_t *ik = ikey + eb * N;
+        uint64_t *ak = akey + eb * N;
         for (int tri = 0; tri < 2; ++tri) {
             int64_t ka, kb, kc;
             int na, nb, nc;
             tri_nodes(base, n, j, P.nr, tri, ka, kb, kc, na, nb, nc);
             const double2 pa = XY[ka], pb = XY[kb], pc = XY[kc];
-            const double xmin = fmin(pa.x, fmin(pb.x, pc.x)), xmax = fmax(pa.x, fmax(pb.x, pc.x));
-            const double ymin = fmin(pa.y, fmin(pb.y, pc.y)), ymax = fmax(pa.y, fmax(pb.y, pc.y));
-            double ilo = ceil((xmin - P.x0) * P.inv_h), ihi = floor((xmax - P.x0) * P.inv_h);
-            double jlo = ceil((ymin - P.y0) * P.inv_h), jhi = floor((ymax - P.y0) * P.inv_h);
-            if (ilo < 0.0) ilo = 0.0;
-            if (jlo < 0.0) jlo = 0.0;
-            if (ihi > (double)(P.nx - 1)) ihi = (double)(P.nx - 1);
-            if (jhi > (double)(P.ny - 1)) jhi = (double)(P.ny - 1);
-            if (!(ilo <= ihi && jlo <= jhi)) continue;
+            int ilo, ihi, jlo, jhi;
+            if (!px_range(P, pa, pb, pc, ilo, ihi, jlo, jhi)) continue;
             Tri t;
             if (!make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t)) continue;
-            const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
-            const uint64_t my = ((((uint64_t)n * P.nr) + j) << 1) | (uint64_t)tri;
-            for (long jj = (long)jlo; jj <= (long)jhi; ++jj) {
-                for (long ii = (long)ilo; ii <= (long)ihi; ++ii) {
+            const double ua = (double)na, ub = (double)nb, uc = (double)nc;
+            const uint32_t idx = ((uint32_t)n * (uint32_t)P.nr + (uint32_t)j) << 1 | (uint32_t)tri;
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                for (int ii = ilo; ii <= ihi; ++ii) {
                     double la, lb, lc;
                     if (!bary(t, P.x0 + (double)ii * P.h, P.y0 + (double)jj * P.h, tol, la, lb, lc)) continue;
-                    const double tv = la * ta + lb * tb + lc * tc;
-                    const uint64_t key = order_key(tv);
-                    const int64_t p = (int64_t)jj * P.nx + ii;
-                    if (MODE == 0) {
-                        atomicMin((unsigned long long *)&tk[p], (unsigned long long)key);
-                    } else if (key == tk[p]) {
-                        atomicMin((unsigned long long *)&ik[p], (unsigned long long)my);
-                    }
+                    const uint64_t key = arrival_key(P, la * ua + lb * ub + lc * uc, idx);
+                    atomicMin((unsigned long long *)&ak[(int64_t)jj * P.nx + ii], (unsigned long long)key);
                 }
             }
         }
     }
 }
 
-// The same two passes over the ring list, for the ring elements.
-template <int MODE>
+// The same pass over the ring list, for the ring elements.
 __global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restrict__ XY, int nseg, int cap,
                                                    const uint64_t *__restrict__ list, const int *__restrict__ segn,
-                                                   const double2 *__restrict__ rxy, uint64_t *__restrict__ tkey_rx,
-                                                   uint64_t *__restrict__ ikey_rx) {
+                                                   const double2 *__restrict__ rxy, uint64_t *__restrict__ akey_rx) {
     const double tol = -P.bary_tol;
     const int lane = threadIdx.x & 63;
     const int64_t seg = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -434,8 +443,7 @@ __global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restri
         int eb, n, j;
         cell_decode(list[seg * cap + i], eb, n, j);
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
-        uint64_t *tkr = tkey_rx + (int64_t)eb * P.m;
-        uint64_t *ikr = ikey_rx + (int64_t)eb * P.m;
+        uint64_t *akr = akey_rx + (int64_t)eb * P.m;
         for (int tri = 0; tri < 2; ++tri) {
             int64_t ka, kb, kc;
             int na, nb, nc;
@@ -445,34 +453,29 @@ __global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restri
             if (!make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t)) continue;
             int rlo, rhi;
             if (!rx_range(P, t, rlo, rhi)) continue;
-            const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
-            const uint64_t my = ((((uint64_t)n * P.nr) + j) << 1) | (uint64_t)tri;
+            const double ua = (double)na, ub = (double)nb, uc = (double)nc;
+            const uint32_t idx = ((uint32_t)n * (uint32_t)P.nr + (uint32_t)j) << 1 | (uint32_t)tri;
             for (int rr = rlo; rr <= rhi; ++rr) {
                 const int r = ((rr % P.m) + P.m) % P.m;
                 const double2 q = rxy[r];
                 if (q.x < t.xmin || q.x > t.xmax || q.y < t.ymin || q.y > t.ymax) continue;
                 double la, lb, lc;
                 if (!bary(t, q.x, q.y, tol, la, lb, lc)) continue;
-                const double tv = la * ta + lb * tb + lc * tc;
-                const uint64_t key = order_key(tv);
-                if (MODE == 0) {
-                    atomicMin((unsigned long long *)&tkr[r], (unsigned long long)key);
-                } else if (key == tkr[r]) {
-                    atomicMin((unsigned long long *)&ikr[r], (unsigned long long)my);
-                }
+                const uint64_t key = arrival_key(P, la * ua + lb * ub + lc * uc, idx);
+                atomicMin((unsigned long long *)&akr[r], (unsigned long long)key);
             }
         }
     }
 }
 
-// Pass 3: every point recomputes its winning triangle's interpolation and
-// writes T (in place of the key), a and B.  Points are pixels (RX = false)
-// or ring elements (RX = true).
+// Write pass: every point recomputes its first arrival's interpolation
+// (the triangle index is the low part of its key) and writes T in place of
+// the key, a and B.  Points are pixels (RX = false) or ring elements
+// (RX = true).
 template <bool RX>
 __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const double2 *__restrict__ AB,
-                               const double2 *__restrict__ rxy, uint64_t *__restrict__ tkey,
-                               const uint64_t *__restrict__ ikey, float *__restrict__ amp_out,
-                               float *__restrict__ att_out) {
+                               const double2 *__restrict__ rxy, uint64_t *__restrict__ akey,
+                               float *__restrict__ amp_out, float *__restrict__ att_out) {
     const int64_t npts = RX ? (int64_t)P.m : (int64_t)P.nx * P.ny;
     {
         // one flat grid over (emitter, point block), XCD-contiguous
@@ -482,26 +485,25 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
         const int64_t p = (wg - (int64_t)eb * bpe) * 256 + threadIdx.x;
         if (p >= npts) return;
         const int64_t idx = (int64_t)eb * npts + p;
-        const uint64_t key = tkey[idx];
-        double *Tout = reinterpret_cast<double *>(tkey);
+        const uint64_t key = akey[idx];
+        double *Tout = reinterpret_cast<double *>(akey);
         if (key == ~0ull) {
             Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
             amp_out[idx] = 0.0f;
             att_out[idx] = 0.0f;
             return;
         }
-        const uint64_t w = ikey[idx];
-        const int tri = (int)(w & 1ull);
-        const int64_t cell = (int64_t)(w >> 1);
-        const int64_t n64 = cell / P.nr;
-        const int j = (int)(cell - n64 * P.nr);
-        if (w == ~0ull || n64 >= P.nmax || j >= P.nr - 1) {  // no winner recorded: uncovered
+        const uint32_t w = (uint32_t)(key & ((1ull << P.idx_bits) - 1ull));
+        const int tri = (int)(w & 1u);
+        const uint32_t cell = w >> 1;
+        const int n = (int)(cell / (uint32_t)P.nr);
+        const int j = (int)(cell - (uint32_t)n * (uint32_t)P.nr);
+        if (n >= P.nmax || j >= P.nr - 1) {  // cannot occur for a key written by the pixel pass
             Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
             amp_out[idx] = 0.0f;
             att_out[idx] = 0.0f;
             return;
         }
-        const int n = (int)n64;
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
         int64_t ka, kb, kc;
         int na, nb, nc;
@@ -543,7 +545,6 @@ struct TraceWs {
     double2 *sa, *rxy;
     double2 *XY, *AB;   // node position (x, y) and (amplitude factor, absorption)
     int *L;
-    uint64_t *ikey, *ikey_rx;
     uint64_t *list_px, *list_rx;  // candidate cells (pixel / ring), one segment per wave
     int *seg_px, *seg_rx;         // segment lengths
 };
@@ -552,8 +553,7 @@ size_t per_emitter_bytes(const rb_geometry *g, const rb_trace_opts *t) {
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays;
     const size_t segs = cell_segments(g, t, 1);
     return nodes * 2 * sizeof(double2) + (size_t)t->n_rays * sizeof(int) +
-           (size_t)g->nx * g->ny * sizeof(uint64_t) + (size_t)g->m * sizeof(uint64_t) +
-           2 * segs * (cell_seg_cap(t) * sizeof(uint64_t) + sizeof(int)) + 12 * 256;
+           2 * segs * (cell_seg_cap(t) * sizeof(uint64_t) + sizeof(int)) + 10 * 256;
 }
 
 TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int batch) {
@@ -565,8 +565,6 @@ TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int
     w.XY = c.take<double2>(nodes);
     w.AB = c.take<double2>(nodes);
     w.L = c.take<int>((size_t)t->n_rays * batch);
-    w.ikey = c.take<uint64_t>(N * batch);
-    w.ikey_rx = c.take<uint64_t>((size_t)g->m * batch);
     const size_t segs = cell_segments(g, t, batch);
     w.list_px = c.take<uint64_t>(segs * cell_seg_cap(t));
     w.list_rx = c.take<uint64_t>(segs * cell_seg_cap(t));
@@ -599,7 +597,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         return RB_ENOMEM;
     }
     // largest batch whose carve fits (estimate from above, then step down)
-    int batch = (int)std::min<size_t>((size_t)g->m, 2 + (ws_bytes - one) / (per_emitter_bytes(g, t) - 12 * 256));
+    int batch = (int)std::min<size_t>((size_t)g->m, 2 + (ws_bytes - one) / (per_emitter_bytes(g, t) - 10 * 256));
     while (batch > 1) {
         Carver c2(nullptr, 0);
         carve_trace(c2, g, t, batch);
@@ -624,6 +622,13 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     P.two_sin_half = 2.0 * std::sin(0.5 * dpsi);
     P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
     P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
+    {
+        // arrival keys: triangle index in the low bits, fixed-point step index above
+        auto bit_length = [](uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; };
+        const uint64_t nidx = 2ull * (uint64_t)P.nmax * (uint64_t)P.nr;
+        P.idx_bits = bit_length(nidx - 1);
+        P.qscale = std::ldexp(1.0, 64 - P.idx_bits - bit_length((uint64_t)P.nmax));
+    }
 
     const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
     k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, 1.0 / g->c_background, slowness, alpha0, w.sa);
@@ -633,12 +638,11 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     for (int e0 = 0; e0 < g->m; e0 += batch) {
         P.e0 = e0;
         P.ne = std::min(batch, g->m - e0);
-        uint64_t *tkey = reinterpret_cast<uint64_t *>(out->T + (int64_t)e0 * N);
-        uint64_t *tkey_rx = reinterpret_cast<uint64_t *>(out->T_rx + (int64_t)e0 * g->m);
-        RB_TRY(fill_u64(tkey, ~0ull, (int64_t)P.ne * N, st));
-        RB_TRY(fill_u64(w.ikey, ~0ull, (int64_t)P.ne * N, st));
-        RB_TRY(fill_u64(tkey_rx, ~0ull, (int64_t)P.ne * g->m, st));
-        RB_TRY(fill_u64(w.ikey_rx, ~0ull, (int64_t)P.ne * g->m, st));
+        // the T tables hold the arrival keys until the write pass
+        uint64_t *akey = reinterpret_cast<uint64_t *>(out->T + (int64_t)e0 * N);
+        uint64_t *akey_rx = reinterpret_cast<uint64_t *>(out->T_rx + (int64_t)e0 * g->m);
+        RB_TRY(fill_u64(akey, ~0ull, (int64_t)P.ne * N, st));
+        RB_TRY(fill_u64(akey_rx, ~0ull, (int64_t)P.ne * g->m, st));
         const int waves = (P.nr + kOwn - 1) / kOwn;
         dim3 gt((waves + 3) / 4, P.ne);
         k_trace<<<gt, 256, 0, st>>>(P, w.sa, w.XY, w.AB, w.L);
@@ -649,21 +653,15 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         k_cells<<<gc, 256, 0, st>>>(P, w.XY, w.L, cap, w.list_px, w.list_rx, w.seg_px, w.seg_rx);
         RB_LAUNCHED();
         const unsigned nbl = blocks_for(nseg, 4);
-        k_raster_px<0><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, tkey, w.ikey);
+        k_raster_px<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, akey);
         RB_LAUNCHED();
-        k_raster_rx<0><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, tkey_rx, w.ikey_rx);
-        RB_LAUNCHED();
-        k_raster_px<1><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, tkey, w.ikey);
-        RB_LAUNCHED();
-        k_raster_rx<1><<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, tkey_rx, w.ikey_rx);
+        k_raster_rx<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, akey_rx);
         RB_LAUNCHED();
         const unsigned gw = blocks_for(N, 256) * P.ne;
-        k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey, w.ikey,
-                                                  out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
+        k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
         RB_LAUNCHED();
         const unsigned gr = blocks_for(g->m, 256) * P.ne;
-        k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, tkey_rx, w.ikey_rx,
-                                                 out->amp_rx + (int64_t)e0 * g->m, out->att_rx + (int64_t)e0 * g->m);
+        k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey_rx, out->amp_rx + (int64_t)e0 * g->m, out->att_rx + (int64_t)e0 * g->m);
         RB_LAUNCHED();
     }
     return RB_OK;
