@@ -365,6 +365,10 @@ __global__ void k_block_flags(int m, int nb, int nf, const double *__restrict__ 
 // is stored k-permuted, so a lane's eight A values of a chunk are two float4
 // loads (served from L2: A is shared by every workgroup).
 constexpr int kAdjNT = 64, kAdjKC = 32, kAdjLD = 80;
+// The tiles of the chunk's own 64 emitters are also kept for the epilogue,
+// [e][px] with a row stride of 68 floats: the four lane groups read rows
+// 4 apart, which then fall 16 banks apart.
+constexpr int kAdjLE = 68;
 
 __device__ __forceinline__ void adj_stage_load(const float *__restrict__ gr, const float *__restrict__ gi, int m,
                                                int64_t N, int rc, int64_t x0, bool vec, f4 (&v)[4]) {
@@ -393,6 +397,16 @@ __device__ __forceinline__ void adj_stage_load(const float *__restrict__ gr, con
             v[3][q] = okb ? gi[(int64_t)r * N + xb] : 0.0f;
         }
     }
+}
+
+// Epilogue copy of a staged tile whose receivers are emitters ec .. ec + 63.
+__device__ __forceinline__ void adj_stage_keep(float (*sE)[64][kAdjLE], int row0, const f4 (&v)[4]) {
+    const int t = threadIdx.x;
+    const int rr = row0 + (t >> 3), c4 = (t & 7) * 4;
+    *reinterpret_cast<f4 *>(&sE[0][rr][c4]) = v[0];
+    *reinterpret_cast<f4 *>(&sE[0][rr][c4 + 32]) = v[1];
+    *reinterpret_cast<f4 *>(&sE[1][rr][c4]) = v[2];
+    *reinterpret_cast<f4 *>(&sE[1][rr][c4 + 32]) = v[3];
 }
 
 __device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], const f4 (&v)[4]) {
@@ -457,6 +471,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                                                         const uint8_t *__restrict__ flags, double *__restrict__ pg,
                                                         double *__restrict__ ph) {
     __shared__ float sB[2][2][kAdjKC][kAdjLD];
+    __shared__ float sE[2][64][kAdjLE];
     __shared__ double sred[2][2][kAdjNT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
@@ -512,6 +527,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
             bool on = chunk_on(0);
             if (on) load_a(0, va, vi, vw);
             adj_stage_store(sB[0], stg);
+            if (ec == 0) adj_stage_keep(sE, 0, stg);
             __syncthreads();
             for (int c = 0; c < nch; ++c) {
                 const int rc = c * kAdjKC, buf = c & 1;
@@ -527,7 +543,11 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                     // may be computed along with the other one
                     adj_mma_steps<2>(va, vi, vw, sB[buf][0], sB[buf][1], kk, 32 * wp + row, p1, p2, p3, z, 0);
                 }
-                if (c + 1 < nch) adj_stage_store(sB[buf ^ 1], stg);
+                if (c + 1 < nch) {
+                    adj_stage_store(sB[buf ^ 1], stg);
+                    const int rn = rc + kAdjKC - ec;   // wave-uniform
+                    if (rn >= 0 && rn < 64) adj_stage_keep(sE, rn, stg);
+                }
                 __syncthreads();
                 on = on_n;
                 if (on) {
@@ -541,18 +561,20 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                         }
                 }
             }
-            // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e
+            // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e, with
+            // G_e from the LDS copy (zero beyond the grid; rows e >= m may be
+            // stale when m is not a multiple of 64, hence the test)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int e = ec + 32 * we + 16 * b + MM<float>::out_row(kk, i);
+                    const int el = 32 * we + 16 * b + MM<float>::out_row(kk, i);
+                    const bool ok = ec + el < P.m;
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
-                        const int64_t x = x0 + 32 * wp + 16 * cb + row;
-                        const bool ok = (e < P.m) && (x < N);
-                        const float ge_r = ok ? gr[(int64_t)e * N + x] : 0.0f;
-                        const float ge_i = ok ? gi[(int64_t)e * N + x] : 0.0f;
+                        const int pl = 32 * wp + 16 * cb + row;
+                        const float ge_r = ok ? sE[0][el][pl] : 0.0f;
+                        const float ge_i = ok ? sE[1][el][pl] : 0.0f;
                         const float yr = p1[b][cb][i] + p2[b][cb][i];
                         const float yi = (p3[b][cb][i] - p1[b][cb][i]) + p2[b][cb][i];
                         gp[cb] += ge_r * yr + ge_i * yi;
