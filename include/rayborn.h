@@ -112,8 +112,10 @@ typedef struct {
  * fan edges), giving a = sqrt(c(x) / (8 pi max(J, j_min))).  Each cell of
  * the wavefront mesh is split into two triangles; pixel centres and ring
  * elements inside a triangle (barycentrics >= -1e-12) take the barycentric
- * T, a, B; the smallest T wins (first arrival), exact ties going to the
- * triangle first in (step, ray, triangle) order.
+ * T, a, B of the first arrival: the candidate with the smallest
+ * floor(max(u, 0) 2^F), u = T / dtau the interpolated step index and
+ * F = 64 - bits(2 nmax n_rays - 1) - bits(nmax), ties going to the triangle
+ * first in (step, ray, triangle) order.
  *
  * slowness: [N] FP64 s = 1/c.  alpha0: [N] FP64 or NULL (no absorption).
  * out: all six table pointers required.  ws: rb_trace_workspace_bytes().
@@ -173,6 +175,27 @@ rb_status rb_born_adjoint_weighted(const rb_geometry *g, const void *G_re, const
                                    int32_t nf, const double *d_res, const double *w_data,
                                    double *grad, double *hdiag, void *ws, size_t ws_bytes,
                                    void *stream);
+
+/*
+ * Hessian diagonal of Eq. 10 for the data weights the single step uses
+ * (Results: receivers on the opposite part of the ring, the largest values
+ * of a frequency set zeroed):
+ *     W_er = 1 if d(e, r) >= dmin and (e, r) is not zeroed, else 0,
+ *     d(e, r) = min(|e - r|, m - |e - r|),
+ *     hdiag(x) += sum_k omega_k^4 h^4 sum_{e,r} W_er |G_e|^2 |G_r|^2,
+ * equal to rb_born_adjoint_weighted's hdiag for that W, in O(m) per pixel
+ * and frequency (circular band sums) instead of O(m^2).  zeroed: device
+ * [nf][zcap] pairs (e, r) of int32, each a selected pair (d(e, r) >= dmin)
+ * listed at most once, indices in [0, m) (others are ignored); nzero:
+ * device [nf] counts (entries beyond zcap are ignored); zcap = 0 means no
+ * zeroed pairs (zeroed and nzero may then be NULL).  hdiag: [N] FP64,
+ * accumulated into.  G and scale as for rb_born_adjoint_weighted.
+ * Deterministic.  No workspace (m <= 4096 always fits).
+ */
+rb_status rb_born_hessian_banded(const rb_geometry *g, const void *G_re, const void *G_im,
+                                 const float *scale, rb_dtype dtype, const double *freqs_hz,
+                                 int32_t nf, int32_t dmin, const int32_t *zeroed,
+                                 const int32_t *nzero, int32_t zcap, double *hdiag, void *stream);
 
 /*
  * One linearised frequency set, Hessian-free single step (Inverse Problem

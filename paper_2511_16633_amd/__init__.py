@@ -24,6 +24,7 @@ from ._binding import (  # noqa: F401
     build_green,
     born_forward,
     born_adjoint_weighted,
+    born_hessian_banded,
     invert_frequency_set,
     version,
 )

@@ -229,6 +229,17 @@ def born_adjoint_weighted(g, G_re, G_im, scale, dtype, freqs, d_res: torch.Tenso
                                           _ptr(hdiag), _ptr(ws), ws.numel(), _stream(stream)))
 
 
+def born_hessian_banded(g, G_re, G_im, scale, dtype, freqs, dmin: int, zeroed: Optional[torch.Tensor],
+                        nzero: Optional[torch.Tensor], hdiag: torch.Tensor, stream=None):
+    """hdiag += Hessian diagonal for weights W_er = [d(e,r) >= dmin] minus the
+    zeroed pairs; zeroed: int32 [nf][zcap][2] (e, r), nzero: int32 [nf]."""
+    fa, nf = _freqs(freqs)
+    zcap = 0 if zeroed is None else int(zeroed.shape[1])
+    _check(lib().rb_born_hessian_banded(ctypes.byref(geometry_struct(g)), _ptr(G_re), _ptr(G_im), _ptr(scale),
+                                        _dt(dtype), fa, nf, int(dmin), _ptr(zeroed), _ptr(nzero), zcap,
+                                        _ptr(hdiag), _stream(stream)))
+
+
 def invert_frequency_set(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[torch.Tensor], freqs,
                          p_meas: torch.Tensor, c_out: torch.Tensor, ws: Optional[torch.Tensor] = None,
                          stream=None) -> float:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librayborn.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["common.hip", "trace.hip", "green.hip", "adjoint.hip", "forward.hip", "invert.hip"]
+SOURCES = ["common.hip", "trace.hip", "green.hip", "adjoint.hip", "forward.hip", "hessian.hip", "invert.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

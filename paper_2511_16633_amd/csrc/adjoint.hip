@@ -421,9 +421,9 @@ __device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], con
 // NB row blocks starting at b0.  The complex product Y = A conj(G) uses
 // three real products, P1 = Ar Gr, P2 = Ai Gi, P3 = (Ar + Ai)(Gr - Gi)
 // (Ar + Ai formed in registers), so Yr = P1 + P2 and Yi = P3 - P1 + P2; with
-// the Hessian term Z = W |G|^2 that is four MFMAs per block and step, each
-// on a different accumulator.
-template <int NB>
+// the Hessian term Z = W |G|^2 (HESS) that is four MFMAs per block and step,
+// each on a different accumulator.
+template <int NB, bool HESS>
 __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&vi)[2][2], const f4 (&vw)[2][2],
                                               float (*sBr)[kAdjLD], float (*sBi)[kAdjLD],
                                               int kk, int xc0, f4 (&p1)[2][2], f4 (&p2)[2][2], f4 (&p3)[2][2],
@@ -445,26 +445,28 @@ __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&v
         float b2[2], bd[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-            b2[cb] = br[q4][cb] * br[q4][cb] + bi[q4][cb] * bi[q4][cb];
+            if (HESS) b2[cb] = br[q4][cb] * br[q4][cb] + bi[q4][cb] * bi[q4][cb];
             bd[cb] = br[q4][cb] - bi[q4][cb];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int b = b0 + q;
             const float a_r = va[b][s8 >> 2][s8 & 3], a_i = vi[b][s8 >> 2][s8 & 3];
-            const float a_s = a_r + a_i, a_w = vw[b][s8 >> 2][s8 & 3];
+            const float a_s = a_r + a_i;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 p1[b][cb] = MM<float>::mma(a_r, br[q4][cb], p1[b][cb]);
                 p2[b][cb] = MM<float>::mma(a_i, bi[q4][cb], p2[b][cb]);
                 p3[b][cb] = MM<float>::mma(a_s, bd[cb], p3[b][cb]);
-                z[b][cb] = MM<float>::mma(a_w, b2[cb], z[b][cb]);
+                if (HESS) z[b][cb] = MM<float>::mma(vw[b][s8 >> 2][s8 & 3], b2[cb], z[b][cb]);
             }
         }
     }
     }
 }
 
+// HESS = false computes the gradient only (three MFMAs per block and step).
+template <bool HESS>
 __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
                                                         const float *__restrict__ Gi, const float *__restrict__ Ar,
                                                         const float *__restrict__ Ai, const float *__restrict__ Wt,
@@ -517,8 +519,10 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                     va[b][1] = *reinterpret_cast<const f4 *>(ar + off + 4);
                     vi[b][0] = *reinterpret_cast<const f4 *>(ai + off);
                     vi[b][1] = *reinterpret_cast<const f4 *>(ai + off + 4);
-                    vw[b][0] = *reinterpret_cast<const f4 *>(wt + off);
-                    vw[b][1] = *reinterpret_cast<const f4 *>(wt + off + 4);
+                    if (HESS) {
+                        vw[b][0] = *reinterpret_cast<const f4 *>(wt + off);
+                        vw[b][1] = *reinterpret_cast<const f4 *>(wt + off + 4);
+                    }
                 }
             };
             f4 stg[4];
@@ -541,7 +545,8 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                 if (on) {
                     // a block that is off holds exact zeros in A and W, so it
                     // may be computed along with the other one
-                    adj_mma_steps<2>(va, vi, vw, sB[buf][0], sB[buf][1], kk, 32 * wp + row, p1, p2, p3, z, 0);
+                    adj_mma_steps<2, HESS>(va, vi, vw, sB[buf][0], sB[buf][1], kk, 32 * wp + row, p1, p2, p3, z,
+                                           0);
                 }
                 if (c + 1 < nch) {
                     adj_stage_store(sB[buf ^ 1], stg);
@@ -578,7 +583,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                         const float yr = p1[b][cb][i] + p2[b][cb][i];
                         const float yi = (p3[b][cb][i] - p1[b][cb][i]) + p2[b][cb][i];
                         gp[cb] += ge_r * yr + ge_i * yi;
-                        hp[cb] += (ge_r * ge_r + ge_i * ge_i) * z[b][cb][i];
+                        if (HESS) hp[cb] += (ge_r * ge_r + ge_i * ge_i) * z[b][cb][i];
                     }
                 }
             }
@@ -620,7 +625,7 @@ __global__ void k_adj_sum(int64_t N, int nf, const double *__restrict__ pg, cons
     double g = 0.0, h = 0.0;
     for (int k = 0; k < nf; ++k) {
         g += pg[(int64_t)k * N + x];
-        h += ph[(int64_t)k * N + x];
+        if (hd) h += ph[(int64_t)k * N + x];
     }
     grad[x] += g;
     if (hd) hd[x] += h;
@@ -727,9 +732,14 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
         }
         case RB_F32: {
             dim3 ga(blocks_for(P.N, kAdjNT), nf);
-            k_adjoint_f32<<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, (const float *)w.Ar,
-                                              (const float *)w.Ai, (const float *)w.Wt, w.flags,
-                                              w.pg, w.ph);
+            if (hdiag)
+                k_adjoint_f32<true><<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
+                                                        (const float *)w.Ar, (const float *)w.Ai,
+                                                        (const float *)w.Wt, w.flags, w.pg, w.ph);
+            else
+                k_adjoint_f32<false><<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
+                                                         (const float *)w.Ar, (const float *)w.Ai,
+                                                         (const float *)w.Wt, w.flags, w.pg, w.ph);
             RB_LAUNCHED();
             k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
             break;

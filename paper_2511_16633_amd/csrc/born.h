@@ -1,4 +1,4 @@
-// Born contraction kernels (adjoint.hip, forward.hip): parameters and host
+// Born contraction kernels (adjoint.hip, forward.hip, hessian.hip): parameters and host
 // entry points shared with the inversion driver.
 #pragma once
 #include "common.h"
@@ -30,7 +30,13 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
                        rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
                        size_t ws_bytes, hipStream_t st);
 
-// Argument checks shared by the two contraction entry points.
+// hdiag += Hessian diagonal for band-selection weights with zeroed pairs
+// (see rb_born_hessian_banded); zeroed: [nf][zcap] (e, r), nzero: [nf].
+rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                            rb_dtype dt, const double *freqs, int nf, int dmin, const int *zeroed,
+                            const int *nzero, int zcap, double *hdiag, hipStream_t st);
+
+// Argument checks shared by the contraction entry points.
 rb_status check_contraction(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
                             rb_dtype dt, const double *freqs, int32_t nf);
 

@@ -1,0 +1,225 @@
+// Diagonal of the Gauss-Newton Hessian (paper, Inverse Problem section,
+// Eq. 10; the single-step paragraph's weights) for data weights of the form
+// the inversion uses: receiver selection by circular distance (Results:
+// the opposite part of the ring) with some selected pairs zeroed (Results:
+// the largest values of a frequency set set to zero),
+//     W_er = [d(e, r) >= dmin] - [(e, r) zeroed],
+//     hd(x) = sum_k omega_k^4 h^4 sum_e g_e(x) sum_r W_er g_r(x),  g = |G|^2.
+// With S = sum_r g_r and B_e = sum_{d(e,r) < dmin} g_r (the band the
+// selection removes), sum_r W_er g_r = S - B_e - sum_{r zeroed for e} g_r,
+// so a pixel costs O(m + zeroed pairs) instead of the O(m^2) of a dense W:
+// B_e is a circular window sum that slides by one receiver per emitter.
+#include <algorithm>
+#include <cmath>
+
+#include "born.h"
+#include "common.h"
+
+namespace rb {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <>
+__device__ __forceinline__ double to_d<__hip_bfloat16>(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+template <>
+__device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
+
+constexpr int kHbThreads = 256;
+
+struct HbParams {
+    int m, nf, pb, dmin, zcap;
+    int64_t N;
+    double ch[RB_MAX_NF];   // omega^4 h^4
+};
+
+// A block holds PB pixels; its 256 threads form 256 / PB groups per pixel.
+// g for the block's pixels is staged in LDS as [r][PB] values of type L,
+// and every sum is taken in L: FP64 for FP64 tables, else FP32 (the
+// precision of the matrix-core path).  Group q loads receivers
+// r = q (mod groups) and takes emitters [m q / groups, m (q + 1) / groups);
+// partial sums are combined in group order, so the result is deterministic.
+template <typename T, typename L, int PB>
+__global__ void __launch_bounds__(kHbThreads) k_hess_band(HbParams P, const T *__restrict__ Gr,
+                                                          const T *__restrict__ Gi, const float *__restrict__ gscale,
+                                                          const int2 *__restrict__ zeroed,
+                                                          const int *__restrict__ nzero, double *__restrict__ hd) {
+    constexpr int NG = kHbThreads / PB;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    L *sg = reinterpret_cast<L *>(lds_raw);   // [m][PB]
+    __shared__ L spart[kHbThreads];
+    __shared__ int2 sz[kHbThreads];           // a chunk of the zeroed-pair list
+    const int m = P.m;
+    const int t = threadIdx.x;
+    const int px = t % PB, grp = t / PB;
+    const int64_t x = (int64_t)blockIdx.x * PB + px;
+    const bool okx = x < P.N;
+    const L *col = sg + px;
+    const int half = P.dmin - 1;              // band: r = e + s, |s| <= half
+    const bool none = 2 * half + 1 >= m;      // the band covers the ring: nothing selected
+    const int e0 = (m * grp) / NG, e1 = (m * (grp + 1)) / NG;
+    double total = 0.0;
+    for (int k = 0; k < P.nf; ++k) {
+        const T *gr = Gr + (int64_t)k * m * P.N + x;
+        const T *gi = Gi + (int64_t)k * m * P.N + x;
+        const L sc = gscale ? (L)gscale[k] * (L)gscale[k] : (L)1;
+        L sp = 0;
+        // eight rows in flight per thread
+        for (int r0 = grp; r0 < m; r0 += 8 * NG) {
+            T va[8], vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = r0 + u * NG;
+                const bool ok = okx && r < m;
+                va[u] = ok ? gr[(int64_t)r * P.N] : T(0);
+                vb[u] = ok ? gi[(int64_t)r * P.N] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = r0 + u * NG;
+                if (r < m) {
+                    const L a = (L)to_d(va[u]), b = (L)to_d(vb[u]);
+                    const L v = (a * a + b * b) * sc;
+                    sg[r * PB + px] = v;
+                    sp += v;
+                }
+            }
+        }
+        spart[t] = sp;
+        __syncthreads();
+        L S = 0;
+        for (int q = 0; q < NG; ++q) S += spart[q * PB + px];
+        L acc = 0;
+        if (!none && e0 < e1) {
+            // window of e0: receivers e0 - half .. e0 + half (mod m); 2 half + 1 < m
+            L B = 0;
+            int ri = e0 - half;
+            if (ri < 0) ri += m;
+#pragma unroll 8
+            for (int s = -half; s <= half; ++s) {
+                B += col[ri * PB];
+                if (++ri == m) ri = 0;
+            }
+            // slide: add e + half + 1, drop e - half
+            int ra = e0 + half + 1, rd = e0 - half;
+            if (ra >= m) ra -= m;
+            if (rd < 0) rd += m;
+#pragma unroll 4
+            for (int e = e0; e < e1; ++e) {
+                acc += col[e * PB] * (S - B);
+                if (half >= 0) {
+                    B += col[ra * PB] - col[rd * PB];
+                    if (++ra == m) ra = 0;
+                    if (++rd == m) rd = 0;
+                }
+            }
+        }
+        // zeroed pairs, staged through LDS a chunk at a time
+        const int nz = nzero ? min(nzero[k], P.zcap) : 0;   // block-uniform
+        for (int c0 = 0; c0 < nz; c0 += kHbThreads) {
+            __syncthreads();   // the previous chunk has been read
+            if (c0 + t < nz) sz[t] = zeroed[(int64_t)k * P.zcap + c0 + t];
+            __syncthreads();
+            const int cn = min(kHbThreads, nz - c0);
+            for (int i0 = grp; i0 < cn; i0 += 8 * NG) {
+                L pr[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = i0 + u * NG;
+                    pr[u] = 0;
+                    if (i < cn) {
+                        const int2 q = sz[i];
+                        if ((unsigned)q.x < (unsigned)m && (unsigned)q.y < (unsigned)m)
+                            pr[u] = col[q.x * PB] * col[q.y * PB];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc -= pr[u];
+            }
+        }
+        __syncthreads();   // every thread has read spart, sg and sz
+        spart[t] = acc;
+        __syncthreads();
+        if (grp == 0) {
+            L a = 0;
+            for (int q = 0; q < NG; ++q) a += spart[q * PB + px];
+            total += (double)a * P.ch[k];
+        }
+        __syncthreads();
+    }
+    if (grp == 0 && okx) hd[x] += total;
+}
+
+// LDS of [m][PB] values within 32 KiB
+constexpr size_t kHbLds = 32768;
+
+}  // namespace
+
+rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                            rb_dtype dt, const double *freqs, int nf, int dmin, const int *zeroed,
+                            const int *nzero, int zcap, double *hdiag, hipStream_t st) {
+    HbParams P;
+    P.m = g->m;
+    P.nf = nf;
+    P.N = (int64_t)g->nx * g->ny;
+    P.dmin = dmin;
+    P.zcap = zcap;
+    // pixels per block: [m][pb] values within 32 KiB (m <= 4096)
+    const bool f64 = dt == RB_F64;
+    const int pb = f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2));
+    const size_t lds = (size_t)P.m * pb * (f64 ? sizeof(double) : sizeof(float));
+    if (lds > kHbLds) {
+        set_error("m = %d is too large for the banded Hessian", P.m);
+        return RB_EUNSUPPORTED;
+    }
+    P.pb = pb;
+    const double dA = g->h * g->h;
+    for (int k = 0; k < nf; ++k) {
+        const double om = 2.0 * M_PI * freqs[k];
+        const double c = om * om * dA;
+        P.ch[k] = c * c;
+    }
+    const unsigned nb = (unsigned)((P.N + pb - 1) / pb);
+    const int2 *z = reinterpret_cast<const int2 *>(zeroed);
+    if (zcap == 0) nzero = nullptr;
+    auto go = [&](auto tag, auto ltag, const float *gs) {
+        using T = decltype(tag);
+        using L = decltype(ltag);
+        const T *gr = static_cast<const T *>(G_re), *gi = static_cast<const T *>(G_im);
+        switch (pb) {
+            case 32: k_hess_band<T, L, 32><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+            case 16: k_hess_band<T, L, 16><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+            case 8: k_hess_band<T, L, 8><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+            case 4: k_hess_band<T, L, 4><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+            case 2: k_hess_band<T, L, 2><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+            default: k_hess_band<T, L, 1><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
+        }
+    };
+    switch (dt) {
+        case RB_F64: go(double(), double(), nullptr); break;
+        case RB_F32: go(float(), float(), nullptr); break;
+        case RB_BF16: go(__hip_bfloat16(), float(), gscale); break;
+        case RB_F16: go(__half(), float(), gscale); break;
+    }
+    RB_LAUNCHED();
+    return RB_OK;
+}
+
+}  // namespace rb
+
+extern "C" {
+
+rb_status rb_born_hessian_banded(const rb_geometry *g, const void *G_re, const void *G_im, const float *scale,
+                                 rb_dtype dtype, const double *freqs_hz, int32_t nf, int32_t dmin,
+                                 const int32_t *zeroed, const int32_t *nzero, int32_t zcap, double *hdiag,
+                                 void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_contraction(g, G_re, G_im, scale, dtype, freqs_hz, nf));
+    RB_CHECK_ARG(hdiag != nullptr, "hdiag is NULL");
+    RB_CHECK_ARG(dmin >= 0, "dmin must be >= 0");
+    RB_CHECK_ARG(zcap >= 0 && (zcap == 0 || (zeroed && nzero)), "zeroed/nzero are required when zcap > 0");
+    return rb::hessian_band_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, dmin, zeroed, nzero, zcap, hdiag,
+                                 rb::as_stream(stream));
+}
+
+}  // extern "C"

@@ -158,6 +158,42 @@ __global__ void __launch_bounds__(kWThreads) k_weights(int m, int dmin, int64_t 
     }
 }
 
+// The zeroed selected pairs of one frequency per block, as (e, r) in flat
+// index order (for the banded Hessian diagonal): per-thread counts over
+// contiguous chunks, an exclusive scan in thread order, then the writes.
+__global__ void __launch_bounds__(kWThreads) k_zero_list(int m, int dmin, const double *__restrict__ W, int zcap,
+                                                         int2 *__restrict__ zl, int *__restrict__ nz) {
+    __shared__ int64_t scan[kWThreads];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    const double *wk = W + (int64_t)k * mm;
+    const int64_t chunk = (mm + kWThreads - 1) / kWThreads;
+    const int64_t lo = (int64_t)tid * chunk, hi = std::min<int64_t>(mm, lo + chunk);
+    int64_t cnt = 0;
+    for (int64_t i = lo; i < hi; ++i)
+        if (selected(i, m, dmin) && wk[i] == 0.0) ++cnt;
+    scan[tid] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int t = 0; t < kWThreads; ++t) {
+            const int64_t v = scan[t];
+            scan[t] = acc;
+            acc += v;
+        }
+        nz[k] = (int)std::min<int64_t>(acc, zcap);
+    }
+    __syncthreads();
+    int64_t pos = scan[tid];
+    for (int64_t i = lo; i < hi && pos < zcap; ++i) {
+        if (selected(i, m, dmin) && wk[i] == 0.0) {
+            const int e = (int)(i / m);
+            zl[(int64_t)k * zcap + pos] = make_int2(e, (int)(i - (int64_t)e * m));
+            ++pos;
+        }
+    }
+}
+
 // Support: |x| < R - margin and covered by every emitter.
 __global__ void k_support(int nx, int ny, double h, double x0, double y0, double rs, int m,
                           const double *__restrict__ T, uint8_t *__restrict__ S) {
@@ -311,6 +347,8 @@ struct InvWs {
     float *amp, *att, *amp_rx, *att_rx, *gscale;
     void *Gr, *Gi;
     uint8_t *S;
+    int2 *zl;   // zeroed pairs [nf][m m]
+    int *nz;    // their counts [nf]
     void *scratch;
 };
 
@@ -338,6 +376,8 @@ InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
     w.part = c.take<double>(2 * kRB);
     w.res = c.take<double>(8);
     w.hmax = c.take<double>(1);
+    w.zl = c.take<int2>((size_t)nf * mm);
+    w.nz = c.take<int>(RB_MAX_NF);
     w.scratch = c.take<char>(0);
     return w;
 }
@@ -406,10 +446,16 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     k_weights<<<nf, kWThreads, 0, st>>>(m, dmin, kzero, p_meas, w.W);
     RB_LAUNCHED();
     // 3. gradient and Hessian diagonal
+    // the Hessian diagonal comes from the band structure of W: the
+    // backprojection computes the gradient only
+    k_zero_list<<<nf, kWThreads, 0, st>>>(m, dmin, w.W, m * m, w.zl, w.nz);
+    RB_LAUNCHED();
     RB_TRY(fill_f64(w.grad, 0.0, N, st));
     RB_TRY(fill_f64(w.hd, 0.0, N, st));
-    RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.D, w.W, w.grad, w.hd, scratch,
+    RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.D, w.W, w.grad, nullptr, scratch,
                         scratch_bytes, st));
+    RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin, reinterpret_cast<int *>(w.zl),
+                             w.nz, m * m, w.hd, st));
     // 4. diagonally weighted direction on the support
     const double rs = g->ring_radius - g->support_margin;
     k_support<<<blocks_for(N, 256), 256, 0, st>>>(g->nx, g->ny, g->h, g->x0, g->y0, rs, m, w.T, w.S);

@@ -95,6 +95,24 @@ def test_fullsize_backprojection_sampled_pixels(rb, prob):
         ho += born.hessian_diag(G, Wd[k], f, g.h ** 2)
     assert np.linalg.norm(gg[xs] - go) / np.linalg.norm(go) <= 1e-5
     assert np.linalg.norm(hg[xs] - ho) / np.linalg.norm(ho) <= 1e-5
+    # the banded Hessian diagonal for the same weights (band + zeroed pairs)
+    zl, nz = [], []
+    for k in range(nf):
+        z = np.flatnonzero((mask > 0) & (Wd[k] == 0))
+        zl.append(np.stack([z // g.m, z % g.m], -1).astype(np.int32))
+        nz.append(len(z))
+    zcap = max(1, max(nz))
+    za = np.zeros((nf, zcap, 2), np.int32)
+    for k in range(nf):
+        za[k, :nz[k]] = zl[k]
+    dmin = int(math.ceil(0.25 * 0.5 * g.m - 1e-9))
+    hb = torch.zeros(g.n_pixels, dtype=torch.float64, device=DEV)
+    rb.born_hessian_banded(g, Gr, Gi, None, "f32", freqs, dmin, torch.as_tensor(za, device=DEV),
+                           torch.as_tensor(np.array(nz, np.int32), device=DEV), hb)
+    torch.cuda.synchronize()
+    hbg = hb.cpu().numpy()
+    assert np.linalg.norm(hbg[xs] - ho) / np.linalg.norm(ho) <= 1e-5
+    assert np.linalg.norm(hbg - hg) / np.linalg.norm(hg) <= 2e-5
 
 
 def test_fullsize_forward_sampled_pairs(rb, prob):

@@ -198,6 +198,88 @@ def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
     assert _rel(hd.cpu().numpy(), h_o) <= tol
 
 
+def _banded_weights(m, nf, dmin, nzero_each, seed):
+    """Band-selection weights with `nzero_each` selected pairs zeroed per
+    frequency, and the (e, r) list of those pairs."""
+    e = np.arange(m)[:, None]
+    r = np.arange(m)[None, :]
+    d = np.minimum(np.abs(e - r), m - np.abs(e - r))
+    sel = d >= dmin
+    rng = np.random.default_rng(seed)
+    Wd, lists = [], []
+    for _ in range(nf):
+        w = sel.astype(np.float64)
+        idx = np.flatnonzero(sel)
+        z = np.sort(rng.choice(idx, size=min(nzero_each, idx.size), replace=False)) if idx.size else idx
+        w.reshape(-1)[z] = 0.0
+        Wd.append(w)
+        lists.append(np.stack([z // m, z % m], axis=-1).astype(np.int32))
+    return np.stack(Wd), lists
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("shape", [(37, 29, 40, 5, 6), (64, 64, 64, 8, 40), (21, 50, 97, 12, 0),
+                                   (30, 30, 33, 0, 9), (30, 30, 16, 9, 0), (24, 23, 300, 38, 70)])
+def test_hessian_banded_matches_oracle(rb, dtype, shape):
+    """The banded Hessian diagonal against the oracle's dense sum with the same
+    weights, and against the backprojection's Hessian diagonal (dmin = 0: no
+    band; dmin = 9 at m = 16: the band covers the ring, so hd = 0)."""
+    nx, ny, m, dmin, nz = shape
+    geom = W.centred_grid(nx, 0.5e-3, m, 12e-3, 1500.0)
+    import dataclasses
+    geom = dataclasses.replace(geom, ny=ny, y0=-0.5 * (ny - 1) * 0.5e-3)
+    nf = 2
+    T, A, B, freqs, D, _, _ = _contraction_inputs(geom, nf, 41)
+    Wd, lists = _banded_weights(m, nf, dmin, nz, 42)
+    _say(f"hessian_banded dtype={dtype} nx={nx} ny={ny} m={m} dmin={dmin} zeroed={nz}")
+    Gr, Gi, sc = _gpu_green(rb, geom, T, A, B, freqs, dtype)
+    zcap = max(1, max(len(q) for q in lists))
+    zl = np.zeros((nf, zcap, 2), np.int32)
+    for k, q in enumerate(lists):
+        zl[k, :len(q)] = q
+    nzero = torch.as_tensor(np.array([len(q) for q in lists], np.int32), device=DEV)
+    hd = torch.zeros(geom.n_pixels, dtype=torch.float64, device=DEV)
+    rb.born_hessian_banded(geom, Gr, Gi, sc, dtype, freqs, dmin, torch.as_tensor(zl, device=DEV), nzero, hd)
+    grad = torch.zeros_like(hd)
+    hd_mfma = torch.zeros_like(hd)
+    rb.born_adjoint_weighted(geom, Gr, Gi, sc, dtype, freqs, _t(np.stack([D.real, D.imag], -1)), _t(Wd), grad,
+                             hd_mfma)
+    torch.cuda.synchronize()
+    h_o = np.zeros(geom.n_pixels)
+    for k, f in enumerate(freqs):
+        G = born.green(T, A.astype(np.float64), B.astype(np.float64), f)
+        h_o += born.hessian_diag(G, Wd[k], f, geom.h ** 2)
+    hg = hd.cpu().numpy()
+    if not np.any(Wd):
+        assert np.all(hg == 0.0) and np.all(h_o == 0.0)
+        return
+    tol = CONTRACTION_TOL[dtype]
+    assert _rel(hg, h_o) <= tol
+    assert _rel(hg, hd_mfma.cpu().numpy()) <= 2 * tol
+
+
+def test_hessian_banded_ignores_bad_pairs_and_is_deterministic(rb):
+    geom = W.centred_grid(24, 0.5e-3, 32, 8e-3, 1500.0)
+    T, A, B, freqs, _, _, _ = _contraction_inputs(geom, 1, 51)
+    Wd, lists = _banded_weights(32, 1, 4, 10, 52)
+    Gr, Gi, sc = _gpu_green(rb, geom, T, A, B, freqs, "f32")
+    zl = np.zeros((1, 12, 2), np.int32)
+    zl[0, :10] = lists[0]
+    zl[0, 10] = (-1, 3)        # out of range: ignored
+    zl[0, 11] = (5, 32)        # out of range: ignored
+    zdev = torch.as_tensor(zl, device=DEV)
+    outs = []
+    for n in (12, 12):
+        hd = torch.zeros(geom.n_pixels, dtype=torch.float64, device=DEV)
+        rb.born_hessian_banded(geom, Gr, Gi, sc, "f32", freqs, 4, zdev,
+                               torch.tensor([n], dtype=torch.int32, device=DEV), hd)
+        outs.append(hd.cpu().numpy())
+    G = born.green(T, A.astype(np.float64), B.astype(np.float64), freqs[0])
+    h_o = born.hessian_diag(G, Wd[0], freqs[0], geom.h ** 2)
+    assert np.array_equal(outs[0], outs[1])
+    assert _rel(outs[0], h_o) <= 1e-5
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("shape", [(37, 29, 40), (50, 50, 130)])
 def test_forward_matches_oracle(rb, dtype, shape):
