@@ -10,7 +10,9 @@ update the model.  Inputs are synthetic and resident in HBM before timing.
 Metric: Born backprojection throughput in Gpixel.pair.freq/s =
 N * P * F / t_step / 1e9 (N pixels, P selected emitter-receiver pairs,
 F frequencies).  The roofline entry is for the dominant kernel, the fused
-complex MFMA backprojection, at 10 flop per (pixel, pair, frequency).
+complex MFMA backprojection as the step runs it (gradient only; the step
+takes the Hessian diagonal from band sums), at 8 flop per (pixel, pair,
+frequency).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -152,21 +154,21 @@ def main():
     hd = torch.zeros(N, dtype=torch.float64, device=dev)
     aws = torch.empty(rb.adjoint_workspace_bytes(g, nf, args.dtype), dtype=torch.uint8, device=dev)
     for _ in range(3):
-        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, hd, ws=aws, stream=stream)
+        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, None, ws=aws, stream=stream)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(args.adjoint_reps):
-        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, hd, ws=aws, stream=stream)
+        rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0], Wd, grad, None, ws=aws, stream=stream)
     ev1.record(stream)
     ev1.synchronize()
     adj_ms = ev0.elapsed_time(ev1) / args.adjoint_reps
-    flops = 10.0 * N * P * nf
+    flops = 8.0 * N * P * nf
     achieved = flops / (adj_ms * 1e-3) / 1e12
     esize = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
-    alg_bytes = 2 * nf * g.m * N * esize + 2 * nf * N * 8   # G (re, im) once + per-frequency partials
+    alg_bytes = 2 * nf * g.m * N * esize + nf * N * 8   # G (re, im) once + per-frequency gradient partials
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[args.dtype], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK[args.dtype], 4), "traffic": measured_traffic(args.dtype),
-                "kernel": "k_adjoint (fused complex backprojection + Hessian diagonal)",
+                "kernel": "k_adjoint_f32 (fused complex backprojection, gradient as the step runs it)",
                 "launch_ms": round(adj_ms, 4), "algorithmic_flop_per_launch": flops,
                 "algorithmic_bytes_per_launch": alg_bytes}
 
@@ -188,6 +190,7 @@ def main():
         b.synchronize()
         return a.elapsed_time(b) / reps
 
+    dmin = int(math.ceil((1.0 - prob.inv.recv_fraction) * 0.5 * g.m - 1e-9))
     tws = torch.empty(rb.trace_workspace_bytes(g, topts), dtype=torch.uint8, device=dev)
     fws = torch.empty(rb.forward_workspace_bytes(g, nf, args.dtype), dtype=torch.uint8, device=dev)
     dout = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=dev)
@@ -196,6 +199,10 @@ def main():
         "build_green": timed(lambda: rb.build_green(g, tabs, fs, prob.inv.y_pow, args.dtype, Gr, Gi, sc,
                                                     stream=stream)),
         "born_adjoint_weighted": adj_ms,
+        "born_adjoint_weighted+hdiag": timed(lambda: rb.born_adjoint_weighted(g, Gr, Gi, sc, args.dtype, fs, pms[0],
+                                                                              Wd, grad, hd, ws=aws, stream=stream)),
+        "born_hessian_banded": timed(lambda: rb.born_hessian_banded(g, Gr, Gi, sc, args.dtype, fs, dmin, None, None,
+                                                                    hd, stream=stream)),
         "born_forward": timed(lambda: rb.born_forward(g, Gr, Gi, sc, args.dtype, fs, grad, dout, ws=fws,
                                                       stream=stream)),
     }

@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
         const int64_t x = x0 + tid;
         if (x < N) {
             pg[(int64_t)blockIdx.y * N + x] = sred[0][0][tid] + sred[1][0][tid];
-            ph[(int64_t)blockIdx.y * N + x] = sred[0][1][tid] + sred[1][1][tid];
+            if (HESS) ph[(int64_t)blockIdx.y * N + x] = sred[0][1][tid] + sred[1][1][tid];
         }
     }
 }
