@@ -358,64 +358,63 @@ __global__ void k_block_flags(int m, int nb, int nf, const double *__restrict__ 
 
 // ------------------------------------------------------------------ FP32, LDS-staged
 // Backprojection.  The workgroup owns 64 pixels; its four waves are 2
-// (emitter halves) x 2 (pixel halves), each computing 32 e x 32 px of Y, Z
-// per chunk of 64 emitters.  Receivers are consumed 32 at a time: the G tile
-// [32 r][64 px] is staged in LDS, double buffered, with a row stride of 80
-// floats so the four lane groups (rows 4 s + kk) fall on disjoint banks.  A
-// is stored k-permuted, so a lane's eight A values of a chunk are two float4
-// loads (served from L2: A is shared by every workgroup).
-constexpr int kAdjNT = 64, kAdjKC = 32, kAdjLD = 80;
-// The tiles of the chunk's own 64 emitters are also kept for the epilogue,
-// [e][px] with a row stride of 68 floats: the four lane groups read rows
-// 4 apart, which then fall 16 banks apart.
-constexpr int kAdjLE = 68;
+// (emitter halves) x 2 (pixel halves), each computing 32 e x 32 px of Y per
+// chunk of 64 emitters.  Receivers are consumed 32 at a time: the G tile
+// [32 r][64 px] (re, im) goes from global memory straight into LDS
+// (global_load_lds, 16 bytes per lane), double buffered, so staging costs
+// no registers and overlaps the MFMAs of the previous chunk.  Rows are
+// unpadded; the 16-byte chunks of row r are XOR-swizzled by (r & 3), which
+// puts the four lane groups of a B-fragment read (rows 4 s + kk) on distinct
+// banks.  A is stored k-permuted, so a lane's eight A values of a chunk are
+// two float4 loads (served from L2: A is shared by every workgroup),
+// prefetched one chunk ahead.
+constexpr int kAdjNT = 64, kAdjKC = 32, kAdjTile = kAdjKC * 64;
 
-__device__ __forceinline__ void adj_stage_load(const float *__restrict__ gr, const float *__restrict__ gi, int m,
-                                               int64_t N, int rc, int64_t x0, bool vec, f4 (&v)[4]) {
-    const int t = threadIdx.x;
-    const int rr = t >> 3, c4 = (t & 7) * 4;
-    const int r = rc + rr;
-    if (vec) {
-        if (r < m) {
-            const float *pr = gr + (int64_t)r * N + x0 + c4;
-            const float *pi = gi + (int64_t)r * N + x0 + c4;
-            v[0] = *reinterpret_cast<const f4 *>(pr);
-            v[1] = *reinterpret_cast<const f4 *>(pr + 32);
-            v[2] = *reinterpret_cast<const f4 *>(pi);
-            v[3] = *reinterpret_cast<const f4 *>(pi + 32);
-        } else {
-            v[0] = v[1] = v[2] = v[3] = f4{0, 0, 0, 0};
-        }
-    } else {
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// LDS offset (floats) of (tile row r, pixel px) in a swizzled [32][64] tile
+__device__ __forceinline__ int adj_off(int r, int px) {
+    return r * 64 + ((((px >> 2) ^ ((r & 3) << 2))) << 2) + (px & 3);
+}
+
+// Aligned full tiles: wave w fills rows 8 w .. 8 w + 7 of both arrays, four
+// rows per instruction.  Lane l of an instruction writes LDS chunk
+// (row l / 16, chunk l % 16), so it loads the global chunk that the swizzle
+// puts there.  Rows at or beyond m read row m - 1: their A entries are zero.
+__device__ __forceinline__ void adj_stage_async(const float *__restrict__ gr, const float *__restrict__ gi, int m,
+                                                int64_t N, int rc, int64_t x0, float *sT) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t xa = x0 + c4 + q, xb = xa + 32;
-            const bool oka = r < m && xa < N, okb = r < m && xb < N;
-            v[0][q] = oka ? gr[(int64_t)r * N + xa] : 0.0f;
-            v[1][q] = okb ? gr[(int64_t)r * N + xb] : 0.0f;
-            v[2][q] = oka ? gi[(int64_t)r * N + xa] : 0.0f;
-            v[3][q] = okb ? gi[(int64_t)r * N + xb] : 0.0f;
-        }
+    for (int j = 0; j < 2; ++j) {
+        const int r0 = wave * 8 + j * 4;
+        const int rl = r0 + (lane >> 4);
+        const int r = min(rc + rl, m - 1);
+        const int gc = (lane & 15) ^ ((rl & 3) << 2);
+        const int64_t go = (int64_t)r * N + x0 + 4 * gc;
+        __builtin_amdgcn_global_load_lds(gr + go, (lds_void_t *)(sT + r0 * 64), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(gi + go, (lds_void_t *)(sT + kAdjTile + r0 * 64), 16, 0, 0);
     }
 }
 
-// Epilogue copy of a staged tile whose receivers are emitters ec .. ec + 63.
-__device__ __forceinline__ void adj_stage_keep(float (*sE)[64][kAdjLE], int row0, const f4 (&v)[4]) {
+// Ragged or unaligned tiles: through registers, zero beyond m and N.
+__device__ __forceinline__ void adj_stage_regs(const float *__restrict__ gr, const float *__restrict__ gi, int m,
+                                               int64_t N, int rc, int64_t x0, float *sT) {
     const int t = threadIdx.x;
-    const int rr = row0 + (t >> 3), c4 = (t & 7) * 4;
-    *reinterpret_cast<f4 *>(&sE[0][rr][c4]) = v[0];
-    *reinterpret_cast<f4 *>(&sE[0][rr][c4 + 32]) = v[1];
-    *reinterpret_cast<f4 *>(&sE[1][rr][c4]) = v[2];
-    *reinterpret_cast<f4 *>(&sE[1][rr][c4 + 32]) = v[3];
-}
-
-__device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], const f4 (&v)[4]) {
-    const int t = threadIdx.x;
-    const int rr = t >> 3, c4 = (t & 7) * 4;
-    *reinterpret_cast<f4 *>(&sB[0][rr][c4]) = v[0];
-    *reinterpret_cast<f4 *>(&sB[0][rr][c4 + 32]) = v[1];
-    *reinterpret_cast<f4 *>(&sB[1][rr][c4]) = v[2];
-    *reinterpret_cast<f4 *>(&sB[1][rr][c4 + 32]) = v[3];
+    const int rl = t >> 3, r = rc + rl, p0 = (t & 7) * 8;
+    float vr[8], vi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t x = x0 + p0 + q;
+        const bool ok = r < m && x < N;
+        vr[q] = ok ? gr[(int64_t)r * N + x] : 0.0f;
+        vi[q] = ok ? gi[(int64_t)r * N + x] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        sT[adj_off(rl, p0 + q)] = vr[q];
+        sT[kAdjTile + adj_off(rl, p0 + q)] = vi[q];
+    }
 }
 
 // NB row blocks starting at b0.  The complex product Y = A conj(G) uses
@@ -425,9 +424,9 @@ __device__ __forceinline__ void adj_stage_store(float (*sB)[kAdjKC][kAdjLD], con
 // each on a different accumulator.
 template <int NB, bool HESS>
 __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&vi)[2][2], const f4 (&vw)[2][2],
-                                              float (*sBr)[kAdjLD], float (*sBi)[kAdjLD],
-                                              int kk, int xc0, f4 (&p1)[2][2], f4 (&p2)[2][2], f4 (&p3)[2][2],
-                                              f4 (&z)[2][2], int b0) {
+                                              const float *sBr, const float *sBi, int kk, const int (&coff)[2],
+                                              f4 (&p1)[2][2], f4 (&p2)[2][2], f4 (&p3)[2][2], f4 (&z)[2][2],
+                                              int b0) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         // B fragments for four steps at a time (one LDS wait per half chunk)
@@ -436,8 +435,9 @@ __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&v
         for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                br[q4][cb] = sBr[4 * (4 * half + q4) + kk][xc0 + 16 * cb];
-                bi[q4][cb] = sBi[4 * (4 * half + q4) + kk][xc0 + 16 * cb];
+                const int o = (4 * (4 * half + q4) + kk) * 64 + coff[cb];
+                br[q4][cb] = sBr[o];
+                bi[q4][cb] = sBi[o];
             }
 #pragma unroll
     for (int q4 = 0; q4 < 4; ++q4) {
@@ -465,15 +465,15 @@ __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&v
     }
 }
 
-// HESS = false computes the gradient only (three MFMAs per block and step).
+// HESS = false computes the gradient only (three MFMAs per block and step);
+// its registers allow three workgroups per CU (34 KB of LDS each).
 template <bool HESS>
-__global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
+__global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
                                                         const float *__restrict__ Gi, const float *__restrict__ Ar,
                                                         const float *__restrict__ Ai, const float *__restrict__ Wt,
                                                         const uint8_t *__restrict__ flags, double *__restrict__ pg,
                                                         double *__restrict__ ph) {
-    __shared__ float sB[2][2][kAdjKC][kAdjLD];
-    __shared__ float sE[2][64][kAdjLE];
+    __shared__ __align__(16) float sB[2][2 * kAdjTile];   // [buffer][re tile, im tile]
     __shared__ double sred[2][2][kAdjNT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
@@ -481,7 +481,11 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
     const int we = wave >> 1, wp = wave & 1;
     const int64_t N = P.N;
     const int64_t x0 = (int64_t)blockIdx.x * kAdjNT;
-    const bool vec = ((N & 3) == 0) && (x0 + kAdjNT <= N);
+    const bool vec = ((N & 3) == 0) && (x0 + kAdjNT <= N);   // workgroup-uniform
+    // this lane's column offsets in the swizzled tile (rows 4 s + kk)
+    int coff[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) coff[cb] = adj_off(kk, 32 * wp + 16 * cb + row) - kk * 64;
     const int nch = P.mp / kAdjKC;
     double gacc[2] = {0.0, 0.0}, hacc[2] = {0.0, 0.0};
 
@@ -525,34 +529,33 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                     }
                 }
             };
-            f4 stg[4];
+            auto stage = [&](int rc, float *dst) {
+                if (vec)
+                    adj_stage_async(gr, gi, P.m, N, rc, x0, dst);
+                else
+                    adj_stage_regs(gr, gi, P.m, N, rc, x0, dst);
+            };
             f4 va[2][2], vi[2][2], vw[2][2];
-            adj_stage_load(gr, gi, P.m, N, 0, x0, vec, stg);
+            stage(0, sB[0]);
             bool on = chunk_on(0);
             if (on) load_a(0, va, vi, vw);
-            adj_stage_store(sB[0], stg);
-            if (ec == 0) adj_stage_keep(sE, 0, stg);
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's direct-to-LDS loads have landed
             __syncthreads();
             for (int c = 0; c < nch; ++c) {
                 const int rc = c * kAdjKC, buf = c & 1;
                 bool on_n = false;
                 f4 na[2][2], ni[2][2], nw[2][2];
                 if (c + 1 < nch) {
-                    adj_stage_load(gr, gi, P.m, N, rc + kAdjKC, x0, vec, stg);
+                    stage(rc + kAdjKC, sB[buf ^ 1]);
                     on_n = chunk_on(rc + kAdjKC);
                     if (on_n) load_a(rc + kAdjKC, na, ni, nw);
                 }
                 if (on) {
                     // a block that is off holds exact zeros in A and W, so it
                     // may be computed along with the other one
-                    adj_mma_steps<2, HESS>(va, vi, vw, sB[buf][0], sB[buf][1], kk, 32 * wp + row, p1, p2, p3, z,
-                                           0);
+                    adj_mma_steps<2, HESS>(va, vi, vw, sB[buf], sB[buf] + kAdjTile, kk, coff, p1, p2, p3, z, 0);
                 }
-                if (c + 1 < nch) {
-                    adj_stage_store(sB[buf ^ 1], stg);
-                    const int rn = rc + kAdjKC - ec;   // wave-uniform
-                    if (rn >= 0 && rn < 64) adj_stage_keep(sE, rn, stg);
-                }
+                __builtin_amdgcn_s_waitcnt(0);   // chunk c + 1 has landed in LDS
                 __syncthreads();
                 on = on_n;
                 if (on) {
@@ -566,20 +569,18 @@ __global__ void __launch_bounds__(256, 2) k_adjoint_f32(AdjParams P, const float
                         }
                 }
             }
-            // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e, with
-            // G_e from the LDS copy (zero beyond the grid; rows e >= m may be
-            // stale when m is not a multiple of 64, hence the test)
+            // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int el = 32 * we + 16 * b + MM<float>::out_row(kk, i);
-                    const bool ok = ec + el < P.m;
+                    const int e = ec + 32 * we + 16 * b + MM<float>::out_row(kk, i);
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
-                        const int pl = 32 * wp + 16 * cb + row;
-                        const float ge_r = ok ? sE[0][el][pl] : 0.0f;
-                        const float ge_i = ok ? sE[1][el][pl] : 0.0f;
+                        const int64_t x = x0 + 32 * wp + 16 * cb + row;
+                        const bool ok = (e < P.m) && (x < N);
+                        const float ge_r = ok ? gr[(int64_t)e * N + x] : 0.0f;
+                        const float ge_i = ok ? gi[(int64_t)e * N + x] : 0.0f;
                         const float yr = p1[b][cb][i] + p2[b][cb][i];
                         const float yi = (p3[b][cb][i] - p1[b][cb][i]) + p2[b][cb][i];
                         gp[cb] += ge_r * yr + ge_i * yi;
