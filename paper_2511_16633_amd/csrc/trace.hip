@@ -38,7 +38,7 @@ struct TP {
     double rdie2;      // (R + 2h)^2
     double j_min;
     double bary_tol;
-    double two_sin_full, two_sin_half;
+    double inv_chord_full, inv_chord_half;   // 1 / (2 sin dpsi), 1 / (2 sin (dpsi / 2))
     double ring2_lo, ring2_hi;  // (R (1 -+ 2e-9))^2: conservative ring test on squares
     int e0, ne;        // emitter batch
     int idx_bits;      // bits of the triangle index in an arrival key
@@ -121,6 +121,7 @@ __global__ void k_pack(int nx, int ny, double s_bg, const double *__restrict__ s
 // a = sqrt(c / (8 pi max(J, j_min))) costs no extra field evaluation.
 // Nodes are stored [eb][n][j] (positions and (a, B) as double2 pairs).
 constexpr int kOwn = 62;
+typedef double nd2 __attribute__((ext_vector_type(2)));
 
 __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__ sa, double2 *__restrict__ XY,
                                                double2 *__restrict__ AB, int *__restrict__ L) {
@@ -160,20 +161,23 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
             if (lo && hi) {
                 dx = xr - xl;
                 dy = yr - yl;
-                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_full;
+                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_full;
             } else if (hi) {
                 dx = xr - st[0];
                 dy = yr - st[1];
-                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
+                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_half;
             } else if (lo) {
                 dx = st[0] - xl;
                 dy = st[1] - yl;
-                Jv = sqrt(dx * dx + dy * dy) / P.two_sin_half;
+                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_half;
             }
             if (Jv < P.j_min) Jv = P.j_min;
             const size_t k = base + (size_t)n * P.nr;
-            XY[k] = make_double2(st[0], st[1]);
-            AB[k] = make_double2(sqrt((1.0 / s0) / (eight_pi * Jv)), st[4]);
+            // nodes are written once and read by later passes: keep them
+            // from displacing the field grid in L2
+            __builtin_nontemporal_store(nd2{st[0], st[1]}, reinterpret_cast<nd2 *>(&XY[k]));
+            __builtin_nontemporal_store(nd2{sqrt(recip(s0 * (eight_pi * Jv))), st[4]},
+                                        reinterpret_cast<nd2 *>(&AB[k]));
         }
         if (alive && (last || n == P.nmax)) {
             if (own) L[(size_t)eb * P.nr + j] = n;
@@ -618,8 +622,8 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     P.j_min = t->j_min > 0.0 ? t->j_min : 0.25 * g->h;
     P.bary_tol = 1e-12;
     const double dpsi = M_PI / (double)t->n_rays;
-    P.two_sin_full = 2.0 * std::sin(dpsi);
-    P.two_sin_half = 2.0 * std::sin(0.5 * dpsi);
+    P.inv_chord_full = 1.0 / (2.0 * std::sin(dpsi));
+    P.inv_chord_half = 1.0 / (2.0 * std::sin(0.5 * dpsi));
     P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
     P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
     {
