@@ -482,12 +482,28 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
                                float *__restrict__ amp_out, float *__restrict__ att_out) {
     const int64_t npts = RX ? (int64_t)P.m : (int64_t)P.nx * P.ny;
     {
-        // one flat grid over (emitter, point block), XCD-contiguous
-        const int64_t bpe = (npts + 255) / 256;
+        // one flat grid over (emitter, point block), XCD-contiguous.  Pixel
+        // blocks are 16 x 16 tiles, each wave an 8 x 8 square: neighbouring
+        // lanes then interpolate on neighbouring mesh nodes whatever the ray
+        // direction, so their gathers share cache lines.
+        const int tx = (P.nx + 15) >> 4, ty = (P.ny + 15) >> 4;
+        const int64_t bpe = RX ? (npts + 255) / 256 : (int64_t)tx * ty;
         const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
         const int eb = (int)(wg / bpe);
-        const int64_t p = (wg - (int64_t)eb * bpe) * 256 + threadIdx.x;
-        if (p >= npts) return;
+        const int64_t b = wg - (int64_t)eb * bpe;
+        int64_t p;
+        int ii = 0, jj = 0;
+        if (RX) {
+            p = b * 256 + threadIdx.x;
+            if (p >= npts) return;
+        } else {
+            const int t = threadIdx.x, w = t >> 6, l = t & 63;
+            const int by = (int)(b / tx), bx = (int)(b - (int64_t)by * tx);
+            ii = bx * 16 + 8 * (w & 1) + (l & 7);
+            jj = by * 16 + 8 * (w >> 1) + (l >> 3);
+            if (ii >= P.nx || jj >= P.ny) return;
+            p = (int64_t)jj * P.nx + ii;
+        }
         const int64_t idx = (int64_t)eb * npts + p;
         const uint64_t key = akey[idx];
         double *Tout = reinterpret_cast<double *>(akey);
@@ -521,7 +537,6 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
             px = q.x;
             py = q.y;
         } else {
-            const int jj = (int)((uint32_t)p / (uint32_t)P.nx), ii = (int)(p - (int64_t)jj * P.nx);
             px = P.x0 + (double)ii * P.h;
             py = P.y0 + (double)jj * P.h;
         }
@@ -661,7 +676,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         RB_LAUNCHED();
         k_raster_rx<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, akey_rx);
         RB_LAUNCHED();
-        const unsigned gw = blocks_for(N, 256) * P.ne;
+        const unsigned gw = (unsigned)(((g->nx + 15) / 16) * ((g->ny + 15) / 16)) * P.ne;
         k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
         RB_LAUNCHED();
         const unsigned gr = blocks_for(g->m, 256) * P.ne;
