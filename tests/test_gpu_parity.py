@@ -172,7 +172,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
-@pytest.mark.parametrize("shape", [(37, 29, 40), (64, 64, 64), (21, 50, 97)])
+@pytest.mark.parametrize("shape", [(37, 29, 40), (64, 64, 64), (21, 50, 97), (30, 30, 48)])
 def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
     nx, ny, m = shape
     geom = W.centred_grid(nx, 0.5e-3, m, 12e-3, 1500.0)
@@ -186,6 +186,8 @@ def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
     hd = torch.zeros_like(grad)
     dres = _t(np.stack([D.real, D.imag], axis=-1))
     rb.born_adjoint_weighted(geom, Gr, Gi, sc, dtype, freqs, dres, _t(Wd), grad, hd)
+    grad_only = torch.zeros_like(grad)
+    rb.born_adjoint_weighted(geom, Gr, Gi, sc, dtype, freqs, dres, _t(Wd), grad_only, None)
     torch.cuda.synchronize()
     g_o = np.zeros(geom.n_pixels)
     h_o = np.zeros(geom.n_pixels)
@@ -196,6 +198,7 @@ def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
     tol = CONTRACTION_TOL[dtype]
     assert _rel(grad.cpu().numpy(), g_o) <= tol
     assert _rel(hd.cpu().numpy(), h_o) <= tol
+    assert _rel(grad_only.cpu().numpy(), g_o) <= tol   # the gradient-only kernel
 
 
 def _banded_weights(m, nf, dmin, nzero_each, seed):
