@@ -25,6 +25,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
@@ -246,7 +248,8 @@ def straight_ray_data(geom: Geometry, c: np.ndarray, alpha: np.ndarray,
     omega = 2.0 * math.pi * np.asarray(freqs, np.float64)
     fm = (np.asarray(freqs, np.float64) * 1e-6) ** y_pow
     s_bg = 1.0 / geom.c_background
-    for e in range(m):
+
+    def emitter_row(e):
         d = pos - pos[e]
         L = np.hypot(d[:, 0], d[:, 1])
         xs = pos[e, 0] + d[:, 0:1] * t_mid[None, :]
@@ -257,8 +260,18 @@ def straight_ray_data(geom: Geometry, c: np.ndarray, alpha: np.ndarray,
         ic, jc = np.clip(ii, 0, geom.nx - 1), np.clip(jj, 0, geom.ny - 1)
         sv = np.where(ok, s[jc, ic], s_bg)
         av = np.where(ok, alpha[jc, ic], 0.0)
-        T = sv.sum(axis=1) * (L / nsamp)
-        Bab = av.sum(axis=1) * (L / nsamp)
+        return L, sv.sum(axis=1) * (L / nsamp), av.sum(axis=1) * (L / nsamp)
+
+    # the chord integrals of different emitters are independent (threads:
+    # NumPy releases the GIL in these array operations)
+    workers = max(1, min(16, os.cpu_count() or 1)) if m >= 128 else 1
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            rows = list(ex.map(emitter_row, range(m)))
+    else:
+        rows = [emitter_row(e) for e in range(m)]
+    for e in range(m):
+        L, T, Bab = rows[e]
         with np.errstate(divide="ignore", invalid="ignore"):
             for k in range(nf):
                 amp = np.sqrt(geom.c_background / (8.0 * math.pi * omega[k] * L))
@@ -314,6 +327,18 @@ def _sets(freqs: np.ndarray, per_set: int) -> List[np.ndarray]:
     return [freqs[i:i + per_set].copy() for i in range(0, len(freqs), per_set)]
 
 
+def data_for_sets(geom: Geometry, c: np.ndarray, alpha: np.ndarray,
+                  freq_sets: List[np.ndarray]) -> List[np.ndarray]:
+    """straight_ray_data for every set, the chord integrals taken once."""
+    allf = np.concatenate([np.asarray(f, np.float64) for f in freq_sets])
+    d = straight_ray_data(geom, c, alpha, allf)
+    out, k = [], 0
+    for f in freq_sets:
+        out.append(np.ascontiguousarray(d[k:k + len(f)]))
+        k += len(f)
+    return out
+
+
 def small_ring(seed: int = 1000, with_data: bool = True) -> Problem:
     """64-element ring, R = 30 mm, 128x128 grid at 0.5 mm, water plus three
     random ellipses; one set {200, 250} kHz; FP64; homogeneous start."""
@@ -323,7 +348,7 @@ def small_ring(seed: int = 1000, with_data: bool = True) -> Problem:
     p = Problem("ring64_grid128", geom, TraceOpts(n_rays=360), InvertOpts(),
                 c, alpha, np.full_like(c, 1500.0), [freqs], "f64", seed)
     if with_data:
-        p.p_meas = [straight_ray_data(geom, c, alpha, f) for f in p.freq_sets]
+        p.p_meas = data_for_sets(geom, c, alpha, p.freq_sets)
     return p
 
 
@@ -336,7 +361,7 @@ def breast_ring256(seed: int = 1001, with_data: bool = True, dtype: str = "f32")
     p = Problem("ring256_grid480", geom, TraceOpts(n_rays=720), InvertOpts(),
                 c, alpha, smoothed(c, 4e-3, geom.h, 1500.0), _sets(freqs, 3), dtype, seed)
     if with_data:
-        p.p_meas = [straight_ray_data(geom, c, alpha, f) for f in p.freq_sets]
+        p.p_meas = data_for_sets(geom, c, alpha, p.freq_sets)
     return p
 
 
@@ -349,7 +374,7 @@ def breast_ring1024(seed: int = 1003, with_data: bool = True, dtype: str = "bf16
     p = Problem("ring1024_grid1100", geom, TraceOpts(n_rays=1440), InvertOpts(),
                 c, alpha, smoothed(c, 4e-3, geom.h, 1500.0), _sets(freqs, 4), dtype, seed)
     if with_data:
-        p.p_meas = [straight_ray_data(geom, c, alpha, f) for f in p.freq_sets]
+        p.p_meas = data_for_sets(geom, c, alpha, p.freq_sets)
     return p
 
 
@@ -375,7 +400,7 @@ def custom(n: int, h: float, m: int, ring_radius: float, n_rays: int,
     p = Problem(f"custom_{kind}_{n}_{m}", geom, TraceOpts(n_rays=n_rays), InvertOpts(),
                 c, alpha, start, sets, dtype, seed)
     if with_data:
-        p.p_meas = [straight_ray_data(geom, c, alpha, f) for f in p.freq_sets]
+        p.p_meas = data_for_sets(geom, c, alpha, p.freq_sets)
     return p
 
 
