@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-reps", type=int, default=20)
+    ap.add_argument("--workload", default="ring256_grid480", choices=["ring256_grid480", "ring1024_grid1100"],
+                    help="ring256_grid480 (default, the measured workload) or the large instance")
+    ap.add_argument("--emitter-batch", type=int, default=0, help="emitters traced per batch (0: all that fit)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -99,7 +102,9 @@ def main():
 
     dev = "cuda:0"
     t0 = time.time()
-    prob = W.breast_ring256(dtype=args.dtype)
+    large = args.workload == "ring1024_grid1100"
+    prob = W.breast_ring1024(dtype=args.dtype) if large else W.breast_ring256(dtype=args.dtype)
+    batch = args.emitter_batch or (128 if large else 0)
     g = prob.geom
     topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
     print(f"[bench] inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -108,7 +113,7 @@ def main():
     alpha = torch.as_tensor(prob.alpha0.reshape(-1), device=dev)
     pms = [torch.as_tensor(np.stack([p.real, p.imag], -1), device=dev) for p in prob.p_meas]
     nf_max = max(len(f) for f in prob.freq_sets)
-    ws = torch.empty(rb.invert_workspace_bytes(g, topts, nf_max, args.dtype), dtype=torch.uint8, device=dev)
+    ws = torch.empty(rb.invert_workspace_bytes(g, topts, nf_max, args.dtype, batch), dtype=torch.uint8, device=dev)
     c = torch.empty_like(c_start)
     stream = torch.cuda.current_stream()
 
@@ -143,7 +148,9 @@ def main():
     nf = len(fs)
     tabs = rb.alloc_tables(g, dev)
     s = (1.0 / c_start).contiguous()
-    rb.trace_rays(g, topts, s, alpha, tabs, stream=stream)
+    del ws   # the sweep's workspace; the stage timings below use their own
+    tws = torch.empty(rb.trace_workspace_bytes(g, topts, batch), dtype=torch.uint8, device=dev)
+    rb.trace_rays(g, topts, s, alpha, tabs, ws=tws, stream=stream)
     td = rb._binding.TORCH_DTYPES[rb.DTYPES[args.dtype]]
     Gr = torch.empty((nf, g.m, N), dtype=td, device=dev)
     Gi = torch.empty_like(Gr)
@@ -191,7 +198,6 @@ def main():
         return a.elapsed_time(b) / reps
 
     dmin = int(math.ceil((1.0 - prob.inv.recv_fraction) * 0.5 * g.m - 1e-9))
-    tws = torch.empty(rb.trace_workspace_bytes(g, topts), dtype=torch.uint8, device=dev)
     fws = torch.empty(rb.forward_workspace_bytes(g, nf, args.dtype), dtype=torch.uint8, device=dev)
     dout = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=dev)
     stages = {
@@ -212,13 +218,18 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
            "data": "synthetic (seeded breast phantom, straight-ray measured-data stand-in)",
-           "config": {"workload": "ring256_grid480: 256-element ring R=110 mm, 480x480 grid at 0.5 mm, "
-                                  "8 sets x 3 frequencies 0.3-1.25 MHz low to high, 720 rays/emitter, "
-                                  "FP64 rays/phase, " + args.dtype + " contractions",
+           "config": {"workload": (("ring1024_grid1100: 1024-element ring R=110 mm, 1100x1100 grid at 0.2 mm, "
+                                   "12 sets x 4 frequencies 0.3-2.0 MHz low to high, 1440 rays/emitter, ")
+                                  if large else
+                                  ("ring256_grid480: 256-element ring R=110 mm, 480x480 grid at 0.5 mm, "
+                                   "8 sets x 3 frequencies 0.3-1.25 MHz low to high, 720 rays/emitter, "))
+                                 + "FP64 rays/phase, " + args.dtype + " contractions",
                       "pixels": N, "selected_pairs": P, "frequencies": F, "pixel_pair_freq_per_step": units},
            "roofline": roofline, "stages_ms_per_set": stages}
 
-    if not args.no_cpu_baseline:
+    if large:
+        out["config"]["emitter_batch"] = batch
+    if not args.no_cpu_baseline and not large:
         out["cpu_baseline"] = cpu_baseline(prob, topts, P)
     print(json.dumps(out), flush=True)
 
