@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--workload", default="ring256_grid480", choices=["ring256_grid480", "ring1024_grid1100"],
                     help="ring256_grid480 (default, the measured workload) or the large instance")
     ap.add_argument("--emitter-batch", type=int, default=0, help="emitters traced per batch (0: all that fit)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop latency measurement")
+    ap.add_argument("--serving-jobs", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -229,9 +231,56 @@ def main():
 
     if large:
         out["config"]["emitter_batch"] = batch
+    if not args.no_serving and not large:
+        del tabs, Gr, Gi, sc, Wd, grad, hd, aws, tws, fws, dout, pms, c, c_start, alpha
+        torch.cuda.empty_cache()
+        try:
+            out["serving"] = serving_report(dev, args.serving_jobs)
+        except Exception as exc:   # reported, the measured line still prints
+            out["serving"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu_baseline and not large:
         out["cpu_baseline"] = cpu_baseline(prob, topts, P)
     print(json.dumps(out), flush=True)
+
+
+def serving_report(dev, n_jobs):
+    """Latency of the serving loop on a Poisson stream (0.5 jobs/s, sizes
+    64/256/1024 elements in the ratio 5:4:1, FP32 contractions), against the
+    same jobs served one at a time (plain sequential runs)."""
+    import copy
+    import torch
+    import workload as W
+    from paper_2511_16633_amd import serving as S
+    t = time.time()
+    specs = W.serving_stream(n_jobs)
+    jobs = []
+    for sp in specs:
+        p = W.serving_job(sp["size_class"], sp["seed"], sp["ring_radius"])
+        topts = W.resolve_trace_opts(p.geom, p.c_start, p.trace.n_rays)
+        jobs.append(S.Job(jid=sp["job"], arrival=sp["arrival_s"], geom=p.geom, topts=topts, inv=p.inv, dtype="f32",
+                          c_start=p.c_start, alpha0=p.alpha0, freq_sets=p.freq_sets, p_meas=p.p_meas,
+                          size_class=sp["size_class"]))
+    print(f"[bench] serving: {n_jobs} jobs generated in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
+    srv = S.Server(dev, max_running=4)
+    mixed = srv.run(jobs, realtime=True)
+    print(f"[bench] serving: stream served, p50 {mixed['p50_latency_s']:.3f} s, p99 {mixed['p99_latency_s']:.3f} s",
+          file=sys.stderr, flush=True)
+    service, same = [], True
+    for j in jobs:
+        a = copy.copy(j)
+        a.result = None
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        S.run_job(a, dev)
+        service.append(time.perf_counter() - t)
+        same = same and a.result is not None and j.result is not None and bool(np.array_equal(a.result, j.result))
+    seq = S.sequential_baseline(jobs, service)
+    counts = [sum(1 for j in jobs if j.size_class == c) for c in range(3)]
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"stream": f"Poisson 0.5 jobs/s, {n_jobs} jobs, seed 42; ring64_grid128 / ring256_grid480 / "
+                      f"ring1024_grid1100 = {counts[0]} / {counts[1]} / {counts[2]}; ring radius 80-120 mm; f32",
+            "budget_gib": round(srv.budget / 2**30, 1), "max_running": srv.max_running,
+            "served": rnd(mixed), "sequential_plain": rnd(seq), "same_alone_and_mixed": same}
 
 
 def cpu_baseline(prob, topts, P):

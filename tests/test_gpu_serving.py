@@ -1,0 +1,75 @@
+"""Serving loop on the GPU: jobs of different ring sizes run concurrently on
+their own streams, and every result is bit-for-bit the one the job gives
+alone."""
+import copy
+
+import numpy as np
+import pytest
+
+import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def serving():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_16633_amd as rbm
+    from paper_2511_16633_amd import serving as S
+    rbm.lib()
+    return S
+
+
+def _jobs(S):
+    specs = [(0, 2101, 0.085), (0, 2102, 0.11), (1, 2103, 0.1), (0, 2104, 0.095), (0, 2105, 0.12), (0, 2106, 0.03)]
+    jobs = []
+    for i, (cls, seed, radius) in enumerate(specs):
+        p = W.serving_job(cls, seed, radius)
+        topts = W.resolve_trace_opts(p.geom, p.c_start, p.trace.n_rays)
+        jobs.append(S.Job(jid=i, arrival=0.05 * i, geom=p.geom, topts=topts, inv=p.inv, dtype="f32",
+                          c_start=p.c_start, alpha0=p.alpha0, freq_sets=p.freq_sets, p_meas=p.p_meas,
+                          size_class=cls))
+    return jobs
+
+
+def test_mixed_results_equal_alone(serving):
+    S = serving
+    print("[gpu-case] serving: 6 jobs alone, then mixed", flush=True)
+    alone = _jobs(S)
+    srv = S.Server(DEV, max_running=4)
+    for j in alone:
+        S.plan(j, srv.budget // 2)
+        S.run_job(j, DEV)
+    mixed = _jobs(S)
+    stats = srv.run(mixed, realtime=False)
+    assert stats["errors"] == 0, [j.error for j in mixed]
+    for a, b in zip(alone, mixed):
+        assert a.result is not None and b.result is not None
+        assert np.array_equal(a.result, b.result), f"job {a.jid} differs alone and mixed"
+        assert a.norms == b.norms
+        assert not np.array_equal(b.result, b.c_start.reshape(-1))   # the model was updated
+    # several jobs were on the device at once
+    spans = sorted((j.t_admit, j.t_done) for j in mixed)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+
+
+def test_admission_respects_the_budget(serving):
+    """A budget that holds one large-ish job at a time still serves every job,
+    and jobs never overlap beyond the budget."""
+    S = serving
+    print("[gpu-case] serving: tight budget", flush=True)
+    jobs = _jobs(S)
+    for j in jobs:
+        S.plan(j, 1 << 62)
+    budget = max(j.footprint for j in jobs)
+    srv = S.Server(DEV, budget_bytes=budget, max_running=8)
+    stats = srv.run(jobs, realtime=False)
+    assert stats["errors"] == 0
+    events = sorted([(j.t_admit, j.footprint) for j in jobs] + [(j.t_done, -j.footprint) for j in jobs])
+    used = 0
+    for _, d in events:
+        used += d
+        assert used <= budget

@@ -421,6 +421,40 @@ def serving_stream(n_jobs: int = 200, rate: float = 0.5, seed: int = 42,
     return jobs
 
 
+SERVING_CLASSES = ("ring64_grid128", "ring256_grid480", "ring1024_grid1100")
+
+
+def serving_job(size_class: int, seed: int, ring_radius: float, with_data: bool = True,
+                dtype: str = "f32") -> Problem:
+    """One job of the serving stream: the grid, ring size and frequency sets
+    of the 64-, 256- or 1024-element workloads, with the job's own ring
+    radius and seeded phantom (support scaled to min(R, half grid))."""
+    if size_class == 0:
+        n, h, m, n_rays = 128, 0.5e-3, 64, 360
+        sets = [np.array([200e3, 250e3])]
+    elif size_class == 1:
+        n, h, m, n_rays = 480, 0.5e-3, 256, 720
+        sets = _sets(np.linspace(0.3e6, 1.25e6, 24), 3)
+    elif size_class == 2:
+        n, h, m, n_rays = 1100, 0.2e-3, 1024, 1440
+        sets = _sets(np.linspace(0.3e6, 2.0e6, 48), 4)
+    else:
+        raise ValueError(size_class)
+    geom = centred_grid(n, h, m, ring_radius, 1500.0)
+    support = min(ring_radius, 0.5 * n * h)
+    if size_class == 0:
+        c, alpha = ellipse_phantom(geom, seed, centre_radius=0.6 * support)
+        start = np.full_like(c, 1500.0)
+    else:
+        c, alpha = breast_phantom(geom, seed, support_radius=0.8 * support, calcifications=size_class == 2)
+        start = smoothed(c, 4e-3, h, 1500.0)
+    p = Problem(f"{SERVING_CLASSES[size_class]}_job{seed}", geom, TraceOpts(n_rays=n_rays), InvertOpts(),
+                c, alpha, start, sets, dtype, seed)
+    if with_data:
+        p.p_meas = data_for_sets(geom, c, alpha, p.freq_sets)
+    return p
+
+
 def resolve_trace_opts(geom: Geometry, c: np.ndarray, n_rays: int,
                        headroom: float = 1.1) -> TraceOpts:
     """Fix the ray step and length for a job from its start model.
