@@ -16,6 +16,7 @@
 // around the diagonal) are skipped per 16x16 block.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "born.h"
 #include "common.h"
@@ -143,126 +144,10 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjParams P, const T *__restric
     }
 }
 
-// 16-bit variant: MFMA 16x16x32 with FP32 accumulation.  Lane group kk
-// supplies k = 8 kk + i (i = 0..7); operands are stored pre-scaled.
-template <typename S, int RB, int CB>
-__global__ void __launch_bounds__(256) k_adjoint16(AdjParams P, const S *__restrict__ Gr, const S *__restrict__ Gi,
-                                                   const S *__restrict__ Ar, const S *__restrict__ Ai,
-                                                   const S *__restrict__ Wt, const uint8_t *__restrict__ flags,
-                                                   const float *__restrict__ gscale,
-                                                   const float *__restrict__ ascale, double *__restrict__ grad,
-                                                   double *__restrict__ hd) {
-    using V = typename MM16<S>::vec;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row = lane & 15, kk = lane >> 4;
-    const int64_t N = P.N;
-    const int64_t xw = (int64_t)blockIdx.x * (64 * CB) + (int64_t)wave * 16 * CB;
-    double gacc[CB], hacc[CB];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) gacc[c] = hacc[c] = 0.0;
-
-    for (int k = 0; k < P.nf; ++k) {
-        const S *gr = Gr + (int64_t)k * P.m * N;
-        const S *gi = Gi + (int64_t)k * P.m * N;
-        const S *ar = Ar + (int64_t)k * P.mp * P.mp;
-        const S *ai = Ai + (int64_t)k * P.mp * P.mp;
-        const S *wt = Wt + (int64_t)k * P.mp * P.mp;
-        const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
-        float gp[CB], hp[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) gp[c] = hp[c] = 0.0f;
-        for (int ec = 0; ec < P.mp; ec += 16 * RB) {
-            f4 yr[RB][CB], yn[RB][CB], z[RB][CB];
-#pragma unroll
-            for (int b = 0; b < RB; ++b)
-#pragma unroll
-                for (int c = 0; c < CB; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
-            for (int rc = 0; rc < P.mp; rc += 32) {
-                bool on[RB];
-                bool any = false;
-#pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    const int eb = ec / 16 + b;
-                    on[b] = (eb < P.nb) && (fl[eb * P.nb + rc / 16] || fl[eb * P.nb + rc / 16 + 1]);
-                    any |= on[b];
-                }
-                if (!any) continue;
-                V br[CB], bi[CB], b2[CB];
-#pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const int64_t x = xw + 16 * c + row;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int r = rc + 8 * kk + i;
-                        const bool ok = (r < P.m) && (x < N);
-                        const float fr = ok ? MM16<S>::to_f(gr[(int64_t)r * N + x]) : 0.0f;
-                        const float fi = ok ? MM16<S>::to_f(gi[(int64_t)r * N + x]) : 0.0f;
-                        br[c][i] = MM16<S>::from_f(fr);
-                        bi[c][i] = MM16<S>::from_f(fi);
-                        b2[c][i] = MM16<S>::from_f(fr * fr + fi * fi);
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    if (!on[b]) continue;
-                    const int64_t off = (int64_t)(ec + 16 * b + row) * P.mp + rc + 8 * kk;
-                    const V va = *reinterpret_cast<const V *>(ar + off);
-                    const V vi = *reinterpret_cast<const V *>(ai + off);
-                    const V vw = *reinterpret_cast<const V *>(wt + off);
-                    const V vn = neg(vi);
-#pragma unroll
-                    for (int c = 0; c < CB; ++c) {
-                        yr[b][c] = MM16<S>::mma(va, br[c], yr[b][c]);
-                        yr[b][c] = MM16<S>::mma(vi, bi[c], yr[b][c]);
-                        yn[b][c] = MM16<S>::mma(va, bi[c], yn[b][c]);
-                        yn[b][c] = MM16<S>::mma(vn, br[c], yn[b][c]);
-                        z[b][c] = MM16<S>::mma(vw, b2[c], z[b][c]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < RB; ++b) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int e = ec + 16 * b + 4 * kk + i;
-#pragma unroll
-                    for (int c = 0; c < CB; ++c) {
-                        const int64_t x = xw + 16 * c + row;
-                        const bool ok = (e < P.m) && (x < N);
-                        const float ge_r = ok ? MM16<S>::to_f(gr[(int64_t)e * N + x]) : 0.0f;
-                        const float ge_i = ok ? MM16<S>::to_f(gi[(int64_t)e * N + x]) : 0.0f;
-                        gp[c] += ge_r * yr[b][c][i] - ge_i * yn[b][c][i];
-                        hp[c] += (ge_r * ge_r + ge_i * ge_i) * z[b][c][i];
-                    }
-                }
-            }
-        }
-        const double gs = (double)gscale[k], as = (double)ascale[k];
-        const double g2 = gs * gs;
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            gacc[c] += (double)gp[c] * (P.cg[k] * g2 * as);
-            hacc[c] += (double)hp[c] * (P.ch[k] * g2 * g2);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        double g = gacc[c], h = hacc[c];
-        g += __shfl_xor(g, 16);
-        h += __shfl_xor(h, 16);
-        g += __shfl_xor(g, 32);
-        h += __shfl_xor(h, 32);
-        const int64_t x = xw + 16 * c + row;
-        if (kk == 0 && x < N) {
-            grad[x] += g;
-            if (hd) hd[x] += h;
-        }
-    }
-}
-
 // Operands of the adjoint: A = W . D (re, im) and W in the storage type,
 // padded to mp x mp with zeros.  For 16-bit types A is divided by ascale[k]
-// = max |W D| (W is 0/1-valued in the inversion, stored unscaled).
+// = max |W D| (1 if that is 0; W is 0/1-valued in the inversion, stored
+// unscaled).
 template <typename T>
 __device__ __forceinline__ T cvt(double v);
 template <>
@@ -273,28 +158,6 @@ template <>
 __device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
 template <>
 __device__ __forceinline__ __half cvt<__half>(double v) { return __float2half((float)v); }
-
-__global__ void k_adj_absmax(int m, const double *__restrict__ d, const double *__restrict__ w,
-                             float *__restrict__ ascale) {
-    // one block per frequency
-    __shared__ double sh[256];
-    const int k = blockIdx.x;
-    const int64_t mm = (int64_t)m * m;
-    double best = 0.0;
-    for (int64_t i = threadIdx.x; i < mm; i += 256) {
-        const int64_t q = (int64_t)k * mm + i;
-        const double wv = w[q];
-        const double re = wv * d[2 * q], im = wv * d[2 * q + 1];
-        best = fmax(best, fmax(fabs(re), fabs(im)));
-    }
-    sh[threadIdx.x] = best;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) ascale[k] = sh[0] > 0.0 ? (float)sh[0] : 1.0f;
-}
 
 // PERMUTE: within every 32-column chunk, receiver 4 s + kk is stored at
 // column 8 kk + s (the operand order of k_adjoint_f32).
@@ -316,7 +179,8 @@ __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, 
             re = wv * d[2 * q];
             im = wv * d[2 * q + 1];
             if (SCALED) {
-                const double inv = 1.0 / (double)ascale[k];
+                const float a = ascale[k];   // 0 when every weight is zero
+                const double inv = a > 0.0f ? 1.0 / (double)a : 1.0;
                 re *= inv;
                 im *= inv;
             }
@@ -332,28 +196,37 @@ __global__ void k_adj_prep(int m, int mp, int nf, const double *__restrict__ d, 
     }
 }
 
-// flags[k][eb][rb] = 1 if any weight of the 16x16 block is nonzero
-__global__ void k_block_flags(int m, int nb, int nf, const double *__restrict__ w, uint8_t *__restrict__ flags) {
-    const int64_t tot = (int64_t)nf * nb * nb;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= tot) return;
-    const int k = (int)(idx / ((int64_t)nb * nb));
-    const int64_t rem = idx - (int64_t)k * nb * nb;
-    const int eb = (int)(rem / nb), rb = (int)(rem - (int64_t)eb * nb);
-    uint8_t any = 0;
-    for (int i = 0; i < 16 && !any; ++i) {
-        const int e = eb * 16 + i;
-        if (e >= m) break;
-        for (int j = 0; j < 16; ++j) {
-            const int r = rb * 16 + j;
-            if (r >= m) break;
-            if (w[((int64_t)k * m + e) * m + r] != 0.0) {
-                any = 1;
-                break;
-            }
+// One workgroup per 16x16 block (eb, rb) and frequency, one thread per
+// entry: flags[k][eb][rb] = 1 if any weight of the block is nonzero, and
+// for 16-bit operands (amax != null) the block's max |W D| (as float bits;
+// max is order-independent) folded into amax[k], which starts at zero.
+__global__ void __launch_bounds__(256) k_adj_blocks(int m, int nb, const double *__restrict__ d,
+                                                    const double *__restrict__ w, uint8_t *__restrict__ flags,
+                                                    unsigned *__restrict__ amax) {
+    __shared__ float sm[4];
+    const int k = blockIdx.y, eb = blockIdx.x / nb, rb = blockIdx.x - (blockIdx.x / nb) * nb;
+    const int e = eb * 16 + (threadIdx.x >> 4), r = rb * 16 + (threadIdx.x & 15);
+    double wv = 0.0, re = 0.0, im = 0.0;
+    if (e < m && r < m) {
+        const int64_t q = ((int64_t)k * m + e) * m + r;
+        wv = w[q];
+        if (amax) {
+            re = wv * d[2 * q];
+            im = wv * d[2 * q + 1];
         }
     }
-    flags[idx] = any;
+    const int any = __syncthreads_or(wv != 0.0);
+    if (threadIdx.x == 0) flags[((int64_t)k * nb + eb) * nb + rb] = any ? 1 : 0;
+    if (!amax) return;
+    float v = (float)fmax(fabs(re), fabs(im));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float b = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+        if (b > 0.0f) atomicMax(amax + k, __float_as_uint(b));
+    }
 }
 
 // ------------------------------------------------------------------ FP32, LDS-staged
@@ -618,6 +491,349 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
     }
 }
 
+// ------------------------------------------------------------------ 16-bit, LDS-staged
+// Backprojection with 16-bit tables on the 16x16x32 matrix cores (FP32
+// accumulation; G and A = W.D pre-scaled per frequency).  The workgroup owns
+// 64 pixels and one frequency; its four waves each take 16 EB emitters and
+// all 64 pixels (four column blocks of 16 pixels), and the workgroup walks the
+// emitters in passes of 64 EB.  The MFMA's B operand needs eight consecutive
+// receivers of one pixel per lane, while the tables keep pixels contiguous:
+// each tile of 32 receivers x 64 pixels is copied into LDS by direct
+// global->LDS loads of four bytes per lane (two rows of 128 bytes per
+// instruction, 8 bytes of padding per row pair), and each lane gathers its
+// eight receivers for four pixels at once with 8-byte LDS reads, splitting
+// the 16-bit halves among four fragments.  Three tile buffers keep two tiles
+// in flight.  The A fragments (eight consecutive receivers of one emitter) are
+// single 16-byte loads from L2, one k-step ahead.
+constexpr int kA16NT = 64, kA16KC = 32;
+constexpr int kA16Pair = 264;                      // bytes per pair of tile rows (2 x 128 + 8)
+constexpr int kA16Arr = (kA16KC / 2) * kA16Pair;   // one array (re or im) of a tile
+#ifndef A16_GRAD_WAVES
+#define A16_GRAD_WAVES 4
+#endif
+constexpr int kA16GradWaves = A16_GRAD_WAVES;   // waves per workgroup of the gradient-only kernel
+constexpr int kA16Buf = 3;                         // tiles c, c + 1, c + 2
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// byte offset of (tile row rl, pixel px) within one array of a tile
+__device__ __forceinline__ int a16_off(int rl, int px) { return (rl >> 1) * kA16Pair + (rl & 1) * 128 + 2 * px; }
+
+// Aligned full tiles (m a multiple of 32, so every row exists): wave w of
+// NW fills row pairs (16 / NW) w .. of both arrays, one pair per
+// instruction.  Lane l of an instruction loads pixels 2 (l % 32) and
+// 2 (l % 32) + 1 of row 2 p + l / 32, which is where its four bytes land;
+// `loff` = (l / 32) N + 2 (l % 32) is that lane's fixed offset from the
+// tile's first pixel in row 2 p.
+template <int NW>
+__device__ __forceinline__ void a16_stage_async(const unsigned short *__restrict__ gr,
+                                                const unsigned short *__restrict__ gi, int64_t N, int rc,
+                                                unsigned loff, unsigned char *sT) {
+    constexpr int PW = (kA16KC / 2) / NW;   // row pairs per wave
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+        const int p = PW * wave + j;
+        const int64_t ro = (int64_t)(rc + 2 * p) * N;   // uniform
+        __builtin_amdgcn_global_load_lds(gr + ro + loff, (lds_void_t *)(sT + p * kA16Pair), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(gi + ro + loff, (lds_void_t *)(sT + kA16Arr + p * kA16Pair), 4, 0, 0);
+    }
+}
+
+// Ragged or odd-width tiles: through registers, zero beyond m and N; the
+// tile is 512 runs of eight pixels ([array][row][run]).
+template <int NW>
+__device__ __forceinline__ void a16_stage_regs(const unsigned short *__restrict__ gr,
+                                               const unsigned short *__restrict__ gi, int m, int64_t N, int rc,
+                                               int64_t x0, unsigned char *sT) {
+#pragma unroll
+    for (int q = threadIdx.x; q < 2 * kA16KC * 8; q += 64 * NW) {
+        const int arr = q >> 8, rl = (q >> 3) & 31, p0 = (q & 7) * 8;
+        const unsigned short *g = arr ? gi : gr;
+        const int r = rc + rl;
+        unsigned short v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t x = x0 + p0 + u;
+            v[u] = (r < m && x < N) ? g[(int64_t)r * N + x] : (unsigned short)0;
+        }
+        unsigned short *d = reinterpret_cast<unsigned short *>(sT + arr * kA16Arr + a16_off(rl, p0));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = v[u];
+    }
+}
+
+// B fragments of the four column blocks at once.  Column block q holds the
+// pixels 4 j + q (j = lane % 16), so lane (j, kk) reads pixels 4 j .. 4 j + 3
+// of rows 8 kk .. 8 kk + 7 with eight 8-byte LDS reads and splits the 16-bit
+// halves among the four fragments.  `base` = a16_off(8 kk, 4 j).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename V>
+__device__ __forceinline__ void a16_frags(const unsigned char *sA, int base, V (&out)[4]) {
+    u32x2 d[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        d[i] = *reinterpret_cast<const u32x2 *>(sA + base + (i >> 1) * kA16Pair + (i & 1) * 128);
+    // byte permutes: the low (0x05040100) or high (0x07060302) halves of
+    // rows 2 h (low half of the result) and 2 h + 1 (high half)
+    u32x4 w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const u32x2 a = d[2 * h], b = d[2 * h + 1];
+        w[0][h] = __builtin_amdgcn_perm(b.x, a.x, 0x05040100u);
+        w[1][h] = __builtin_amdgcn_perm(b.x, a.x, 0x07060302u);
+        w[2][h] = __builtin_amdgcn_perm(b.y, a.y, 0x05040100u);
+        w[3][h] = __builtin_amdgcn_perm(b.y, a.y, 0x07060302u);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = __builtin_bit_cast(V, w[q]);
+}
+
+// |G|^2 of a fragment, rounded to the storage type
+template <typename S, typename V>
+__device__ __forceinline__ V a16_abs2(V br, V bi) {
+    V o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float a = (float)br[i], b = (float)bi[i];
+        o[i] = MM16<S>::from_f(a * a + b * b);
+    }
+    return o;
+}
+
+template <int I>
+using Idx = std::integral_constant<int, I>;
+
+template <typename S, bool HESS, int EB, int NW>
+__global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(AdjParams P, const S *__restrict__ Gr,
+                                                          const S *__restrict__ Gi, const S *__restrict__ Ar,
+                                                          const S *__restrict__ Ai, const S *__restrict__ Wt,
+                                                          const uint8_t *__restrict__ flags,
+                                                          const float *__restrict__ gscale,
+                                                          const float *__restrict__ ascale,
+                                                          double *__restrict__ pg, double *__restrict__ ph) {
+    using V = typename MM16<S>::vec;
+    // Three tile buffers as separate LDS objects, always addressed by a
+    // compile-time index: the compiler can then tell that a direct load into
+    // one buffer does not write the buffer being read, and does not make the
+    // LDS reads wait for it.
+    __shared__ __align__(16) unsigned char sG0[2 * kA16Arr];
+    __shared__ __align__(16) unsigned char sG1[2 * kA16Arr];
+    __shared__ __align__(16) unsigned char sG2[2 * kA16Arr];
+    __shared__ float sred[2][NW][kA16NT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t N = P.N;
+    const int k = blockIdx.y;
+    const int64_t x0 = (int64_t)blockIdx.x * kA16NT;
+    const bool vec = ((N & 1) == 0) && (x0 + kA16NT <= N) && (P.m % kA16KC == 0);   // workgroup-uniform
+    const S *gre = Gr + (int64_t)k * P.m * N;
+    const S *gim = Gi + (int64_t)k * P.m * N;
+    const unsigned short *gr = reinterpret_cast<const unsigned short *>(gre);
+    const unsigned short *gi = reinterpret_cast<const unsigned short *>(gim);
+    const S *ar = Ar + (int64_t)k * P.mp * P.mp;
+    const S *ai = Ai + (int64_t)k * P.mp * P.mp;
+    const S *wt = Wt + (int64_t)k * P.mp * P.mp;
+    const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
+    const int nch = P.mp / kA16KC;
+    const unsigned short *grx = gr + x0, *gix = gi + x0;   // tile origin in row 0
+    const unsigned loff = (unsigned)((lane >> 5) * N + 2 * (lane & 31));
+    const int fbase = a16_off(8 * kk, 4 * row);   // column block q: pixels 4 row + q
+    float gp[4] = {0.0f, 0.0f, 0.0f, 0.0f}, hp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto buf = [&](auto itag) -> unsigned char * {
+        constexpr int I = decltype(itag)::value % kA16Buf;
+        return I == 0 ? sG0 : (I == 1 ? sG1 : sG2);
+    };
+
+    for (int ec = 0; ec < P.mp; ec += 16 * EB * NW) {
+        const int e0 = ec + 16 * EB * wave;
+        f4 yr[EB][4], yn[EB][4], z[EB][4];
+#pragma unroll
+        for (int b = 0; b < EB; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
+        auto stage = [&](int c, unsigned char *dst, auto vtag) {
+            if (decltype(vtag)::value)
+                a16_stage_async<NW>(grx, gix, N, c * kA16KC, loff, dst);
+            else
+                a16_stage_regs<NW>(gr, gi, P.m, N, c * kA16KC, x0, dst);
+        };
+        // A rows beyond mp read row mp - 1 (those blocks are never used), so
+        // every wave issues the same loads whatever its rows; a lane's offset
+        // within a chunk is fixed for the pass
+        unsigned aoff[EB];
+#pragma unroll
+        for (int b = 0; b < EB; ++b) aoff[b] = (unsigned)(min(e0 + 16 * b + row, P.mp - 1) * P.mp + 8 * kk);
+        auto load_a = [&](int c, V (&va)[EB], V (&vi)[EB], V (&vw)[EB]) {
+            const int co = c * kA16KC;   // uniform
+#pragma unroll
+            for (int b = 0; b < EB; ++b) {
+                va[b] = *reinterpret_cast<const V *>(ar + co + aoff[b]);
+                vi[b] = *reinterpret_cast<const V *>(ai + co + aoff[b]);
+                if (HESS) vw[b] = *reinterpret_cast<const V *>(wt + co + aoff[b]);
+            }
+        };
+        // Chunks of 32 receivers in which a 16-row block of this wave has a
+        // nonzero weight, as wave-uniform bit masks (nch <= 128), so that
+        // the k-loop itself issues no flag loads.
+        uint64_t cm[2] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < EB; ++b)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int eb = (e0 >> 4) + b, c = 64 * h + lane;
+                const bool on =
+                    eb < P.nb && c < nch && (fl[eb * P.nb + 2 * c] | fl[eb * P.nb + 2 * c + 1]) != 0;
+                cm[h] |= __ballot(on);
+            }
+        // One k-step on tile c, held in buffer c mod 3: wait for tile c and
+        // A(c), then issue A(c + 1) and tile c + 2, then the MFMAs of tile c.
+        // The issue order per wave is A(c), tile c + 1, A(c + 1), tile
+        // c + 2, ..., so only the direct loads of tile c + 1 may still be
+        // outstanding at the wait.  A block whose weights are zero in this
+        // chunk has A = 0 there, so all blocks are computed when any is on.
+        auto kstep = [&](int c, auto itag, V (&va)[EB], V (&vi)[EB], V (&vw)[EB], V (&na)[EB], V (&ni)[EB],
+                         V (&nw)[EB], auto vtag, auto full) {
+            constexpr int I = decltype(itag)::value;
+            constexpr bool FULL = decltype(full)::value;   // c + 2 < nch
+            if (FULL || c + 1 < nch)
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * (kA16KC / 2) / NW));   // tile c + 1
+            else
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            lds_barrier();
+            load_a(min(c + 1, nch - 1), na, ni, nw);
+            // A(c + 1) is issued before the tile's direct loads: the next
+            // step's vmcnt wait then covers it, and the compiler (which takes
+            // direct loads and register loads as completing out of order)
+            // adds no wait of its own
+            __builtin_amdgcn_sched_barrier(0);
+            if (FULL || c + 2 < nch) stage(c + 2, buf(Idx<I + 2>()), vtag);
+            if (!(((c < 64 ? cm[0] : cm[1]) >> (c & 63)) & 1)) return;
+            const unsigned char *sb = buf(Idx<I>());
+            V brs[4], bis[4];
+            a16_frags<V>(sb, fbase, brs);
+            a16_frags<V>(sb + kA16Arr, fbase, bis);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const V br = brs[cb], bi = bis[cb];
+                V b2;
+                if (HESS) b2 = a16_abs2<S, V>(br, bi);
+#pragma unroll
+                for (int b = 0; b < EB; ++b) {
+                    yr[b][cb] = MM16<S>::mma(va[b], br, yr[b][cb]);
+                    yr[b][cb] = MM16<S>::mma(vi[b], bi, yr[b][cb]);
+                    yn[b][cb] = MM16<S>::mma(va[b], bi, yn[b][cb]);
+                    yn[b][cb] = MM16<S>::mma(neg(vi[b]), br, yn[b][cb]);
+                    if (HESS) z[b][cb] = MM16<S>::mma(vw[b], b2, z[b][cb]);
+                }
+            }
+        };
+        // The k-loop, specialised on the staging path (workgroup-uniform) and
+        // unrolled by six so that the buffer index (period 3) and the A
+        // registers (period 2) are compile-time at every step.  The steady
+        // state has no conditional steps, which keeps the compiler's own
+        // load-counter waits exact; the last two to seven steps follow.
+        auto kloop = [&](auto vtag) {
+            using F = std::true_type;
+            using T = std::false_type;
+            V va[EB], vi[EB], vw[EB], na[EB], ni[EB], nw[EB];
+            lds_barrier();   // the previous pass is done with the tile buffers
+            stage(0, sG0, vtag);
+            load_a(0, va, vi, vw);
+            if (nch > 1) stage(1, sG1, vtag);
+            int c = 0;
+            for (; c + 8 <= nch; c += 6) {
+                kstep(c, Idx<0>(), va, vi, vw, na, ni, nw, vtag, F());
+                kstep(c + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, F());
+                kstep(c + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, F());
+                kstep(c + 3, Idx<0>(), na, ni, nw, va, vi, vw, vtag, F());
+                kstep(c + 4, Idx<1>(), va, vi, vw, na, ni, nw, vtag, F());
+                kstep(c + 5, Idx<2>(), na, ni, nw, va, vi, vw, vtag, F());
+            }
+            if (c < nch) kstep(c, Idx<0>(), va, vi, vw, na, ni, nw, vtag, T());
+            if (c + 1 < nch) kstep(c + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, T());
+            if (c + 2 < nch) kstep(c + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, T());
+            if (c + 3 < nch) kstep(c + 3, Idx<0>(), na, ni, nw, va, vi, vw, vtag, T());
+            if (c + 4 < nch) kstep(c + 4, Idx<1>(), va, vi, vw, na, ni, nw, vtag, T());
+            if (c + 5 < nch) kstep(c + 5, Idx<2>(), na, ni, nw, va, vi, vw, vtag, T());
+            if (c + 6 < nch) kstep(c + 6, Idx<0>(), va, vi, vw, na, ni, nw, vtag, T());
+        };
+        if (vec)
+            kloop(std::true_type());
+        else
+            kloop(std::false_type());
+        // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e (Y =
+        // A conj(G)); a lane's four pixels 4 row .. 4 row + 3 of a row are one
+        // 8-byte load
+        const bool wide = ((N & 3) == 0) && (x0 + 4 * row + 4 <= N);
+#pragma unroll
+        for (int b = 0; b < EB; ++b) {
+            if (e0 + 16 * b >= P.m) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = e0 + 16 * b + 4 * kk + i;
+                const int64_t xb = x0 + 4 * row;
+                float ger[4], gei[4];
+                if (e < P.m && wide) {
+                    const u32x2 vr = *reinterpret_cast<const u32x2 *>(gr + (int64_t)e * N + xb);
+                    const u32x2 vi = *reinterpret_cast<const u32x2 *>(gi + (int64_t)e * N + xb);
+                    ger[0] = MM16<S>::bits_to_f(vr.x);
+                    ger[1] = MM16<S>::bits_to_f(vr.x >> 16);
+                    ger[2] = MM16<S>::bits_to_f(vr.y);
+                    ger[3] = MM16<S>::bits_to_f(vr.y >> 16);
+                    gei[0] = MM16<S>::bits_to_f(vi.x);
+                    gei[1] = MM16<S>::bits_to_f(vi.x >> 16);
+                    gei[2] = MM16<S>::bits_to_f(vi.y);
+                    gei[3] = MM16<S>::bits_to_f(vi.y >> 16);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = (e < P.m) && (xb + q < N);
+                        ger[q] = ok ? MM16<S>::bits_to_f(gr[(int64_t)e * N + xb + q]) : 0.0f;
+                        gei[q] = ok ? MM16<S>::bits_to_f(gi[(int64_t)e * N + xb + q]) : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    gp[cb] += ger[cb] * yr[b][cb][i] - gei[cb] * yn[b][cb][i];
+                    if (HESS) hp[cb] += (ger[cb] * ger[cb] + gei[cb] * gei[cb]) * z[b][cb][i];
+                }
+            }
+        }
+    }
+    // the four lane groups of a column, then the waves, in a fixed order
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        float g = gp[cb], h = hp[cb];
+        g += __shfl_xor(g, 16);
+        h += __shfl_xor(h, 16);
+        g += __shfl_xor(g, 32);
+        h += __shfl_xor(h, 32);
+        if (kk == 0) {
+            sred[0][wave][4 * row + cb] = g;
+            sred[1][wave][4 * row + cb] = h;
+        }
+    }
+    __syncthreads();
+    if (tid < kA16NT) {
+        const int64_t x = x0 + tid;
+        if (x < N) {
+            const double gs = (double)gscale[k], as = ascale[k] > 0.0f ? (double)ascale[k] : 1.0;
+            const double g2 = gs * gs;
+            double g = 0.0, h = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                g += (double)sred[0][w][tid];
+                h += (double)sred[1][w][tid];
+            }
+            pg[(int64_t)k * N + x] = g * (P.cg[k] * g2 * as);
+            if (HESS) ph[(int64_t)k * N + x] = h * (P.ch[k] * g2 * g2);
+        }
+    }
+}
+
 // grad += sum_k pg[k], hd += sum_k ph[k] in frequency order.
 __global__ void k_adj_sum(int64_t N, int nf, const double *__restrict__ pg, const double *__restrict__ ph,
                           double *__restrict__ grad, double *__restrict__ hd) {
@@ -696,10 +912,10 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
     const int64_t tot = (int64_t)nf * P.mp * P.mp;
     const unsigned bp = (unsigned)std::min<int64_t>(blocks_for(tot, 256), 8192);
     const bool scaled = (dt == RB_BF16 || dt == RB_F16);
-    if (scaled) {
-        k_adj_absmax<<<nf, 256, 0, st>>>(g->m, d_res, w_data, w.ascale);
-        RB_LAUNCHED();
-    }
+    if (scaled) RB_TRY(fill_f32(w.ascale, 0.0f, nf, st));
+    k_adj_blocks<<<dim3(P.nb * P.nb, nf), 256, 0, st>>>(g->m, P.nb, d_res, w_data, w.flags,
+                                                        scaled ? reinterpret_cast<unsigned *>(w.ascale) : nullptr);
+    RB_LAUNCHED();
     switch (dt) {
         case RB_F64:
             k_adj_prep<double, false><<<bp, 256, 0, st>>>(g->m, P.mp, nf, d_res, w_data, nullptr, (double *)w.Ar,
@@ -719,9 +935,6 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
                                                          (__half *)w.Ai, (__half *)w.Wt);
             break;
     }
-    RB_LAUNCHED();
-    const int64_t nfl = (int64_t)nf * P.nb * P.nb;
-    k_block_flags<<<blocks_for(nfl, 256), 256, 0, st>>>(g->m, P.nb, nf, w_data, w.flags);
     RB_LAUNCHED();
     switch (dt) {
         case RB_F64: {
@@ -745,19 +958,26 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
             break;
         }
-        case RB_BF16: {
-            const unsigned nb = blocks_for(P.N, 64 * 2);
-            k_adjoint16<__hip_bfloat16, 4, 2><<<nb, 256, 0, st>>>(
-                P, (const __hip_bfloat16 *)G_re, (const __hip_bfloat16 *)G_im, (const __hip_bfloat16 *)w.Ar,
-                (const __hip_bfloat16 *)w.Ai, (const __hip_bfloat16 *)w.Wt, w.flags, gscale, w.ascale, grad, hdiag);
-            break;
-        }
+        case RB_BF16:
         case RB_F16: {
-            const unsigned nb = blocks_for(P.N, 64 * 2);
-            k_adjoint16<__half, 4, 2><<<nb, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im,
-                                                          (const __half *)w.Ar, (const __half *)w.Ai,
-                                                          (const __half *)w.Wt, w.flags, gscale, w.ascale, grad,
-                                                          hdiag);
+            dim3 ga(blocks_for(P.N, kA16NT), nf);
+            auto go = [&](auto tag) {
+                using S = decltype(tag);
+                const S *gr = (const S *)G_re, *gi = (const S *)G_im;
+                const S *ar = (const S *)w.Ar, *ai = (const S *)w.Ai, *wt = (const S *)w.Wt;
+                if (hdiag)
+                    k_adjoint16_lds<S, true, 2, 4><<<ga, 256, 0, st>>>(P, gr, gi, ar, ai, wt, w.flags, gscale,
+                                                                       w.ascale, w.pg, w.ph);
+                else
+                    k_adjoint16_lds<S, false, 2, kA16GradWaves><<<ga, 64 * kA16GradWaves, 0, st>>>(
+                        P, gr, gi, ar, ai, wt, w.flags, gscale, w.ascale, w.pg, w.ph);
+            };
+            if (dt == RB_BF16)
+                go(__hip_bfloat16());
+            else
+                go(__half());
+            RB_LAUNCHED();
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
             break;
         }
     }

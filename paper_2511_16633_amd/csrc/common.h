@@ -98,6 +98,19 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
     return x * q + (x < r ? x : r) + s;
 }
 
+// Immediate of s_waitcnt that waits until at most n vector-memory operations
+// of the wave are outstanding and leaves the other counters alone (CDNA
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).  Direct
+// global->LDS loads count here, so this orders them with later LDS reads.
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// Workgroup barrier that orders LDS accesses only.  Unlike __syncthreads()
+// it does not wait for the wave's global loads still in flight (direct
+// global->LDS loads filling another buffer are ordered with vmcnt waits).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Fill kernels are used instead of hipMemsetAsync so that a caller may
 // capture the library's work into a HIP graph.
 rb_status fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);

@@ -89,74 +89,6 @@ __global__ void __launch_bounds__(256) k_forward(FwdParams P, const T *__restric
     }
 }
 
-template <typename S>
-__global__ void __launch_bounds__(256) k_forward16(FwdParams P, const S *__restrict__ Gr, const S *__restrict__ Gi,
-                                                   const double *__restrict__ delta,
-                                                   const double *__restrict__ dmax, float *__restrict__ part) {
-    using V = typename MM16<S>::vec;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row = lane & 15, kk = lane >> 4;
-    int te, tr;
-    tri_tile(blockIdx.x, P.ntl, te, tr);
-    const int split = blockIdx.y, k = blockIdx.z;
-    const int64_t N = P.N;
-    const S *gr = Gr + (int64_t)k * P.m * N;
-    const S *gi = Gi + (int64_t)k * P.m * N;
-    const int e = te * 64 + 16 * wave + row;
-    const int64_t ks = (int64_t)split * P.kchunk;
-    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
-    const double inv_d = dmax[0] > 0.0 ? 1.0 / dmax[0] : 0.0;
-    f4 re[4], im[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) re[c] = im[c] = f4{0, 0, 0, 0};
-    for (int64_t xc = ks; xc < ke; xc += 32) {
-        V a_r, a_i, a_n;
-        float dl[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int64_t x = xc + 8 * kk + i;
-            const bool okx = x < ke;
-            dl[i] = okx ? (float)(delta[x] * inv_d) : 0.0f;
-            const bool ok = okx && e < P.m;
-            const float vr = ok ? MM16<S>::to_f(gr[(int64_t)e * N + x]) : 0.0f;
-            const float vi = ok ? MM16<S>::to_f(gi[(int64_t)e * N + x]) : 0.0f;
-            a_r[i] = MM16<S>::from_f(vr);
-            a_i[i] = MM16<S>::from_f(vi);
-            a_n[i] = MM16<S>::from_f(-vi);
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int r = tr * 64 + 16 * c + row;
-            V b_r, b_i;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int64_t x = xc + 8 * kk + i;
-                const bool ok = (x < ke) && (r < P.m);
-                const float vr = ok ? MM16<S>::to_f(gr[(int64_t)r * N + x]) : 0.0f;
-                const float vi = ok ? MM16<S>::to_f(gi[(int64_t)r * N + x]) : 0.0f;
-                b_r[i] = MM16<S>::from_f(vr * dl[i]);
-                b_i[i] = MM16<S>::from_f(vi * dl[i]);
-            }
-            re[c] = MM16<S>::mma(a_r, b_r, re[c]);
-            re[c] = MM16<S>::mma(a_n, b_i, re[c]);
-            im[c] = MM16<S>::mma(a_r, b_i, im[c]);
-            im[c] = MM16<S>::mma(a_i, b_r, im[c]);
-        }
-    }
-    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int r = tr * 64 + 16 * c + row;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ee = te * 64 + 16 * wave + 4 * kk + i;
-            const int64_t o = ((int64_t)ee * P.mp + r) * 2;
-            pp[o] = re[c][i];
-            pp[o + 1] = im[c][i];
-        }
-    }
-}
-
 // d[k][e][r] = c_k * sum_split part (fixed order), read from the upper triangle.
 template <typename T>
 __global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const float *__restrict__ gscale,
@@ -201,6 +133,19 @@ __global__ void k_absmax_f64(const double *__restrict__ v, int64_t n, double *__
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Workgroup -> (tile, split, frequency) for the flat grid of the 16-bit
+// kernel.  The tiles of one pixel split read the same pixel range of G, so
+// consecutive logical ids (tile fastest) are kept on one XCD and its L2.
+__device__ __forceinline__ void fwd_block(const FwdParams &P, int &te, int &tr, int &split, int &k) {
+    const int64_t nblk = (int64_t)P.ntri * P.nsplit * P.nf;
+    const int64_t L = xcd_remap(blockIdx.x, nblk);
+    const int t = (int)(L % P.ntri);
+    const int64_t rest = L / P.ntri;
+    split = (int)(rest % P.nsplit);
+    k = (int)(rest / P.nsplit);
+    tri_tile(t, P.ntl, te, tr);
 }
 
 // Forward.  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
@@ -362,6 +307,168 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
     }
 }
 
+// ------------------------------------------------------------------ 16-bit, LDS-staged
+// Forward with 16-bit tables on the 16x16x32 matrix cores (FP32
+// accumulation), tiled as the FP32 kernel: a 64 x 64 (e, r) tile per
+// workgroup, waves 2 x 2 of 32 x 32, 32 pixels per k-step.  Both operands
+// take eight consecutive pixels of one row per lane, which the tables store
+// contiguously, so a thread stages eight pixels of one row of G_e and of
+// G_r delta (delta pre-scaled to float) with 16-byte loads, and a fragment
+// is one 16-byte LDS read.  The four 16-byte chunks of a 64-byte tile row
+// are XOR-swizzled by (row / 2) mod 4, which puts the reads of a fragment
+// on distinct banks.  Tiles are double buffered.
+constexpr int kF16KC = 32, kF16Arr = 64 * kF16KC * 2;   // one array of a tile (bytes)
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int f16_off(int row, int ch) { return row * 64 + 16 * (ch ^ ((row >> 1) & 3)); }
+
+// out[x] = delta[x] / max |delta| as float (0 if delta is zero)
+__global__ void k_delta_f32(int64_t N, const double *__restrict__ delta, const double *__restrict__ dmax,
+                            float *__restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const double inv = dmax[0] > 0.0 ? 1.0 / dmax[0] : 0.0;
+    out[x] = (float)(delta[x] * inv);
+}
+
+struct F16Stage {
+    u32x4 ar, ai, br, bi;
+    f4 d0, d1;
+};
+
+__device__ __forceinline__ void f16_stage_load(const unsigned short *__restrict__ gr,
+                                               const unsigned short *__restrict__ gi,
+                                               const float *__restrict__ df, int m, int64_t N, int e_row,
+                                               int r_row, int64_t xs, int64_t ke, bool vec, F16Stage &v) {
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    if (vec) {
+        v.ar = e_row < m ? *reinterpret_cast<const u32x4 *>(gr + (int64_t)e_row * N + xs) : z;
+        v.ai = e_row < m ? *reinterpret_cast<const u32x4 *>(gi + (int64_t)e_row * N + xs) : z;
+        v.br = r_row < m ? *reinterpret_cast<const u32x4 *>(gr + (int64_t)r_row * N + xs) : z;
+        v.bi = r_row < m ? *reinterpret_cast<const u32x4 *>(gi + (int64_t)r_row * N + xs) : z;
+        v.d0 = *reinterpret_cast<const f4 *>(df + xs);
+        v.d1 = *reinterpret_cast<const f4 *>(df + xs + 4);
+    } else {
+        unsigned short a_r[8], a_i[8], b_r[8], b_i[8];
+        float d[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t x = xs + q;
+            const bool okx = x < ke;
+            const bool oka = okx && e_row < m, okb = okx && r_row < m;
+            a_r[q] = oka ? gr[(int64_t)e_row * N + x] : (unsigned short)0;
+            a_i[q] = oka ? gi[(int64_t)e_row * N + x] : (unsigned short)0;
+            b_r[q] = okb ? gr[(int64_t)r_row * N + x] : (unsigned short)0;
+            b_i[q] = okb ? gi[(int64_t)r_row * N + x] : (unsigned short)0;
+            d[q] = okx ? df[x] : 0.0f;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            v.ar[h] = a_r[2 * h] | ((unsigned)a_r[2 * h + 1] << 16);
+            v.ai[h] = a_i[2 * h] | ((unsigned)a_i[2 * h + 1] << 16);
+            v.br[h] = b_r[2 * h] | ((unsigned)b_r[2 * h + 1] << 16);
+            v.bi[h] = b_i[2 * h] | ((unsigned)b_i[2 * h + 1] << 16);
+        }
+        v.d0 = f4{d[0], d[1], d[2], d[3]};
+        v.d1 = f4{d[4], d[5], d[6], d[7]};
+    }
+}
+
+// eight 16-bit values times delta, rounded back to the storage type
+template <typename S, typename V>
+__device__ __forceinline__ u32x4 f16_scale(u32x4 raw, f4 d0, f4 d1) {
+    const V v = __builtin_bit_cast(V, raw);
+    V o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = MM16<S>::from_f((float)v[i] * (i < 4 ? d0[i] : d1[i - 4]));
+    return __builtin_bit_cast(u32x4, o);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *__restrict__ Gr,
+                                                          const S *__restrict__ Gi, const float *__restrict__ df,
+                                                          float *__restrict__ part) {
+    using V = typename MM16<S>::vec;
+    __shared__ __align__(16) unsigned char sA[2][2 * kF16Arr];   // [buffer][re, im] G_e rows
+    __shared__ __align__(16) unsigned char sB[2][2 * kF16Arr];   // [buffer][re, im] G_r delta rows
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wr = wave & 1;
+    int te, tr, split, k;
+    fwd_block(P, te, tr, split, k);
+    const int64_t N = P.N;
+    const unsigned short *gr = reinterpret_cast<const unsigned short *>(Gr + (int64_t)k * P.m * N);
+    const unsigned short *gi = reinterpret_cast<const unsigned short *>(Gi + (int64_t)k * P.m * N);
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const int nch = (int)((ke - ks + kF16KC - 1) / kF16KC);
+    const int srow = tid >> 2, sch = tid & 3;
+    const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
+    const int so = f16_off(srow, sch);
+    f4 re[2][2], im[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) re[b][c] = im[b][c] = f4{0, 0, 0, 0};
+    F16Stage stg;
+    auto vec_ok = [&](int64_t xc) { return ((N & 7) == 0) && (xc + kF16KC <= ke); };
+    auto store = [&](int buf) {
+        *reinterpret_cast<u32x4 *>(sA[buf] + so) = stg.ar;
+        *reinterpret_cast<u32x4 *>(sA[buf] + kF16Arr + so) = stg.ai;
+        *reinterpret_cast<u32x4 *>(sB[buf] + so) = f16_scale<S, V>(stg.br, stg.d0, stg.d1);
+        *reinterpret_cast<u32x4 *>(sB[buf] + kF16Arr + so) = f16_scale<S, V>(stg.bi, stg.d0, stg.d1);
+    };
+    if (nch > 0) {
+        f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, ks + 8 * sch, ke, vec_ok(ks), stg);
+        store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        const int64_t xn = ks + (int64_t)(c + 1) * kF16KC;
+        if (c + 1 < nch) f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, xn + 8 * sch, ke, vec_ok(xn), stg);
+        V a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ra = 32 * we + 16 * b + row, rb = 32 * wr + 16 * b + row;
+            a_r[b] = *reinterpret_cast<const V *>(sA[buf] + f16_off(ra, kk));
+            a_i[b] = *reinterpret_cast<const V *>(sA[buf] + kF16Arr + f16_off(ra, kk));
+            a_n[b] = neg(a_i[b]);
+            b_r[b] = *reinterpret_cast<const V *>(sB[buf] + f16_off(rb, kk));
+            b_i[b] = *reinterpret_cast<const V *>(sB[buf] + kF16Arr + f16_off(rb, kk));
+        }
+        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                re[b][cb] = MM16<S>::mma(a_r[b], b_r[cb], re[b][cb]);
+                re[b][cb] = MM16<S>::mma(a_n[b], b_i[cb], re[b][cb]);
+                im[b][cb] = MM16<S>::mma(a_r[b], b_i[cb], im[b][cb]);
+                im[b][cb] = MM16<S>::mma(a_i[b], b_r[cb], im[b][cb]);
+            }
+        if (c + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int r = tr * 64 + 32 * wr + 16 * cb + row;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ee = te * 64 + 32 * we + 16 * b + 4 * kk + i;
+                const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+                pp[o] = re[b][cb][i];
+                pp[o + 1] = im[b][cb][i];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -407,10 +514,27 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
     return P;
 }
 
+// workspace: max |delta|, the split partials, and (16-bit) delta as float
+struct FwdWs {
+    double *dmax;
+    void *part;
+    float *df;
+};
+
+static FwdWs carve_fwd(Carver &c, const FwdParams &P, rb_dtype dt) {
+    const size_t es = dt == RB_F64 ? 8 : 4;
+    FwdWs w;
+    w.dmax = c.take<double>(1);
+    w.part = c.take<char>((size_t)P.nsplit * P.nf * P.mp * P.mp * 2 * es);
+    w.df = (dt == RB_BF16 || dt == RB_F16) ? c.take<float>((size_t)P.N + 8) : nullptr;
+    return w;
+}
+
 size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
     FwdParams P = fwd_params(g, nullptr, nf, dt);
-    const size_t es = dt == RB_F64 ? 8 : 4;
-    return (size_t)P.nsplit * nf * P.mp * P.mp * 2 * es + 2 * 256 + 256;
+    Carver c(nullptr, 0);
+    carve_fwd(c, P, dt);
+    return c.used + 256;
 }
 
 rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
@@ -422,39 +546,42 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
     }
     FwdParams P = fwd_params(g, freqs, nf, dt);
     Carver c(ws, ws_bytes);
-    double *dmax = c.take<double>(1);
-    const size_t es = dt == RB_F64 ? 8 : 4;
-    void *part = c.take<char>((size_t)P.nsplit * nf * P.mp * P.mp * 2 * es);
-    dim3 grid(P.ntri, P.nsplit, nf);
+    FwdWs w = carve_fwd(c, P, dt);
+    const unsigned nblk = (unsigned)((int64_t)P.ntri * P.nsplit * nf);
     const int64_t tot = (int64_t)nf * P.m * P.m;
     switch (dt) {
-        case RB_F64:
+        case RB_F64: {
+            dim3 grid(P.ntri, P.nsplit, nf);
             k_forward<double><<<grid, 256, 0, st>>>(P, (const double *)G_re, (const double *)G_im, delta,
-                                                    (double *)part);
+                                                    (double *)w.part);
             RB_LAUNCHED();
-            k_forward_reduce<double><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const double *)part, nullptr,
+            k_forward_reduce<double><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const double *)w.part, nullptr,
                                                                            nullptr, d_out);
             break;
+        }
         case RB_F32:
-            k_forward_f32<<<grid, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, delta, (float *)part);
+            k_forward_f32<<<dim3(P.ntri, P.nsplit, nf), 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
+                                                                      delta, (float *)w.part);
             RB_LAUNCHED();
-            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, nullptr,
-                                                                          d_out);
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)w.part, gscale,
+                                                                          nullptr, d_out);
             break;
         case RB_BF16:
         case RB_F16:
-            k_absmax_f64<<<1, 1024, 0, st>>>(delta, P.N, dmax);
+            k_absmax_f64<<<1, 1024, 0, st>>>(delta, P.N, w.dmax);
+            RB_LAUNCHED();
+            k_delta_f32<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, delta, w.dmax, w.df);
             RB_LAUNCHED();
             if (dt == RB_BF16)
-                k_forward16<__hip_bfloat16><<<grid, 256, 0, st>>>(P, (const __hip_bfloat16 *)G_re,
-                                                                  (const __hip_bfloat16 *)G_im, delta, dmax,
-                                                                  (float *)part);
+                k_forward16_lds<__hip_bfloat16><<<nblk, 256, 0, st>>>(P, (const __hip_bfloat16 *)G_re,
+                                                                      (const __hip_bfloat16 *)G_im, w.df,
+                                                                      (float *)w.part);
             else
-                k_forward16<__half><<<grid, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im, delta,
-                                                          dmax, (float *)part);
+                k_forward16_lds<__half><<<nblk, 256, 0, st>>>(P, (const __half *)G_re, (const __half *)G_im,
+                                                              w.df, (float *)w.part);
             RB_LAUNCHED();
-            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)part, gscale, dmax,
-                                                                          d_out);
+            k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)w.part, gscale,
+                                                                          w.dmax, d_out);
             break;
     }
     RB_LAUNCHED();

@@ -45,6 +45,7 @@ struct MM16<__hip_bfloat16> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
     __device__ __forceinline__ static float to_f(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ __forceinline__ static float bits_to_f(unsigned b) { return __uint_as_float((b & 0xffffu) << 16); }
     __device__ __forceinline__ static __bf16 from_f(float v) {
         __hip_bfloat16 b = __float2bfloat16(v);
         return *reinterpret_cast<__bf16 *>(&b);
@@ -57,15 +58,19 @@ struct MM16<__half> {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
     __device__ __forceinline__ static float to_f(__half v) { return __half2float(v); }
+    __device__ __forceinline__ static float bits_to_f(unsigned b) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+    }
     __device__ __forceinline__ static _Float16 from_f(float v) { return (_Float16)v; }
 };
 
-typedef short s8 __attribute__((ext_vector_type(8)));
-// sign flip of eight 16-bit floats (bf16 and fp16 keep the sign in bit 15)
+typedef unsigned int u4x32 __attribute__((ext_vector_type(4)));
+// sign flip of eight 16-bit floats (bf16 and fp16 keep the sign in bit 15),
+// two per 32-bit operation
 template <typename V>
 __device__ __forceinline__ V neg(V v) {
-    s8 b = __builtin_bit_cast(s8, v);
-    b ^= (short)0x8000;
+    u4x32 b = __builtin_bit_cast(u4x32, v);
+    b ^= 0x80008000u;
     return __builtin_bit_cast(V, b);
 }
 
