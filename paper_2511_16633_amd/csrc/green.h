@@ -12,6 +12,28 @@ struct GreenParams {
 };
 
 GreenParams green_params(const double *freqs, int nf, double y_pow);
+
+// G at one table entry (T = t, absorption b) and frequency k, with the
+// amplitude factor `amag` (a omega^-1/2, or a / max(a) for 16-bit storage):
+// the phase is reduced to [0, 1) cycles in FP64 before sincospi.
+__device__ __forceinline__ void green_value(const GreenParams &P, int k, double t, double amag, double b,
+                                            double &re, double &im) {
+    const double cycles = P.f[k] * t + 0.125;
+    const double frac = cycles - floor(cycles);
+    double sn, cs;
+    sincospi(2.0 * frac, &sn, &cs);
+    const double mag = amag * exp(-b * P.fy[k]);
+    re = mag * cs;
+    im = mag * sn;
+}
+
+// Green's tables written by the rasteriser's write pass in place of the
+// T/amp/att tables (32/64-bit storage): G [nf][m][N].
+struct GreenOut {
+    GreenParams P;
+    rb_dtype dt;   // RB_F32 or RB_F64
+    void *Gr, *Gi;
+};
 size_t green_workspace_bytes();
 // Tables [n] -> planar G [nf][n] of dtype; scale [nf] (nullable for 32/64-bit).
 rb_status build_green_impl(const double *T, const float *amp, const float *att, int64_t n,

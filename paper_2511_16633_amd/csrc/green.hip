@@ -42,16 +42,8 @@ __global__ void __launch_bounds__(256) k_green(GreenParams P, const double *__re
     const double inv_amax = SCALED ? 1.0 / (double)amp_max[0] : 1.0;
     for (int k = 0; k < P.nf; ++k) {
         double re = 0.0, im = 0.0;
-        if (cov) {
-            const double cycles = P.f[k] * t + 0.125;
-            const double frac = cycles - floor(cycles);
-            double sn, cs;
-            sincospi(2.0 * frac, &sn, &cs);
-            // 16-bit storage holds G / (max(a) omega^-1/2): |stored| <= 1
-            const double mag = SCALED ? (a * inv_amax) * exp(-b * P.fy[k]) : a * P.rsq[k] * exp(-b * P.fy[k]);
-            re = mag * cs;
-            im = mag * sn;
-        }
+        // 16-bit storage holds G / (max(a) omega^-1/2): |stored| <= 1
+        if (cov) green_value(P, k, t, SCALED ? a * inv_amax : a * P.rsq[k], b, re, im);
         Gr[(int64_t)k * n + i] = store_cast<S>(re);
         Gi[(int64_t)k * n + i] = store_cast<S>(im);
     }

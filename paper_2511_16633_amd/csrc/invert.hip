@@ -15,6 +15,7 @@
 // result does not depend on scheduling.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "born.h"
 #include "common.h"
@@ -24,7 +25,8 @@ namespace rb {
 
 size_t trace_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int batch);
 rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const double *slowness,
-                          const double *alpha0, const rb_tables *out, void *ws, size_t ws_bytes, hipStream_t st);
+                          const double *alpha0, const rb_tables *out, void *ws, size_t ws_bytes, hipStream_t st,
+                          uint8_t *cover, const GreenOut *gout);
 
 namespace {
 
@@ -59,103 +61,211 @@ __global__ void k_residual(GreenParams G, int m, const double *__restrict__ Trx,
     D[2 * idx + 1] = pmeas[2 * idx + 1] - pi;
 }
 
-__device__ __forceinline__ bool selected(int64_t i, int m, int dmin) {
-    const int e = (int)(i / m), r = (int)(i - (int64_t)e * m);
+// Receiver selection of pair (e, r): circular distance at least dmin.
+__device__ __forceinline__ bool selected_er(int e, int r, int m, int dmin) {
     int d = e > r ? e - r : r - e;
     d = d < m - d ? d : m - d;
     return d >= dmin;
 }
 
+constexpr int kWThreads = 1024;
+
+// Exclusive prefix sum of v over the kWThreads threads of the block, in
+// thread order (wave scans by shuffles, then the 16 wave totals); `total`
+// receives the block sum.  Every thread of the block must call it.
+__device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t *s_w, int64_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int64_t t = lane < kWThreads / 64 ? s_w[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < kWThreads / 64; o <<= 1) {
+            const int64_t y = __shfl_up(t, o);
+            if (lane >= o) t += y;
+        }
+        if (lane < kWThreads / 64) s_w[lane] = t;   // inclusive wave prefixes
+    }
+    __syncthreads();
+    const int64_t base = w > 0 ? s_w[w - 1] : 0;
+    total = s_w[kWThreads / 64 - 1];
+    __syncthreads();   // s_w may be reused
+    return base + x - v;
+}
+
 // Data weights for one frequency per block: receiver selection, then zero the
 // kzero selected pairs with the largest |p_meas|^2 (ties to the smaller flat
-// index).  The k-th largest key is found by an 8-bit radix select on the
-// IEEE bits of |p|^2 (non-negative doubles order like their bit patterns).
-constexpr int kWThreads = 1024;
+// index).  The k-th largest is found by a radix select on the IEEE bits of
+// |p|^2 (non-negative doubles order like their bit patterns), stored as
+// key = bits + 1 for a selected pair and 0 for the others, so the passes
+// need no selection test and key 0 never reaches the threshold.  Digits are
+// the 12 sign/exponent bits, then 13 mantissa bits at a time (five passes).
+// Thread t owns the flat indices t, t + T, t + 2T, ... (T = kWThreads), so
+// every access is coalesced; the keys of eight stripes are loaded together.
+// The keys are parked in W, which receives the weights at the end.  A wave
+// whose active lanes share a digit adds them with one LDS atomic.  Ranks
+// among keys equal to the threshold are needed only when the threshold
+// splits them; then the ties are ranked in flat-index order by block scans
+// over the stripes.
+constexpr int kWBins = 1 << 13;
+
 __global__ void __launch_bounds__(kWThreads) k_weights(int m, int dmin, int64_t kzero,
                                                        const double *__restrict__ pmeas,
                                                        double *__restrict__ W) {
-    __shared__ unsigned hist[256];
+    __shared__ unsigned hist[kWBins];
+    __shared__ int64_t s_w[kWThreads / 64];
     __shared__ uint64_t s_pref;
     __shared__ int64_t s_rem;
-    __shared__ int64_t scan[kWThreads];
-    const int k = blockIdx.x, tid = threadIdx.x;
+    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int64_t mm = (int64_t)m * m;
     const double *pk = pmeas + 2 * (int64_t)k * mm;
     double *wk = W + (int64_t)k * mm;
-    auto key_of = [&](int64_t i) -> uint64_t {
-        const double re = pk[2 * i], im = pk[2 * i + 1];
-        return (uint64_t)__double_as_longlong(re * re + im * im);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(wk);
+    const int64_t ns = (mm + kWThreads - 1) / kWThreads;   // stripes of kWThreads indices
+    constexpr int kB = 8;
+    // (flat index, key) of this thread in stripe order, eight stripes' keys
+    // loaded together
+    auto walk = [&](auto f) {
+        for (int64_t s0 = 0; s0 < ns; s0 += kB) {
+            uint64_t kv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int64_t i = (s0 + u) * kWThreads + tid;
+                kv[u] = (s0 + u < ns && i < mm) ? keys[i] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (s0 + u >= ns) break;
+                f((s0 + u) * kWThreads + tid, kv[u]);
+            }
+        }
     };
-    uint64_t kstar = ~0ull;
-    int64_t need = 0;
-    if (kzero > 0) {
-        if (tid == 0) {
-            s_pref = 0;
-            s_rem = kzero;
+    if (kzero <= 0) {   // selection only
+        const int dq = kWThreads / m, dr = kWThreads % m;
+        int e = tid / m, r = tid % m;
+        for (int64_t sidx = 0; sidx < ns; ++sidx) {
+            const int64_t i = sidx * kWThreads + tid;
+            if (i < mm) wk[i] = selected_er(e, r, m, dmin) ? 1.0 : 0.0;
+            e += dq;
+            r += dr;
+            if (r >= m) {
+                r -= m;
+                ++e;
+            }
+        }
+        return;
+    }
+    {
+        const int dq = kWThreads / m, dr = kWThreads % m;
+        int e = tid / m, r = tid % m;
+        for (int64_t s0 = 0; s0 < ns; s0 += kB) {
+            double re[kB], im[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int64_t i = (s0 + u) * kWThreads + tid;
+                const bool ok = s0 + u < ns && i < mm;
+                re[u] = ok ? pk[2 * i] : 0.0;
+                im[u] = ok ? pk[2 * i + 1] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (s0 + u >= ns) break;
+                const int64_t i = (s0 + u) * kWThreads + tid;
+                if (i < mm)
+                    keys[i] = selected_er(e, r, m, dmin)
+                                  ? (uint64_t)__double_as_longlong(re[u] * re[u] + im[u] * im[u]) + 1ull
+                                  : 0ull;
+                e += dq;
+                r += dr;
+                if (r >= m) {
+                    r -= m;
+                    ++e;
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        s_pref = 0;
+        s_rem = kzero;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 5; ++pass) {
+        const int width = pass == 0 ? 12 : 13;
+        const int shift = 52 - 13 * pass;   // 52, 39, 26, 13, 0
+        const int nbins = 1 << width;
+        for (int q = tid; q < nbins; q += kWThreads) hist[q] = 0;
+        __syncthreads();
+        const uint64_t pref = s_pref;
+        const uint64_t hmask = pass == 0 ? 0ull : ~0ull << (shift + width);
+        const unsigned dmask = (unsigned)nbins - 1u;
+        walk([&](int64_t, uint64_t key) {
+            if (key == 0 || (key & hmask) != (pref & hmask)) return;
+            const unsigned dg = (unsigned)(key >> shift) & dmask;
+            const uint64_t act = __ballot(1);
+            const int first = __ffsll((unsigned long long)act) - 1;
+            const unsigned d0 = __shfl(dg, first);
+            if (__ballot(dg == d0) == act) {
+                if (lane == first) atomicAdd(&hist[d0], (unsigned)__popcll(act));
+            } else {
+                atomicAdd(&hist[dg], 1u);
+            }
+        });
+        __syncthreads();
+        // digits in descending order, eight per thread: thread q holds the
+        // digits nbins - 1 - 8 q - u; the chosen digit is where the running
+        // count first reaches rem
+        const int64_t rem = s_rem;
+        int64_t cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = 8 * tid + u;
+            if (j < nbins) cnt += hist[nbins - 1 - j];
+        }
+        int64_t tot;
+        int64_t ex = block_exscan(cnt, s_w, tot);
+        if (cnt > 0 && ex < rem && ex + cnt >= rem) {
+            for (int u = 0; u < 8; ++u) {
+                const int j = 8 * tid + u;
+                const int64_t c = j < nbins ? (int64_t)hist[nbins - 1 - j] : 0;
+                if (c > 0 && ex + c >= rem) {
+                    s_pref = pref | ((uint64_t)(nbins - 1 - j) << shift);
+                    s_rem = rem - ex;
+                    break;
+                }
+                ex += c;
+            }
         }
         __syncthreads();
-        for (int shift = 56; shift >= 0; shift -= 8) {
-            if (tid < 256) hist[tid] = 0;
-            __syncthreads();
-            const uint64_t pref = s_pref;
-            for (int64_t i = tid; i < mm; i += kWThreads) {
-                if (!selected(i, m, dmin)) continue;
-                const uint64_t key = key_of(i);
-                if (shift < 56 && (key >> (shift + 8)) != (pref >> (shift + 8))) continue;
-                atomicAdd(&hist[(key >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int64_t rem = s_rem;
-                for (int dgt = 255; dgt >= 0; --dgt) {
-                    if (rem <= (int64_t)hist[dgt]) {
-                        s_pref = pref | ((uint64_t)dgt << shift);
-                        break;
-                    }
-                    rem -= hist[dgt];
-                }
-                s_rem = rem;
-            }
-            __syncthreads();
-        }
-        kstar = s_pref;
-        need = s_rem;  // how many keys equal to kstar are zeroed, lowest index first
     }
-    // contiguous chunk per thread, so tie ranks follow the flat index
-    const int64_t chunk = (mm + kWThreads - 1) / kWThreads;
-    const int64_t lo = (int64_t)tid * chunk, hi = std::min<int64_t>(mm, lo + chunk);
+    const uint64_t kstar = s_pref;   // a selected key (>= 1)
+    const int64_t need = s_rem;      // keys equal to kstar to zero, lowest flat index first
     int64_t ties = 0;
-    if (kzero > 0)
-        for (int64_t i = lo; i < hi; ++i)
-            if (selected(i, m, dmin) && key_of(i) == kstar) ++ties;
-    scan[tid] = ties;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t acc = 0;
-        for (int t = 0; t < kWThreads; ++t) {
-            const int64_t v = scan[t];
-            scan[t] = acc;
-            acc += v;
+    walk([&](int64_t, uint64_t key) {
+        if (key == kstar) ++ties;
+    });
+    int64_t nties;
+    (void)block_exscan(ties, s_w, nties);
+    // all ties zeroed (need == nties) or none (need == 0) needs no ranks
+    const bool ranked = need > 0 && need < nties;
+    int64_t base = 0;   // ties in earlier stripes
+    walk([&](int64_t i, uint64_t key) {
+        double w = (key == 0 || key > kstar) ? 0.0 : 1.0;
+        const bool tie = key == kstar;
+        if (tie && !ranked && need > 0) w = 0.0;
+        if (ranked) {   // block-uniform
+            int64_t st;
+            const int64_t ex = block_exscan(tie ? 1 : 0, s_w, st);
+            if (tie && base + ex < need) w = 0.0;
+            base += st;
         }
-    }
-    __syncthreads();
-    int64_t rank = scan[tid];
-    for (int64_t i = lo; i < hi; ++i) {
-        double w = 0.0;
-        if (selected(i, m, dmin)) {
-            w = 1.0;
-            if (kzero > 0) {
-                const uint64_t key = key_of(i);
-                if (key > kstar) {
-                    w = 0.0;
-                } else if (key == kstar) {
-                    if (rank < need) w = 0.0;
-                    ++rank;
-                }
-            }
-        }
-        wk[i] = w;
-    }
+        if (i < mm) wk[i] = w;   // replaces this thread's own key
+    });
 }
 
 // The zeroed selected pairs of one frequency per block, as (e, r) in flat
@@ -163,49 +273,50 @@ __global__ void __launch_bounds__(kWThreads) k_weights(int m, int dmin, int64_t 
 // contiguous chunks, an exclusive scan in thread order, then the writes.
 __global__ void __launch_bounds__(kWThreads) k_zero_list(int m, int dmin, const double *__restrict__ W, int zcap,
                                                          int2 *__restrict__ zl, int *__restrict__ nz) {
-    __shared__ int64_t scan[kWThreads];
+    __shared__ int64_t s_w[kWThreads / 64];
     const int k = blockIdx.x, tid = threadIdx.x;
     const int64_t mm = (int64_t)m * m;
     const double *wk = W + (int64_t)k * mm;
     const int64_t chunk = (mm + kWThreads - 1) / kWThreads;
-    const int64_t lo = (int64_t)tid * chunk, hi = std::min<int64_t>(mm, lo + chunk);
+    const int64_t lo = std::min<int64_t>(mm, (int64_t)tid * chunk), hi = std::min<int64_t>(mm, lo + chunk);
+    const int e_lo = (int)(lo / m), r_lo = (int)(lo - (int64_t)e_lo * m);
     int64_t cnt = 0;
-    for (int64_t i = lo; i < hi; ++i)
-        if (selected(i, m, dmin) && wk[i] == 0.0) ++cnt;
-    scan[tid] = cnt;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t acc = 0;
-        for (int t = 0; t < kWThreads; ++t) {
-            const int64_t v = scan[t];
-            scan[t] = acc;
-            acc += v;
+    {
+        int e = e_lo, r = r_lo;
+        for (int64_t i = lo; i < hi; ++i) {
+            if (selected_er(e, r, m, dmin) && wk[i] == 0.0) ++cnt;
+            if (++r == m) {
+                r = 0;
+                ++e;
+            }
         }
-        nz[k] = (int)std::min<int64_t>(acc, zcap);
     }
-    __syncthreads();
-    int64_t pos = scan[tid];
+    int64_t total;
+    int64_t pos = block_exscan(cnt, s_w, total);
+    if (tid == 0) nz[k] = (int)std::min<int64_t>(total, zcap);
+    int e = e_lo, r = r_lo;
     for (int64_t i = lo; i < hi && pos < zcap; ++i) {
-        if (selected(i, m, dmin) && wk[i] == 0.0) {
-            const int e = (int)(i / m);
-            zl[(int64_t)k * zcap + pos] = make_int2(e, (int)(i - (int64_t)e * m));
+        if (selected_er(e, r, m, dmin) && wk[i] == 0.0) {
+            zl[(int64_t)k * zcap + pos] = make_int2(e, r);
             ++pos;
+        }
+        if (++r == m) {
+            r = 0;
+            ++e;
         }
     }
 }
 
-// Support: |x| < R - margin and covered by every emitter.
-__global__ void k_support(int nx, int ny, double h, double x0, double y0, double rs, int m,
-                          const double *__restrict__ T, uint8_t *__restrict__ S) {
+// Support, part 1: |x| < R - margin.  The rasteriser's write pass then
+// clears every pixel that some emitter does not cover.
+__global__ void k_support_disc(int nx, int ny, double h, double x0, double y0, double rs,
+                               uint8_t *__restrict__ S) {
     const int64_t N = (int64_t)nx * ny;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t j = p / nx, i = p - j * nx;
     const double px = x0 + (double)i * h, py = y0 + (double)j * h;
-    uint8_t ok = (px * px + py * py < rs * rs) ? 1 : 0;
-    for (int e = 0; e < m && ok; ++e)
-        if (isnan(T[(int64_t)e * N + p])) ok = 0;
-    S[p] = ok;
+    S[p] = (px * px + py * py < rs * rs) ? 1 : 0;
 }
 
 __global__ void k_direction(int64_t n, const double *__restrict__ grad, const double *__restrict__ hd,
@@ -427,9 +538,18 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     // 1. rays, tables and Green's functions in the current model
     k_slowness<<<blocks_for(N, 256), 256, 0, st>>>(c_in, N, w.s);
     RB_LAUNCHED();
+    // support (step 4): inside the ring margin and covered by every emitter
+    const double rs = g->ring_radius - g->support_margin;
+    k_support_disc<<<blocks_for(N, 256), 256, 0, st>>>(g->nx, g->ny, g->h, g->x0, g->y0, rs, w.S);
+    RB_LAUNCHED();
     rb_tables tab{w.T, w.amp, w.att, w.Trx, w.amp_rx, w.att_rx};
-    RB_TRY(trace_rays_impl(g, t, w.s, alpha0, &tab, scratch, scratch_bytes, st));
-    {
+    if (o->dtype == RB_F32 || o->dtype == RB_F64) {
+        // 32/64-bit G needs no global scale: the rasteriser writes it directly
+        GreenOut gout{green_params(freqs, nf, o->y_pow), o->dtype, w.Gr, w.Gi};
+        RB_TRY(trace_rays_impl(g, t, w.s, alpha0, &tab, scratch, scratch_bytes, st, w.S, &gout));
+        RB_TRY(fill_f32(w.gscale, 1.0f, nf, st));
+    } else {
+        RB_TRY(trace_rays_impl(g, t, w.s, alpha0, &tab, scratch, scratch_bytes, st, w.S, nullptr));
         Carver gc(scratch, scratch_bytes);
         float *amax = gc.take<float>(1);
         float *parts = gc.take<float>(kReduceBlocks);
@@ -457,9 +577,6 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin, reinterpret_cast<int *>(w.zl),
                              w.nz, m * m, w.hd, st));
     // 4. diagonally weighted direction on the support
-    const double rs = g->ring_radius - g->support_margin;
-    k_support<<<blocks_for(N, 256), 256, 0, st>>>(g->nx, g->ny, g->h, g->x0, g->y0, rs, m, w.T, w.S);
-    RB_LAUNCHED();
     RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
     k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.v);
     RB_LAUNCHED();

@@ -20,8 +20,10 @@
 //    pass 3 recomputes the winner's barycentrics per point.  The result is
 //    independent of scheduling.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
+#include "green.h"
 
 namespace rb {
 namespace {
@@ -475,11 +477,17 @@ __global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restri
 // Write pass: every point recomputes its first arrival's interpolation
 // (the triangle index is the low part of its key) and writes T in place of
 // the key, a and B.  Points are pixels (RX = false) or ring elements
-// (RX = true).
-template <bool RX>
+// (RX = true).  With GS = float or double the pass writes the Green's
+// tables of the frequency set (Gr, Gi [nf][m][N], `gofs` = e0 N) instead
+// of T, a and B, from the same values (a and B rounded to float as the
+// tables store them).
+template <bool RX, typename GS = void>
 __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const double2 *__restrict__ AB,
                                const double2 *__restrict__ rxy, uint64_t *__restrict__ akey,
-                               float *__restrict__ amp_out, float *__restrict__ att_out) {
+                               float *__restrict__ amp_out, float *__restrict__ att_out,
+                               uint8_t *__restrict__ cover, GreenParams GP = GreenParams(),
+                               GS *__restrict__ Gr = nullptr, GS *__restrict__ Gi = nullptr, int64_t gofs = 0) {
+    constexpr bool GREEN = !std::is_void<GS>::value;
     const int64_t npts = RX ? (int64_t)P.m : (int64_t)P.nx * P.ny;
     {
         // one flat grid over (emitter, point block), XCD-contiguous.  Pixel
@@ -507,10 +515,22 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
         const int64_t idx = (int64_t)eb * npts + p;
         const uint64_t key = akey[idx];
         double *Tout = reinterpret_cast<double *>(akey);
+        const int64_t gstride = (int64_t)P.m * npts;   // one frequency of G
+        auto uncovered = [&]() {
+            if constexpr (GREEN) {
+                for (int k = 0; k < GP.nf; ++k) {
+                    Gr[k * gstride + gofs + idx] = (GS)0;
+                    Gi[k * gstride + gofs + idx] = (GS)0;
+                }
+            } else {
+                Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
+                amp_out[idx] = 0.0f;
+                att_out[idx] = 0.0f;
+            }
+            if (cover) cover[p] = 0;   // every writer stores the same value
+        };
         if (key == ~0ull) {
-            Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
-            amp_out[idx] = 0.0f;
-            att_out[idx] = 0.0f;
+            uncovered();
             return;
         }
         const uint32_t w = (uint32_t)(key & ((1ull << P.idx_bits) - 1ull));
@@ -519,9 +539,7 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
         const int n = (int)(cell / (uint32_t)P.nr);
         const int j = (int)(cell - (uint32_t)n * (uint32_t)P.nr);
         if (n >= P.nmax || j >= P.nr - 1) {  // cannot occur for a key written by the pixel pass
-            Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
-            amp_out[idx] = 0.0f;
-            att_out[idx] = 0.0f;
+            uncovered();
             return;
         }
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
@@ -543,10 +561,22 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
         double la, lb, lc;
         bary(t, px, py, -P.bary_tol, la, lb, lc);
         const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
-        Tout[idx] = la * ta + lb * tb + lc * tc;
+        const double tv = la * ta + lb * tb + lc * tc;
         const double2 qa = AB[ka], qb = AB[kb], qc = AB[kc];
-        amp_out[idx] = (float)(la * qa.x + lb * qb.x + lc * qc.x);
-        att_out[idx] = (float)(la * qa.y + lb * qb.y + lc * qc.y);
+        const float av = (float)(la * qa.x + lb * qb.x + lc * qc.x);
+        const float bv = (float)(la * qa.y + lb * qb.y + lc * qc.y);
+        if constexpr (GREEN) {
+            for (int k = 0; k < GP.nf; ++k) {
+                double re, im;
+                green_value(GP, k, tv, (double)av * GP.rsq[k], (double)bv, re, im);
+                Gr[k * gstride + gofs + idx] = (GS)re;
+                Gi[k * gstride + gofs + idx] = (GS)im;
+            }
+        } else {
+            Tout[idx] = tv;
+            amp_out[idx] = av;
+            att_out[idx] = bv;
+        }
     }
 }
 
@@ -602,10 +632,14 @@ size_t trace_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int b
     return c.used + 256;
 }
 
-// Traces all emitters into `out`, in batches that fit the workspace.
+// Traces all emitters into `out`, in batches that fit the workspace.  If
+// `cover` is given, cover[p] is set to 0 for every pixel that some emitter
+// does not reach (T = NaN) and left alone otherwise.  If `gout` is given,
+// the pixel tables are not written: the write pass produces the Green's
+// tables of `gout` instead (out->T still serves as the key buffer).
 rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const double *slowness,
                           const double *alpha0, const rb_tables *out, void *ws, size_t ws_bytes,
-                          hipStream_t st) {
+                          hipStream_t st, uint8_t *cover, const GreenOut *gout) {
     const int64_t N = (int64_t)g->nx * g->ny;
     // how many emitters fit
     Carver probe(nullptr, 0);
@@ -677,10 +711,21 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         k_raster_rx<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, akey_rx);
         RB_LAUNCHED();
         const unsigned gw = (unsigned)(((g->nx + 15) / 16) * ((g->ny + 15) / 16)) * P.ne;
-        k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, out->amp + (int64_t)e0 * N, out->att + (int64_t)e0 * N);
+        if (gout && gout->dt == RB_F32)
+            k_raster_write<false, float><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, nullptr, nullptr, cover,
+                                                             gout->P, (float *)gout->Gr, (float *)gout->Gi,
+                                                             (int64_t)e0 * N);
+        else if (gout)
+            k_raster_write<false, double><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, nullptr, nullptr, cover,
+                                                              gout->P, (double *)gout->Gr, (double *)gout->Gi,
+                                                              (int64_t)e0 * N);
+        else
+            k_raster_write<false><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, out->amp + (int64_t)e0 * N,
+                                                      out->att + (int64_t)e0 * N, cover);
         RB_LAUNCHED();
         const unsigned gr = blocks_for(g->m, 256) * P.ne;
-        k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey_rx, out->amp_rx + (int64_t)e0 * g->m, out->att_rx + (int64_t)e0 * g->m);
+        k_raster_write<true><<<gr, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey_rx, out->amp_rx + (int64_t)e0 * g->m,
+                                                 out->att_rx + (int64_t)e0 * g->m, nullptr);
         RB_LAUNCHED();
     }
     return RB_OK;
@@ -709,7 +754,8 @@ rb_status rb_trace_rays(const rb_geometry *g, const rb_trace_opts *t, const doub
     RB_TRY(rb::check_tables(out));
     RB_CHECK_ARG(slowness != nullptr, "slowness is NULL");
     RB_CHECK_ARG(ws != nullptr, "workspace is NULL");
-    return rb::trace_rays_impl(g, t, slowness, alpha0, out, ws, ws_bytes, rb::as_stream(stream));
+    return rb::trace_rays_impl(g, t, slowness, alpha0, out, ws, ws_bytes, rb::as_stream(stream), nullptr,
+                               nullptr);
 }
 
 }  // extern "C"

@@ -365,6 +365,35 @@ def test_invert_frequency_set_matches_oracle(rb, dtype):
     assert np.array_equal(c_in.cpu().numpy(), p.c_start.reshape(-1))
 
 
+def test_invert_outlier_ties_split_by_flat_index(rb):
+    """The outlier threshold falls inside a group of exactly equal |p|^2:
+    of 3k tied pairs the k with the smallest flat index are zeroed (the
+    oracle's lexicographic order), which only the ranked-tie path decides."""
+    p = W.small_ring()
+    topts = W.resolve_trace_opts(p.geom, p.c_start, 360)
+    f = p.freq_sets[0]
+    m = p.geom.m
+    mask = invert.receiver_mask(m, p.inv.recv_fraction)
+    sel = np.flatnonzero(mask.reshape(-1))
+    kz = int(np.floor(p.inv.outlier_fraction * sel.size))
+    assert kz >= 1
+    pm = p.p_meas[0].copy()
+    rng = np.random.default_rng(77)
+    for k in range(pm.shape[0]):
+        big = 2.0 * np.abs(pm[k]).max()
+        tied = np.sort(rng.choice(sel, size=3 * kz, replace=False))
+        pm[k].reshape(-1)[tied] = big * np.exp(0.3j)
+    _say("invert ring64_grid128 f64 with tied outliers")
+    ref = invert.invert_frequency_set(p.geom, topts, p.inv, p.c_start, p.alpha0, f, pm)
+    c_in = _t(p.c_start.reshape(-1))
+    c_out = torch.empty_like(c_in)
+    rb.invert_frequency_set(p.geom, topts, p.inv, "f64", c_in, _t(p.alpha0.reshape(-1)), f,
+                            _t(np.stack([pm.real, pm.imag], -1)), c_out)
+    dc_g = c_out.cpu().numpy() - p.c_start.reshape(-1)
+    dc_o = ref[0].reshape(-1) - p.c_start.reshape(-1)
+    assert _rel(dc_g, dc_o) <= 1e-6
+
+
 def test_invert_in_place_and_ragged(rb):
     p = W.custom(47, 0.5e-3, 24, 11e-3, 150, [[2.4e5, 3.1e5, 3.7e5]], seed=13)
     topts = W.resolve_trace_opts(p.geom, p.c_start, 150)
