@@ -123,6 +123,8 @@ rb_status reduce_max_f64(const double *in, const uint8_t *mask, int64_t n, doubl
                          double *out, hipStream_t st);
 rb_status reduce_max_f32(const float *in, int64_t n, float *partials, float *out,
                          hipStream_t st);
+// out[0] = max over n of |in[i]| (0 for an all-zero input).
+rb_status reduce_absmax_f64(const double *in, int64_t n, double *partials, double *out, hipStream_t st);
 
 constexpr int kReduceBlocks = 1024;
 

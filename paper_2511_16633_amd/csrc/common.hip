@@ -78,13 +78,13 @@ rb_status fill_f32(float *p, float v, int64_t n, hipStream_t st) { return fill(p
 
 // ---------------------------------------------------------------- reductions
 // max is exact and order-independent, so these are deterministic.
-template <typename T>
+template <typename T, bool ABS = false>
 __global__ void k_max_partial(const T *in, const uint8_t *mask, int64_t n, T *partials) {
     __shared__ T sh[256];
-    T best = -INFINITY;
+    T best = ABS ? (T)0 : -INFINITY;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         if (!mask || mask[i]) {
-            T v = in[i];
+            T v = ABS ? fabs(in[i]) : in[i];
             best = v > best ? v : best;
         }
     }
@@ -117,6 +117,14 @@ __global__ void k_max_final(const T *partials, int np, T *out) {
 rb_status reduce_max_f64(const double *in, const uint8_t *mask, int64_t n, double *partials,
                          double *out, hipStream_t st) {
     k_max_partial<double><<<kReduceBlocks, 256, 0, st>>>(in, mask, n, partials);
+    RB_LAUNCHED();
+    k_max_final<double><<<1, 256, 0, st>>>(partials, kReduceBlocks, out);
+    RB_LAUNCHED();
+    return RB_OK;
+}
+
+rb_status reduce_absmax_f64(const double *in, int64_t n, double *partials, double *out, hipStream_t st) {
+    k_max_partial<double, true><<<kReduceBlocks, 256, 0, st>>>(in, nullptr, n, partials);
     RB_LAUNCHED();
     k_max_final<double><<<1, 256, 0, st>>>(partials, kReduceBlocks, out);
     RB_LAUNCHED();

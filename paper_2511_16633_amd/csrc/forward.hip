@@ -122,18 +122,6 @@ __global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const 
     d[2 * idx + 1] = si * c;
 }
 
-__global__ void k_absmax_f64(const double *__restrict__ v, int64_t n, double *__restrict__ out) {
-    __shared__ double sh[1024];
-    double best = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) best = fmax(best, fabs(v[i]));
-    sh[threadIdx.x] = best;
-    __syncthreads();
-    for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = sh[0];
-}
 
 // Workgroup -> (tile, split, frequency) for the flat grid of the 16-bit
 // kernel.  The tiles of one pixel split read the same pixel range of G, so
@@ -516,7 +504,7 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
 
 // workspace: max |delta|, the split partials, and (16-bit) delta as float
 struct FwdWs {
-    double *dmax;
+    double *dmax, *dparts;
     void *part;
     float *df;
 };
@@ -525,6 +513,7 @@ static FwdWs carve_fwd(Carver &c, const FwdParams &P, rb_dtype dt) {
     const size_t es = dt == RB_F64 ? 8 : 4;
     FwdWs w;
     w.dmax = c.take<double>(1);
+    w.dparts = (dt == RB_BF16 || dt == RB_F16) ? c.take<double>(kReduceBlocks) : nullptr;
     w.part = c.take<char>((size_t)P.nsplit * P.nf * P.mp * P.mp * 2 * es);
     w.df = (dt == RB_BF16 || dt == RB_F16) ? c.take<float>((size_t)P.N + 8) : nullptr;
     return w;
@@ -568,8 +557,7 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
         case RB_BF16:
         case RB_F16:
-            k_absmax_f64<<<1, 1024, 0, st>>>(delta, P.N, w.dmax);
-            RB_LAUNCHED();
+            RB_TRY(reduce_absmax_f64(delta, P.N, w.dparts, w.dmax, st));
             k_delta_f32<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, delta, w.dmax, w.df);
             RB_LAUNCHED();
             if (dt == RB_BF16)

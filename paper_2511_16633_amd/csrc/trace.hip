@@ -53,6 +53,7 @@ struct TP {
 // memory and needs no per-corner test; cells farther out are pure water.
 __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &P, double x, double y,
                                       double &s, double &gx, double &gy, double &a) {
+#pragma clang fp contract(fast)
     double u = (x - P.x0) * P.inv_h;
     double v = (y - P.y0) * P.inv_h;
     double fi = floor(u), fj = floor(v);
@@ -89,6 +90,7 @@ __device__ __forceinline__ double recip(double s) {
 
 __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P, const double st[5],
                                     double d[5]) {
+#pragma clang fp contract(fast)
     double s, gx, gy, a;
     field(sa, P, st[0], st[1], s, gx, gy, a);
     const double is = recip(s);
@@ -127,6 +129,8 @@ typedef double nd2 __attribute__((ext_vector_type(2)));
 
 __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__ sa, double2 *__restrict__ XY,
                                                double2 *__restrict__ AB, int *__restrict__ L) {
+    // the integration may fuse multiply-adds (one rounding instead of two)
+#pragma clang fp contract(fast)
     const int lane = threadIdx.x & 63;
     const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int eb = blockIdx.y;
