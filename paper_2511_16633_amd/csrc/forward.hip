@@ -89,28 +89,39 @@ __global__ void __launch_bounds__(256) k_forward(FwdParams P, const T *__restric
     }
 }
 
-// d[k][e][r] = c_k * sum_split part (fixed order), read from the upper triangle.
+// d[k][e][r] = c_k * sum_split part (fixed order) over the upper triangle
+// e <= r, written to (e, r) and (r, e).  A thread per upper-triangle entry of
+// a row-major [mp][mp] index (entries below the diagonal exit), so the
+// partial reads are coalesced; eight splits are loaded together.
 template <typename T>
 __global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const float *__restrict__ gscale,
                                  const double *__restrict__ dmax, double *__restrict__ d) {
     const int64_t mm = (int64_t)P.m * P.m;
-    const int64_t tot = mm * P.nf;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= tot) return;
+    if (idx >= mm * P.nf) return;
     const int k = (int)(idx / mm);
     const int64_t rem = idx - (int64_t)k * mm;
-    int e = (int)(rem / P.m), r = (int)(rem - (int64_t)e * P.m);
-    // d is symmetric: both (e, r) and (r, e) take the upper-triangle element
-    if (e > r) {
-        const int t = e;
-        e = r;
-        r = t;
-    }
+    const int e = (int)(rem / P.m), r = (int)(rem - (int64_t)e * P.m);
+    if (e > r) return;
+    const int64_t stride = (int64_t)P.nf * P.mp * P.mp * 2;   // one split
+    const T *pp = part + (int64_t)k * P.mp * P.mp * 2 + ((int64_t)e * P.mp + r) * 2;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < P.nsplit; ++s) {
-        const T *pp = part + ((int64_t)s * P.nf + k) * P.mp * P.mp * 2 + ((int64_t)e * P.mp + r) * 2;
-        sr += (double)pp[0];
-        si += (double)pp[1];
+    constexpr int kU = 8;
+    for (int s0 = 0; s0 < P.nsplit; s0 += kU) {
+        T vr[kU], vi[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = s0 + u < P.nsplit;
+            vr[u] = ok ? pp[(s0 + u) * stride] : T(0);
+            vi[u] = ok ? pp[(s0 + u) * stride + 1] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (s0 + u < P.nsplit) {
+                sr += (double)vr[u];
+                si += (double)vi[u];
+            }
+        }
     }
     double c = P.cg[k];
     if (gscale) {
@@ -118,10 +129,13 @@ __global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const 
         c *= g * g;
     }
     if (dmax) c *= dmax[0];
-    d[2 * idx] = sr * c;
-    d[2 * idx + 1] = si * c;
+    const double vr = sr * c, vi = si * c;
+    const int64_t o1 = ((int64_t)k * P.m + e) * P.m + r, o2 = ((int64_t)k * P.m + r) * P.m + e;
+    d[2 * o1] = vr;
+    d[2 * o1 + 1] = vi;
+    d[2 * o2] = vr;
+    d[2 * o2 + 1] = vi;
 }
-
 
 // Workgroup -> (tile, split, frequency) for the flat grid of the 16-bit
 // kernel.  The tiles of one pixel split read the same pixel range of G, so
