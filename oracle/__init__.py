@@ -14,7 +14,8 @@ Layout:
   forward operator, its adjoint and the diagonal of the Gauss-Newton
   Hessian (Inverse Problem section, Eqs. 8-10), in NumPy FP64;
 * ``invert.py`` - data-space weights (receiver selection and outlier
-  zeroing, Results section), the diagonally weighted single step and the
+  zeroing, Results section), the diagonally weighted single step, the
+  Jacobi-preconditioned CG solution of the linear subproblem and the
   low-to-high frequency sweep (Inverse Problem section).
 
 Where the paper leaves a choice open, the reading taken is stated in the

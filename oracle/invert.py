@@ -1,4 +1,5 @@
-"""Data weights, the diagonally weighted single step and the frequency sweep.
+"""Data weights, the diagonally weighted single step, the CG solution of the
+linear subproblem and the frequency sweep.
 
 Plain NumPy FP64, test infrastructure.  Follows the paper's Inverse Problem
 section (Eqs. 8-10 and the single-step paragraph) and the data handling of
@@ -21,7 +22,9 @@ its Results section.  Readings taken where the paper is silent:
   beta = Re<J v, W D> / <J v, W J v>, so delta = beta v;
 * update of q = 1/c^2: c_new = (1/c^2 + delta)^(-1/2) where delta != 0,
   c unchanged elsewhere; a non-positive q is an error;
-* reported update norm: sqrt(sum_x (c_new - c)^2) in m/s.
+* reported update norm: sqrt(sum_x (c_new - c)^2) in m/s;
+* CG (the paper's earlier, iterative solution of the linearised equation):
+  see invert_frequency_set_cg for its readings.
 """
 from __future__ import annotations
 
@@ -72,12 +75,13 @@ def support(geom, T: np.ndarray) -> np.ndarray:
     return inside & np.all(np.isfinite(T), axis=0)
 
 
-def invert_frequency_set(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas,
-                         return_parts: bool = False):
-    """One linearised, diagonally weighted single step for one frequency set.
+def linearise(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas) -> dict:
+    """Everything one frequency set's linear subproblem needs, in the model c.
 
-    c: [ny][nx] m/s; alpha: [ny][nx] Np/(m MHz^y) or None; p_meas: [nf][m][m].
-    Returns (c_new, dc_l2) or, with return_parts, a dict of intermediates."""
+    Rays and tables in c, G and the modelled data per frequency, residual D,
+    data weight W, gradient grad = J^T W D, Hessian diagonal Hd, support S,
+    the diagonal weight den = Hd + eps max_S Hd and the pixels where it is
+    used, ok = S and den > 0."""
     c = np.asarray(c, np.float64)
     s = 1.0 / c
     T, A, B, Tr, Ar, Br = rays.tables(geom, topts, s, alpha)
@@ -99,18 +103,13 @@ def invert_frequency_set(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas
     hmax = float(np.max(hd[S])) if S.any() else 0.0
     den = hd + iopts.eps * hmax
     ok = S & (den > 0.0)
-    v = np.zeros(N)
-    v[ok] = grad[ok] / den[ok]
-    num = 0.0
-    dsq = 0.0
-    us = []
-    for k, f in enumerate(freqs):
-        u = born.born_forward(Gs[k], v, f, dA)
-        us.append(u)
-        num += float(np.sum(Ws[k] * np.real(np.conj(u) * Ds[k])))
-        dsq += float(np.sum(Ws[k] * (u.real * u.real + u.imag * u.imag)))
-    beta = num / dsq if dsq > 0.0 else 0.0
-    delta = beta * v
+    return {"c": c, "s": s, "dA": dA, "freqs": list(freqs), "T": T, "amp": A, "att": B,
+            "T_rx": Tr, "amp_rx": Ar, "att_rx": Br, "G": Gs, "D": Ds, "W": Ws,
+            "grad": grad, "hdiag": hd, "support": S, "hmax": hmax, "den": den, "ok": ok}
+
+
+def apply_update(c: np.ndarray, s: np.ndarray, delta: np.ndarray):
+    """q = 1/c^2 + delta where delta != 0; returns (c_new, dc_l2)."""
     q = s.reshape(-1) * s.reshape(-1) + delta
     if np.any(q[delta != 0.0] <= 0.0):
         raise NumericError("1/c^2 + delta is not positive")
@@ -120,12 +119,103 @@ def invert_frequency_set(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas
     c_new[nz] = 1.0 / np.sqrt(q[nz])
     dc = c_new - c_flat
     dc_l2 = math.sqrt(float(np.sum(dc * dc)))
-    c_new = c_new.reshape(c.shape)
+    return c_new.reshape(c.shape), dc_l2
+
+
+def invert_frequency_set(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas,
+                         return_parts: bool = False):
+    """One linearised, diagonally weighted single step for one frequency set.
+
+    c: [ny][nx] m/s; alpha: [ny][nx] Np/(m MHz^y) or None; p_meas: [nf][m][m].
+    Returns (c_new, dc_l2) or, with return_parts, a dict of intermediates."""
+    L = linearise(geom, topts, iopts, c, alpha, freqs, p_meas)
+    N = geom.n_pixels
+    grad, den, ok = L["grad"], L["den"], L["ok"]
+    v = np.zeros(N)
+    v[ok] = grad[ok] / den[ok]
+    num = 0.0
+    dsq = 0.0
+    us = []
+    for k, f in enumerate(freqs):
+        u = born.born_forward(L["G"][k], v, f, L["dA"])
+        us.append(u)
+        num += float(np.sum(L["W"][k] * np.real(np.conj(u) * L["D"][k])))
+        dsq += float(np.sum(L["W"][k] * (u.real * u.real + u.imag * u.imag)))
+    beta = num / dsq if dsq > 0.0 else 0.0
+    delta = beta * v
+    c_new, dc_l2 = apply_update(L["c"], L["s"], delta)
     if return_parts:
-        return {"c_new": c_new, "dc_l2": dc_l2, "grad": grad, "hdiag": hd, "support": S,
-                "direction": v, "beta": beta, "delta": delta, "T": T, "amp": A, "att": B,
-                "T_rx": Tr, "amp_rx": Ar, "att_rx": Br, "W": Ws, "D": Ds, "Jv": us,
-                "hmax": hmax}
+        parts = {k: L[k] for k in ("grad", "hdiag", "support", "T", "amp", "att", "T_rx", "amp_rx",
+                                   "att_rx", "W", "D", "hmax")}
+        parts.update({"c_new": c_new, "dc_l2": dc_l2, "direction": v, "beta": beta, "delta": delta,
+                      "Jv": us})
+        return parts
+    return c_new, dc_l2
+
+
+def hessian_action(L: dict, x: np.ndarray) -> np.ndarray:
+    """J^T W J x summed over the frequency set (Eq. 10's Gauss-Newton Hessian
+    applied to x): a Born forward, the data weight, then the adjoint."""
+    out = np.zeros_like(x)
+    for k, f in enumerate(L["freqs"]):
+        u = born.born_forward(L["G"][k], x, f, L["dA"])
+        out += born.born_adjoint(L["G"][k], L["W"][k] * u, f, L["dA"])
+    return out
+
+
+def invert_frequency_set_cg(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas, n_iter: int,
+                            return_parts: bool = False):
+    """The linear subproblem of one frequency set solved by conjugate gradients.
+
+    The paper's earlier method (Inverse Problem section, the paragraph on
+    solving the linearised equation iteratively) solves H delta = -grad F,
+    i.e. (J^T W J) delta = J^T W D, by CG.  Readings taken: the unknown lives
+    on the pixels where the single step's weight is defined (ok = S and
+    den > 0, zero elsewhere); the CG is preconditioned by that same diagonal
+    weight den = Hd + eps max_S Hd (Jacobi), so its first iterate is exactly
+    the single step's beta v; it starts from delta = 0 and runs n_iter
+    iterations (early stopping is the regularisation), stopping early, with
+    zero steps from then on, once r.z or p.Hp is not positive.  Textbook
+    preconditioned CG (Hestenes-Stiefel), in this order per iteration i:
+        q = H p;  alpha_i = r.z / p.q;  delta += alpha_i p;  r -= alpha_i q;
+        z = r / den on ok;  beta = (r.z)_new / (r.z);  p = z + beta p.
+    Returns (c_new, dc_l2) or, with return_parts, a dict holding also the
+    step lengths alpha_i and the values r_i.z_i before each iteration."""
+    if n_iter < 1:
+        raise ValueError("n_iter must be >= 1")
+    L = linearise(geom, topts, iopts, c, alpha, freqs, p_meas)
+    ok, den = L["ok"], L["den"]
+    N = geom.n_pixels
+    x = np.zeros(N)
+    r = np.where(ok, L["grad"], 0.0)
+    z = np.zeros(N)
+    z[ok] = r[ok] / den[ok]
+    p = z.copy()
+    rz = float(np.dot(r, z))
+    alphas = np.zeros(n_iter)
+    rzs = np.zeros(n_iter)
+    for i in range(n_iter):
+        rzs[i] = rz
+        if not rz > 0.0:
+            break
+        q = np.where(ok, hessian_action(L, p), 0.0)
+        pq = float(np.dot(p, q))
+        if not pq > 0.0:
+            break
+        a = rz / pq
+        alphas[i] = a
+        x = x + a * p
+        r = r - a * q
+        z = np.zeros(N)
+        z[ok] = r[ok] / den[ok]
+        rz_new = float(np.dot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    c_new, dc_l2 = apply_update(L["c"], L["s"], x)
+    if return_parts:
+        parts = dict(L)
+        parts.update({"c_new": c_new, "dc_l2": dc_l2, "delta": x, "alpha": alphas, "rz": rzs})
+        return parts
     return c_new, dc_l2
 
 

@@ -168,3 +168,86 @@ def test_sweep_is_deterministic_and_resumable():
     c3, h3 = invert.sweep(p.geom, to, p.inv, ck, p.alpha0, p.freq_sets[1:], p.p_meas[1:])
     assert np.array_equal(c1, c3) and h1[1:] == h3
     assert all(np.isfinite(h1)) and h1[0] > 0
+
+
+def _dense_hessian(L, freqs):
+    """Re(J^H W J) on the ok pixels from the explicit Jacobian."""
+    ok = L["ok"]
+    n = int(ok.sum())
+    H = np.zeros((n, n))
+    for k, f in enumerate(freqs):
+        J = born.jacobian(L["G"][k], f, L["dA"])[:, ok]
+        w = L["W"][k].reshape(-1)
+        H += np.real(J.conj().T @ (w[:, None] * J))
+    return H
+
+
+def test_cg_first_iterate_is_the_single_step():
+    """Jacobi-preconditioned CG from zero: its first iterate is beta v."""
+    g, c, al, to = _tiny_problem()
+    freqs = np.array([220e3, 260e3])
+    p = W.custom(33, 0.5e-3, 24, 12e-3, 240, [list(freqs)], seed=3)
+    one = invert.invert_frequency_set(g, to, W.InvertOpts(), c, al, freqs, p.p_meas[0], return_parts=True)
+    cg = invert.invert_frequency_set_cg(g, to, W.InvertOpts(), c, al, freqs, p.p_meas[0], 1,
+                                        return_parts=True)
+    scale = np.max(np.abs(one["delta"]))
+    assert scale > 0
+    assert np.max(np.abs(cg["delta"] - one["delta"])) <= 1e-12 * scale
+    assert abs(cg["alpha"][0] - one["beta"]) <= 1e-12 * abs(one["beta"])
+
+
+@pytest.mark.parametrize("n_iter", [1, 2, 3, 5])
+def test_cg_iterates_minimise_quadratic_over_krylov_subspace(n_iter):
+    """The k-th preconditioned CG iterate minimises 1/2 x.Hx - g.x over the
+    Krylov space span{M^-1 g, (M^-1 H) M^-1 g, ...} of dimension k (Galerkin
+    solution from an explicit basis and the explicit Jacobian's Hessian)."""
+    g, c, al, to = _tiny_problem()
+    freqs = np.array([220e3, 260e3])
+    p = W.custom(33, 0.5e-3, 24, 12e-3, 240, [list(freqs)], seed=3)
+    cg = invert.invert_frequency_set_cg(g, to, W.InvertOpts(), c, al, freqs, p.p_meas[0], n_iter,
+                                        return_parts=True)
+    ok = cg["ok"]
+    assert int(ok.sum()) > 100
+    H = _dense_hessian(cg, freqs)
+    rhs = cg["grad"][ok]
+    den = cg["den"][ok]
+    basis = [rhs / den]
+    for _ in range(1, n_iter):
+        basis.append((H @ basis[-1]) / den)
+    Q, _ = np.linalg.qr(np.stack(basis, axis=1))
+    x_star = Q @ np.linalg.solve(Q.T @ H @ Q, Q.T @ rhs)
+    x = cg["delta"][ok]
+    assert np.max(np.abs(x - x_star)) <= 1e-10 * np.max(np.abs(x_star))
+    assert np.all(cg["delta"][~ok] == 0.0)
+    assert np.all(cg["alpha"] > 0) and np.all(cg["rz"] > 0)
+
+
+def test_cg_recovers_perturbation_on_small_support():
+    """Consistent Born data p(c) + J d on a 9-pixel support, no outliers: CG
+    on the normal equations returns d (finite termination, run to 2n)."""
+    rs = 0.75e-3
+    g, c, al, to = _tiny_problem(margin=12e-3 - rs)
+    freqs = np.array([250e3, 320e3])
+    Gs, ps = _model_data(g, to, c, al, freqs)
+    T = rays.tables(g, to, 1.0 / c, al)[0]
+    S = invert.support(g, T)
+    n = int(S.sum())
+    assert n == 9
+    rng = np.random.default_rng(5)
+    d = np.zeros(g.n_pixels)
+    d[S] = 3e-9 * (1.0 + rng.standard_normal(n))
+    p_meas = np.stack([ps[k] + born.born_forward(Gs[k], d, f, g.h ** 2) for k, f in enumerate(freqs)])
+    cg = invert.invert_frequency_set_cg(g, to, W.InvertOpts(outlier_fraction=0.0), c, al, freqs, p_meas,
+                                        2 * n, return_parts=True)
+    assert np.max(np.abs(cg["delta"] - d)) <= 1e-9 * np.max(np.abs(d))
+
+
+def test_cg_zero_residual_stops_with_zero_steps():
+    """Data equal to the model's own: grad = 0, so r.z = 0 and every step is 0."""
+    g, c, al, to = _tiny_problem()
+    freqs = np.array([250e3])
+    _, ps = _model_data(g, to, c, al, freqs)
+    cg = invert.invert_frequency_set_cg(g, to, W.InvertOpts(), c, al, freqs, np.stack(ps), 4,
+                                        return_parts=True)
+    assert np.all(cg["alpha"] == 0.0) and cg["rz"][0] == 0.0
+    assert cg["dc_l2"] == 0.0 and np.array_equal(cg["c_new"], c)
