@@ -7,7 +7,8 @@
  * high-frequency Green's functions (Forward Problem section, Eqs. 4-7), the
  * Born forward and weighted adjoint contractions and the diagonally weighted
  * single step (Inverse Problem section, Eqs. 8-10 and the single-step
- * paragraph).
+ * paragraph), and the conjugate-gradient solution of the same linear
+ * subproblem that the single step replaces.
  *
  * Conventions shared by every entry point:
  *  - Pointers are DEVICE pointers unless marked [host].  The caller owns and
@@ -224,6 +225,37 @@ rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t,
                                   const double *alpha0, const double *freqs_hz, int32_t nf,
                                   const double *p_meas, double *c_out, double *dc_l2,
                                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The same frequency set with the linearised equation solved by conjugate
+ * gradients (Inverse Problem section: the earlier method that solves
+ * H delta = -grad F iteratively, about 10-15 iterations per set, each a
+ * Hessian action) instead of the single step.  Steps 1-4 and 7 are those of
+ * rb_invert_frequency_set; steps 5-6 become n_iter iterations of CG on
+ * (J^T W J) delta = J^T W D over the pixels ok = S and Hd + eps max_S Hd > 0
+ * (delta = 0 elsewhere), preconditioned by the diagonal Hd + eps max_S Hd,
+ * from delta = 0:
+ *     r = grad, z = p = r / den;  per iteration i:
+ *     alpha_i = r.z / <J p, W J p>;  delta += alpha_i p;
+ *     (unless last)  r -= alpha_i J^T W J p;  z = r / den;
+ *                    p = z + (r.z)_new / (r.z) p.
+ * The first iterate is the single step's beta v.  Once r.z or <J p, W J p>
+ * is not positive, every later step is zero.  Cost: n_iter Born forwards
+ * and n_iter - 1 weighted adjoints on top of one single step's linearisation.
+ * n_iter: 1 <= n_iter <= RB_MAX_CG_ITERS.  cg_hist: [host][2 n_iter] or
+ * NULL; receives (alpha_i, (r.z)_i before iteration i) per iteration, both 0
+ * after a stop.  ws: rb_invert_cg_workspace_bytes().  Other arguments,
+ * outputs and errors as for rb_invert_frequency_set.
+ */
+#define RB_MAX_CG_ITERS 64
+size_t rb_invert_cg_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int32_t nf,
+                                    rb_dtype dtype, int32_t emitter_batch);
+rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *t,
+                                     const rb_invert_opts *o, const double *c_in,
+                                     const double *alpha0, const double *freqs_hz, int32_t nf,
+                                     const double *p_meas, int32_t n_iter, double *c_out,
+                                     double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes,
+                                     void *stream);
 
 /* Static description of a status code. */
 const char *rb_status_string(rb_status s);

@@ -20,11 +20,13 @@ from ._binding import (  # noqa: F401
     forward_workspace_bytes,
     adjoint_workspace_bytes,
     invert_workspace_bytes,
+    invert_cg_workspace_bytes,
     trace_rays,
     build_green,
     born_forward,
     born_adjoint_weighted,
     born_hessian_banded,
     invert_frequency_set,
+    invert_frequency_set_cg,
     version,
 )

@@ -84,6 +84,10 @@ def lib():
         "rb_invert_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int, _i32]),
         "rb_invert_frequency_set": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp, _vp,
                                                    _P(_d), _i32, _vp, _vp, _P(_d), _vp, _sz, _vp]),
+        "rb_invert_cg_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int, _i32]),
+        "rb_invert_frequency_set_cg": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp,
+                                                      _vp, _P(_d), _i32, _vp, _i32, _vp, _P(_d), _P(_d), _vp,
+                                                      _sz, _vp]),
         "rb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "rb_last_error": (ctypes.c_char_p, []),
         "rb_version": (ctypes.c_char_p, []),
@@ -253,3 +257,27 @@ def invert_frequency_set(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[to
                                          fa, nf, _ptr(p_meas), _ptr(c_out), ctypes.byref(out), _ptr(ws),
                                          ws.numel(), _stream(stream)))
     return out.value
+
+
+def invert_cg_workspace_bytes(g, t, nf: int, dtype, emitter_batch: int = 0) -> int:
+    return int(lib().rb_invert_cg_workspace_bytes(ctypes.byref(geometry_struct(g)),
+                                                  ctypes.byref(trace_opts_struct(t)), nf, _dt(dtype),
+                                                  emitter_batch))
+
+
+def invert_frequency_set_cg(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[torch.Tensor], freqs,
+                            p_meas: torch.Tensor, n_iter: int, c_out: torch.Tensor,
+                            ws: Optional[torch.Tensor] = None, stream=None):
+    """CG solution of the frequency set's linear subproblem.  Returns
+    (update norm, alphas [n_iter], r.z values [n_iter]); synchronises the stream."""
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(invert_cg_workspace_bytes(g, t, nf, dtype), c_in.device)
+    out = ctypes.c_double(0.0)
+    hist = (ctypes.c_double * (2 * max(int(n_iter), 1)))()
+    _check(lib().rb_invert_frequency_set_cg(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                                            ctypes.byref(invert_opts_struct(o, dtype)), _ptr(c_in), _ptr(alpha0),
+                                            fa, nf, _ptr(p_meas), int(n_iter), _ptr(c_out), ctypes.byref(out),
+                                            hist, _ptr(ws), ws.numel(), _stream(stream)))
+    h = list(hist)
+    return out.value, h[0::2][:n_iter], h[1::2][:n_iter]

@@ -10,6 +10,14 @@
 //   beta      = Re<J v, W D> / <J v, W J v>   exact minimiser along v
 //   c_out     = (1/c^2 + beta v)^(-1/2)
 //
+// The CG variant (the paper's earlier method: the linearised equation
+// H delta = J^T W D solved iteratively) shares steps 1-4 and replaces the
+// single step by Jacobi-preconditioned CG on the pixels where the diagonal
+// weight is defined, preconditioned by that weight, so that its first
+// iterate is beta v.  Its scalars stay on the device; each iteration is one
+// Born forward (p.Hp = <J p, W J p> in data space) and, except the last,
+// one weighted adjoint (H p = J^T W J p).
+//
 // Every reduction here has a fixed order (per-block trees over a fixed grid,
 // then one block), and the outlier selection uses integer keys, so the
 // result does not depend on scheduling.
@@ -453,6 +461,143 @@ __global__ void k_update_write(int64_t n, const double *c, const double *__restr
     c_out[i] = out;
 }
 
+// ------------------------------------------------------------------ CG
+// Device state cg[]: 0 r.z, 1 alpha, 2 beta, 3 stopped (nonzero once r.z or
+// p.Hp has not been positive; every later step is then zero).  hist[2 i] is
+// iteration i's alpha, hist[2 i + 1] its r.z (both 0 for iterations after a
+// stop).
+
+__device__ __forceinline__ bool cg_ok(const uint8_t *S, const double *hd, int64_t i, double eps_hm, double &den) {
+    den = hd[i] + eps_hm;
+    return S[i] && den > 0.0;
+}
+
+// Block tree of one value per thread into part[blockIdx.x].
+__device__ __forceinline__ void block_sum_to(double v, double *s_red, double *part) {
+    s_red[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s_red[threadIdx.x] += s_red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_red[0];
+}
+
+// x = 0, r = grad on ok (0 elsewhere), z = p = r / den (the single step's v);
+// partial sums of r.z.
+__global__ void k_cg_start(int64_t n, const double *__restrict__ grad, const double *__restrict__ hd,
+                           const uint8_t *__restrict__ S, const double *__restrict__ hmax, double eps,
+                           double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
+                           double *__restrict__ p, double *__restrict__ part) {
+    __shared__ double s_red[256];
+    const double hm = hmax[0] > -INFINITY ? hmax[0] : 0.0;
+    const double eps_hm = eps * hm;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double den;
+        const bool ok = cg_ok(S, hd, i, eps_hm, den);
+        const double ri = ok ? grad[i] : 0.0;
+        const double zi = ok ? grad[i] / den : 0.0;
+        x[i] = 0.0;
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        acc += ri * zi;
+    }
+    block_sum_to(acc, s_red, part);
+}
+
+// Sum of the r.z partials.  first: cg[0] = r.z, nothing stopped.  Else
+// beta = new / old (0 once stopped) and cg[0] = new.
+__global__ void k_cg_rz_final(const double *__restrict__ part, int np, double *__restrict__ cg, int first) {
+    __shared__ double s_red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s_red[threadIdx.x] += s_red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rz = s_red[0];
+        if (first) {
+            cg[3] = 0.0;
+        } else {
+            cg[2] = (cg[3] == 0.0 && cg[0] > 0.0) ? rz / cg[0] : 0.0;
+        }
+        cg[0] = rz;
+    }
+}
+
+// alpha = r.z / p.Hp from the partials of <J p, W J p> (second component of
+// the step-length partials); stop on a non-positive r.z or p.Hp.
+__global__ void k_cg_alpha(const double *__restrict__ part, int np, double *__restrict__ cg,
+                           double *__restrict__ hist, int it) {
+    __shared__ double s_red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) acc += part[2 * i + 1];
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s_red[threadIdx.x] += s_red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double a = 0.0, rz = 0.0;
+        if (cg[3] == 0.0) {
+            rz = cg[0];
+            const double pq = s_red[0];
+            if (rz > 0.0 && pq > 0.0)
+                a = rz / pq;
+            else
+                cg[3] = 1.0;
+        }
+        cg[1] = a;
+        hist[2 * it] = a;
+        hist[2 * it + 1] = rz;
+    }
+}
+
+// x += alpha p; r -= alpha q on ok; z = r / den on ok; partial sums of r.z.
+__global__ void k_cg_step(int64_t n, const double *__restrict__ q, const double *__restrict__ hd,
+                          const uint8_t *__restrict__ S, const double *__restrict__ hmax, double eps,
+                          const double *__restrict__ cg, double *__restrict__ x, const double *__restrict__ p,
+                          double *__restrict__ r, double *__restrict__ z, double *__restrict__ part) {
+    __shared__ double s_red[256];
+    const double hm = hmax[0] > -INFINITY ? hmax[0] : 0.0;
+    const double eps_hm = eps * hm;
+    const double a = cg[1];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double den;
+        const bool ok = cg_ok(S, hd, i, eps_hm, den);
+        x[i] = x[i] + a * p[i];
+        const double ri = ok ? r[i] - a * q[i] : r[i];
+        const double zi = ok ? ri / den : 0.0;
+        r[i] = ri;
+        z[i] = zi;
+        acc += ri * zi;
+    }
+    block_sum_to(acc, s_red, part);
+}
+
+// p = z + beta p
+__global__ void k_cg_direction(int64_t n, const double *__restrict__ z, const double *__restrict__ cg,
+                               double *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + cg[2] * p[i];
+}
+
+// x += alpha p (last iteration); res[2] = 1 so that the update kernels
+// apply delta = x.
+__global__ void k_cg_last(int64_t n, const double *__restrict__ cg, const double *__restrict__ p,
+                          double *__restrict__ x, double *__restrict__ res) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] + cg[1] * p[i];
+    if (i == 0) res[2] = 1.0;
+}
+
 struct InvWs {
     double *s, *T, *Trx, *D, *W, *Jv, *grad, *hd, *v, *part, *res, *hmax;
     float *amp, *att, *amp_rx, *att_rx, *gscale;
@@ -460,10 +605,11 @@ struct InvWs {
     uint8_t *S;
     int2 *zl;   // zeroed pairs [nf][m m]
     int *nz;    // their counts [nf]
+    double *x, *r, *z, *p, *q, *cg, *hist;   // CG only
     void *scratch;
 };
 
-InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
+InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt, bool cg) {
     const size_t N = (size_t)g->nx * g->ny, m = g->m, mm = m * m;
     const size_t es = dtype_size(dt);
     InvWs w;
@@ -489,6 +635,16 @@ InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
     w.hmax = c.take<double>(1);
     w.zl = c.take<int2>((size_t)nf * mm);
     w.nz = c.take<int>(RB_MAX_NF);
+    w.x = w.r = w.z = w.p = w.q = w.cg = w.hist = nullptr;
+    if (cg) {
+        w.x = c.take<double>(N);
+        w.r = c.take<double>(N);
+        w.z = c.take<double>(N);
+        w.p = c.take<double>(N);
+        w.q = c.take<double>(N);
+        w.cg = c.take<double>(8);
+        w.hist = c.take<double>(2 * RB_MAX_CG_ITERS);
+    }
     w.scratch = c.take<char>(0);
     return w;
 }
@@ -512,17 +668,19 @@ int selected_count(int m, int dmin) {
 
 }  // namespace
 
-size_t invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int nf, rb_dtype dt, int batch) {
+size_t invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int nf, rb_dtype dt, int batch,
+                              bool cg) {
     Carver c(nullptr, 0);
-    carve_inv(c, g, nf, dt);
+    carve_inv(c, g, nf, dt, cg);
     return c.used + 256 + scratch_need(g, t, nf, dt, batch);
 }
 
+// cg_iters = 0: the single step; cg_iters >= 1: CG (cg_hist [host] may be null).
 rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o, const double *c_in,
-                      const double *alpha0, const double *freqs, int nf, const double *p_meas, double *c_out,
-                      double *dc_l2, void *ws, size_t ws_bytes, hipStream_t st) {
+                      const double *alpha0, const double *freqs, int nf, const double *p_meas, int cg_iters,
+                      double *c_out, double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes, hipStream_t st) {
     Carver c(ws, ws_bytes);
-    InvWs w = carve_inv(c, g, nf, o->dtype);
+    InvWs w = carve_inv(c, g, nf, o->dtype, cg_iters > 0);
     if (c.used + 256 + trace_workspace_bytes(g, t, 1) > ws_bytes ||
         c.used + 256 + std::max(adjoint_workspace_bytes(g, nf, o->dtype),
                                 forward_workspace_bytes(g, nf, o->dtype)) > ws_bytes) {
@@ -576,25 +734,59 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
                         scratch_bytes, st));
     RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin, reinterpret_cast<int *>(w.zl),
                              w.nz, m * m, w.hd, st));
-    // 4. diagonally weighted direction on the support
     RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
-    k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.v);
-    RB_LAUNCHED();
-    // 5. exact step length along v
-    RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.v, w.Jv, scratch, scratch_bytes, st));
-    k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.D, w.part);
-    RB_LAUNCHED();
-    k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
-    RB_LAUNCHED();
+    const double *delta_dir = w.v;  // the update is res[2] * delta_dir
+    if (cg_iters == 0) {
+        // 4. diagonally weighted direction on the support
+        k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.v);
+        RB_LAUNCHED();
+        // 5. exact step length along v
+        RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.v, w.Jv, scratch, scratch_bytes,
+                            st));
+        k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.D, w.part);
+        RB_LAUNCHED();
+        k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
+        RB_LAUNCHED();
+    } else {
+        // 4-5. preconditioned CG from delta = 0
+        k_cg_start<<<kRB, 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.x, w.r, w.z, w.p, w.part);
+        RB_LAUNCHED();
+        k_cg_rz_final<<<1, 256, 0, st>>>(w.part, kRB, w.cg, 1);
+        RB_LAUNCHED();
+        for (int it = 0; it < cg_iters; ++it) {
+            RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.p, w.Jv, scratch, scratch_bytes,
+                                st));
+            // second partial component: <J p, W J p>
+            k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.Jv, w.part);
+            RB_LAUNCHED();
+            k_cg_alpha<<<1, 256, 0, st>>>(w.part, kRB, w.cg, w.hist, it);
+            RB_LAUNCHED();
+            if (it + 1 == cg_iters) break;
+            RB_TRY(fill_f64(w.q, 0.0, N, st));
+            RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.Jv, w.W, w.q, nullptr, scratch,
+                                scratch_bytes, st));
+            k_cg_step<<<kRB, 256, 0, st>>>(N, w.q, w.hd, w.S, w.hmax, o->eps, w.cg, w.x, w.p, w.r, w.z, w.part);
+            RB_LAUNCHED();
+            k_cg_rz_final<<<1, 256, 0, st>>>(w.part, kRB, w.cg, 0);
+            RB_LAUNCHED();
+            k_cg_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.z, w.cg, w.p);
+            RB_LAUNCHED();
+        }
+        k_cg_last<<<blocks_for(N, 256), 256, 0, st>>>(N, w.cg, w.p, w.x, w.res);
+        RB_LAUNCHED();
+        delta_dir = w.x;
+    }
     // 6. update of 1/c^2 and the update norm
-    k_update_partial<<<kRB, 256, 0, st>>>(N, c_in, w.s, w.v, w.res, w.part);
+    k_update_partial<<<kRB, 256, 0, st>>>(N, c_in, w.s, delta_dir, w.res, w.part);
     RB_LAUNCHED();
     k_update_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
     RB_LAUNCHED();
-    k_update_write<<<blocks_for(N, 256), 256, 0, st>>>(N, c_in, w.s, w.v, w.res, c_out);
+    k_update_write<<<blocks_for(N, 256), 256, 0, st>>>(N, c_in, w.s, delta_dir, w.res, c_out);
     RB_LAUNCHED();
     double res[8];
     RB_HIP(hipMemcpyAsync(res, w.res, sizeof(res), hipMemcpyDeviceToHost, st));
+    if (cg_iters > 0 && cg_hist)
+        RB_HIP(hipMemcpyAsync(cg_hist, w.hist, sizeof(double) * 2 * cg_iters, hipMemcpyDeviceToHost, st));
     RB_HIP(hipStreamSynchronize(st));
     if (res[4] != 0.0) {
         if (dc_l2) *dc_l2 = 0.0;
@@ -613,14 +805,19 @@ size_t rb_invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, i
                                  int32_t emitter_batch) {
     if (rb::check_trace(g, t) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
     if (dtype < RB_F64 || dtype > RB_F16) return 0;
-    return rb::invert_workspace_bytes(g, t, nf, dtype, emitter_batch);
+    return rb::invert_workspace_bytes(g, t, nf, dtype, emitter_batch, false);
 }
 
-rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
-                                  const double *c_in, const double *alpha0, const double *freqs_hz, int32_t nf,
-                                  const double *p_meas, double *c_out, double *dc_l2, void *ws, size_t ws_bytes,
-                                  void *stream) {
-    rb::clear_error();
+size_t rb_invert_cg_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int32_t nf, rb_dtype dtype,
+                                    int32_t emitter_batch) {
+    if (rb::check_trace(g, t) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
+    if (dtype < RB_F64 || dtype > RB_F16) return 0;
+    return rb::invert_workspace_bytes(g, t, nf, dtype, emitter_batch, true);
+}
+
+static rb_status check_invert_args(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                                   const double *c_in, const double *freqs_hz, int32_t nf, const double *p_meas,
+                                   double *c_out, void *ws) {
     RB_TRY(rb::check_trace(g, t));
     RB_TRY(rb::check_freqs(freqs_hz, nf));
     RB_CHECK_ARG(o != nullptr, "invert options are NULL");
@@ -631,8 +828,28 @@ rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t, 
     RB_CHECK_ARG(std::isfinite(o->y_pow), "y_pow must be finite");
     RB_CHECK_ARG(c_in && p_meas && c_out, "c_in/p_meas/c_out are NULL");
     RB_CHECK_ARG(ws != nullptr, "workspace is NULL");
-    return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, c_out, dc_l2, ws, ws_bytes,
+    return RB_OK;
+}
+
+rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                                  const double *c_in, const double *alpha0, const double *freqs_hz, int32_t nf,
+                                  const double *p_meas, double *c_out, double *dc_l2, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    rb::clear_error();
+    RB_TRY(check_invert_args(g, t, o, c_in, freqs_hz, nf, p_meas, c_out, ws));
+    return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, 0, c_out, dc_l2, nullptr, ws, ws_bytes,
                            rb::as_stream(stream));
+}
+
+rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                                     const double *c_in, const double *alpha0, const double *freqs_hz, int32_t nf,
+                                     const double *p_meas, int32_t n_iter, double *c_out, double *dc_l2,
+                                     double *cg_hist, void *ws, size_t ws_bytes, void *stream) {
+    rb::clear_error();
+    RB_TRY(check_invert_args(g, t, o, c_in, freqs_hz, nf, p_meas, c_out, ws));
+    RB_CHECK_ARG(n_iter >= 1 && n_iter <= RB_MAX_CG_ITERS, "n_iter must be in [1, %d]", RB_MAX_CG_ITERS);
+    return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, n_iter, c_out, dc_l2, cg_hist, ws,
+                           ws_bytes, rb::as_stream(stream));
 }
 
 }  // extern "C"

@@ -91,3 +91,28 @@ def test_binding_raises_with_message():
     assert "invalid argument" in str(ei.value)
     with pytest.raises(rb.NumericError):
         rb._binding._check(-5)
+
+
+@pytest.mark.parametrize("n_iter", [0, -3, 65])
+def test_cg_iteration_count_is_checked_on_host(n_iter):
+    g = _geom()
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5)
+    L = rb.lib()
+    from paper_2511_16633_amd._binding import _freqs, geometry_struct, invert_opts_struct, trace_opts_struct
+    fa, nf = _freqs([2e5, 3e5])
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    hist = (ctypes.c_double * 4)()
+    out = ctypes.c_double(0.0)
+    rc = L.rb_invert_frequency_set_cg(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                                      ctypes.byref(invert_opts_struct(W.InvertOpts(), "f32")), fake, None, fa,
+                                      nf, fake, n_iter, fake, ctypes.byref(out), hist, fake, 1 << 30, None)
+    assert rc == -1
+    assert b"n_iter" in L.rb_last_error()
+
+
+def test_cg_workspace_holds_the_single_step_workspace():
+    g = _geom()
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5)
+    a = rb.invert_workspace_bytes(g, t, 2, "bf16")
+    b = rb.invert_cg_workspace_bytes(g, t, 2, "bf16")
+    assert b >= a + 5 * 8 * g.nx * g.ny
