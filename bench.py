@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--emitter-batch", type=int, default=0, help="emitters traced per batch (0: all that fit)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop latency measurement")
     ap.add_argument("--serving-jobs", type=int, default=24)
+    ap.add_argument("--cg-iters", type=int, default=10,
+                    help="CG iterations for the CG-solved set timing (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -216,6 +218,45 @@ def main():
     }
     stages = {k: round(v, 3) for k, v in stages.items()}
 
+    # ---- the linear subproblem of set 0 solved by CG instead of the single
+    # step: whole set (trace, tables, CG) for 1 and for K iterations
+    cg = None
+    if args.cg_iters > 0:
+        del fws
+        cws = torch.empty(rb.invert_cg_workspace_bytes(g, topts, nf, args.dtype, batch), dtype=torch.uint8,
+                          device=dev)
+        ccg = torch.empty_like(c_start)
+
+        def cg_set(k):
+            ccg.copy_(c_start)
+            return rb.invert_frequency_set_cg(g, topts, prob.inv, args.dtype, ccg, alpha, fs, pms[0], k, ccg,
+                                              ws=cws, stream=stream)
+
+        def one_set():
+            ccg.copy_(c_start)
+            return rb.invert_frequency_set(g, topts, prob.inv, args.dtype, ccg, alpha, fs, pms[0], ccg, ws=cws,
+                                           stream=stream)
+
+        t_one = timed(one_set)
+        t_1 = timed(lambda: cg_set(1))
+        t_k = timed(lambda: cg_set(args.cg_iters))
+        _, alphas, rzs = cg_set(args.cg_iters)
+        # algorithmic work of one extra iteration: the weighted adjoint
+        # (8 flop per pixel, selected pair, frequency) and the forward over the
+        # selected pairs, symmetric in e and r (4 flop per unit)
+        t_it = (t_k - t_1) / max(args.cg_iters - 1, 1)
+        it_flop = 12.0 * N * P * nf
+        cg = {"iters": args.cg_iters, "ms_per_set": round(t_k, 3), "ms_per_set_one_iteration": round(t_1, 3),
+              "ms_per_set_single_step": round(t_one, 3),
+              "ms_per_extra_iteration": round(t_it, 3),
+              "iteration_tflops": round(it_flop / (t_it * 1e-3) / 1e12, 3),
+              "iteration_frac": round(it_flop / (t_it * 1e-3) / 1e12 / PEAK[args.dtype], 4),
+              "rz_first_last": [rzs[0], rzs[-1]]}
+        print(f"[bench] CG set 0: {args.cg_iters} iterations {t_k:.2f} ms, 1 iteration {t_1:.2f} ms, "
+              f"single step {t_one:.2f} ms", file=sys.stderr, flush=True)
+        del cws, ccg
+        fws = None
+
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpixel·pair·freq/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
@@ -228,6 +269,8 @@ def main():
                                  + "FP64 rays/phase, " + args.dtype + " contractions",
                       "pixels": N, "selected_pairs": P, "frequencies": F, "pixel_pair_freq_per_step": units},
            "roofline": roofline, "stages_ms_per_set": stages}
+    if cg is not None:
+        out["cg"] = cg
 
     if large:
         out["config"]["emitter_batch"] = batch

@@ -2,9 +2,11 @@
 rb_invert_frequency_set_cg) against the FP64 oracle's preconditioned CG.
 
 Tolerances: the update and the per-iteration step lengths alpha_i within
-rel 1e-4 (f64 contractions; the remaining difference comes from the ray
-tables, |dT| <= 1e-9 s) and 1e-3 (f32 contractions) over a few iterations;
-the first CG iterate equals the single step up to rounding.
+rel 1e-5 (f64 and f32 contractions; the remaining difference comes from the
+ray tables, |dT| <= 1e-9 s, measured 3e-7 for the update over six
+iterations); 16-bit contractions within 5e-3 (bf16) and 1e-3 (f16) of the
+FP64 oracle over three iterations (measured 8.7e-4 and 1.1e-4); the first CG
+iterate equals the single step up to rounding.
 """
 import dataclasses
 import sys
@@ -47,7 +49,7 @@ def _pm(p_meas):
     return _t(np.stack([p_meas.real, p_meas.imag], -1))
 
 
-TOL = {"f64": 1e-4, "f32": 1e-3}
+TOL = {"f64": 1e-5, "f32": 1e-5}
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -130,8 +132,9 @@ def test_cg_ragged_in_place_and_repeatable(rb):
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
     dc_g = outs[0][0] - p.c_start.reshape(-1)
     dc_o = ref["c_new"].reshape(-1) - p.c_start.reshape(-1)
-    assert _rel(dc_g, dc_o) <= TOL["f32"]
-    assert _rel(outs[0][2], ref["alpha"]) <= TOL["f32"]
+    ed, ea = _rel(dc_g, dc_o), _rel(outs[0][2], ref["alpha"])
+    _say(f"  rel dc {ed:.2e}  rel alpha {ea:.2e}")
+    assert ed <= 1e-4 and ea <= 1e-4
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
@@ -152,4 +155,5 @@ def test_cg_16bit_against_fp64_oracle(rb, dtype):
     dc_o = ref["c_new"].reshape(-1) - p.c_start.reshape(-1)
     ed, ea = _rel(dc_g, dc_o), _rel(alphas, ref["alpha"])
     _say(f"  rel dc {ed:.2e}  rel alpha {ea:.2e}")
-    assert ed <= 0.05 and ea <= 0.05
+    tol = {"bf16": 5e-3, "f16": 1e-3}[dtype]
+    assert ed <= tol and ea <= tol

@@ -185,5 +185,5 @@ def test_fullsize_cg_three_iterations(rb, prob):
     ea = np.linalg.norm(np.asarray(alphas) - ref["alpha"]) / np.linalg.norm(ref["alpha"])
     print(f"[gpu-case] full-size cg: rel-L2 {rel:.3e}, rel alpha {ea:.3e}, max|dc diff| "
           f"{np.abs(dc_g - dc_o).max():.3e} m/s, norms {l2:.4f} vs {ref['dc_l2']:.4f}", flush=True)
-    assert rel <= 3e-3 and ea <= 3e-3
-    assert abs(l2 - ref["dc_l2"]) <= 3e-3 * ref["dc_l2"]
+    assert rel <= 1e-4 and ea <= 1e-4
+    assert abs(l2 - ref["dc_l2"]) <= 1e-4 * ref["dc_l2"]
