@@ -36,6 +36,7 @@ def lib():
         _lib.orc_tables.restype = ctypes.c_int
         _lib.orc_trace_fan.restype = ctypes.c_int
         _lib.orc_order_bits.restype = ctypes.c_int
+        _lib.orc_rx_links.restype = ctypes.c_int
     return _lib
 
 
@@ -77,6 +78,28 @@ def trace_fan(geom, topts, s: np.ndarray, alpha, e: int) -> dict:
     out["L"] = L
     out["tau"] = np.arange(P.nmax + 1) * P.dtau
     return out
+
+
+def rx_links(geom, topts, s: np.ndarray, alpha, e: int) -> dict:
+    """Emitter e's fan and its first arrivals at the ring elements with the
+    winning triangle: x, y [(nmax+1)][n_rays], L [n_rays], T [m] (NaN if
+    uncovered), tri [m] = 2 (n n_rays + j) + t (-1 if uncovered) and the
+    barycentrics bary [m][3] of the element in that triangle."""
+    P = make_params(geom, topts)
+    s = np.ascontiguousarray(s, np.float64).reshape(-1)
+    al = None if alpha is None else np.ascontiguousarray(alpha, np.float64).reshape(-1)
+    shape = (P.nmax + 1, P.n_rays)
+    x = np.full(shape, np.nan)
+    y = np.full(shape, np.nan)
+    L = np.zeros(P.n_rays, np.int32)
+    T = np.empty(geom.m)
+    W = np.empty(geom.m, np.int64)
+    bary = np.empty((geom.m, 3))
+    rc = lib().orc_rx_links(ctypes.byref(P), _p(s), None if al is None else _p(al), int(e), _p(x), _p(y),
+                            _p(L), _p(T), _p(W), _p(bary))
+    if rc != 0:
+        raise MemoryError("oracle rx_links: allocation failed")
+    return {"x": x, "y": y, "L": L, "T": T, "tri": W, "bary": bary, "nmax": P.nmax}
 
 
 def tables(geom, topts, s: np.ndarray, alpha, e0: int = 0, e1: int | None = None):

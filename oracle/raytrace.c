@@ -238,7 +238,8 @@ static void raster_grid(const orc_params *P, double scale, const vtx *A, const v
 
 static void raster_points(const orc_params *P, double scale, const vtx *A, const vtx *B, const vtx *C,
                           int npts, const double *px, const double *py,
-                          uint64_t *Q, double *T, double *Am, double *Bt)
+                          uint64_t *Q, double *T, double *Am, double *Bt,
+                          int64_t tri_index, int64_t *Wi, double *Wl)
 {
     double e1x = B->x - A->x, e1y = B->y - A->y;
     double e2x = C->x - A->x, e2y = C->y - A->y;
@@ -266,6 +267,10 @@ static void raster_points(const orc_params *P, double scale, const vtx *A, const
             T[r] = la * A->t + lb * B->t + lc * C->t;
             Am[r] = la * A->a + lb * B->a + lc * C->a;
             Bt[r] = la * A->b + lb * B->b + lc * C->b;
+            if (Wi) {   /* the winning triangle and the point's barycentrics */
+                Wi[r] = tri_index;
+                Wl[3 * r] = la; Wl[3 * r + 1] = lb; Wl[3 * r + 2] = lc;
+            }
         }
     }
 }
@@ -317,15 +322,62 @@ int orc_tables(const orc_params *P, const double *s, const double *alpha, int e0
                 vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11], u1};
                 vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01], u1};
                 raster_grid(P, scale, &p00, &p10, &p11, Q, Te, Ae, Be);
-                raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, Tr, Ar, Br);
+                raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
                 raster_grid(P, scale, &p00, &p11, &p01, Q, Te, Ae, Be);
-                raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, Tr, Ar, Br);
+                raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
             }
         }
         free(X); free(L); free(Q);
     }
     free(px); free(py);
     return status;
+}
+
+/*
+ * First arrivals of emitter e's fan at the ring elements, with the winning
+ * triangle: for every element r, T[r] (NaN if uncovered), the triangle
+ * index W[r] = 2 (n n_rays + j) + t (t = 0: (P[n][j], P[n][j+1],
+ * P[n+1][j+1]); t = 1: (P[n][j], P[n+1][j+1], P[n+1][j]); -1 if uncovered)
+ * and the element's barycentrics (la, lb, lc) in it, in the order of those
+ * vertices.  Same rule and arithmetic as orc_tables.  The fan's nodes are
+ * returned in X, Y ([(nmax+1) n_rays]) and L ([n_rays]) as by orc_trace_fan.
+ */
+int orc_rx_links(const orc_params *P, const double *s, const double *alpha, int e,
+                 double *X, double *Y, int32_t *L, double *T, int64_t *W, double *Wl)
+{
+    const int nr = P->n_rays, m = P->m;
+    size_t nn = (size_t)(P->nmax + 1) * nr;
+    double *buf = (double *)malloc(sizeof(double) * nn * 4 + sizeof(double) * 4 * m);
+    uint64_t *Qr = (uint64_t *)malloc(sizeof(uint64_t) * m);
+    if (!buf || !Qr) { free(buf); free(Qr); return -2; }
+    double *PX = buf, *PY = PX + nn, *Bn = PY + nn, *AMP = Bn + nn;
+    double *px = AMP + nn, *py = px + m, *Ar = py + m, *Br = Ar + m;
+    for (int r = 0; r < m; ++r) {
+        double th = 2.0 * M_PI * (double)r / (double)m;
+        px[r] = P->R * cos(th); py[r] = P->R * sin(th);
+        Qr[r] = UINT64_MAX; T[r] = NAN; W[r] = -1;
+        Wl[3 * r] = Wl[3 * r + 1] = Wl[3 * r + 2] = 0.0;
+    }
+    orc_trace_fan(P, s, alpha, e, X, Y, PX, PY, Bn, AMP, L);
+    const double scale = ldexp(1.0, orc_order_bits(P));
+    for (int n = 0; n < P->nmax; ++n) {
+        for (int j = 0; j + 1 < nr; ++j) {
+            if (n + 1 > L[j] || n + 1 > L[j + 1]) continue;
+            size_t k00 = (size_t)n * nr + j, k10 = k00 + 1;
+            size_t k01 = k00 + nr, k11 = k01 + 1;
+            double t0 = (double)n * P->dtau, t1 = (double)(n + 1) * P->dtau;
+            const double u0 = (double)n, u1 = (double)(n + 1);
+            vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00], u0};
+            vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10], u0};
+            vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11], u1};
+            vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01], u1};
+            const int64_t cell = (int64_t)n * nr + j;
+            raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, T, Ar, Br, 2 * cell, W, Wl);
+            raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, T, Ar, Br, 2 * cell + 1, W, Wl);
+        }
+    }
+    free(buf); free(Qr);
+    return 0;
 }
 
 /* Bilinear slowness and gradient at arbitrary points (used by tests). */

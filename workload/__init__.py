@@ -239,14 +239,44 @@ def straight_ray_data(geom: Geometry, c: np.ndarray, alpha: np.ndarray,
     sqrt(c_bg/(8 pi omega L)), with a +pi/4 phase.  Diagonal (e == r) is 0.
     """
     m = geom.m
-    pos = geom.element_positions()
-    s = 1.0 / c
-    nsamp = int(math.ceil(2.0 * geom.ring_radius / (0.5 * geom.h)))
-    t_mid = (np.arange(nsamp) + 0.5) / nsamp
     nf = len(freqs)
     out = np.zeros((nf, m, m), np.complex128)
     omega = 2.0 * math.pi * np.asarray(freqs, np.float64)
     fm = (np.asarray(freqs, np.float64) * 1e-6) ** y_pow
+    rows = _chord_integrals(geom, c, alpha)
+    for e in range(m):
+        L, T, Bab = rows[e]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            for k in range(nf):
+                amp = np.sqrt(geom.c_background / (8.0 * math.pi * omega[k] * L))
+                val = amp * np.exp(-Bab * fm[k]) * np.exp(1j * (omega[k] * T + 0.25 * math.pi))
+                val[L == 0.0] = 0.0
+                out[k, e, :] = val
+    if noise_rel > 0.0:
+        rng = np.random.default_rng(seed)
+        rms = np.sqrt(np.mean(np.abs(out) ** 2, axis=(1, 2), keepdims=True))
+        out = out + noise_rel * rms * (rng.standard_normal(out.shape)
+                                       + 1j * rng.standard_normal(out.shape)) / math.sqrt(2.0)
+    return out
+
+
+def straight_ray_tof(geom: Geometry, c: np.ndarray) -> np.ndarray:
+    """Stand-in for picked times of flight, [m][m] seconds: the straight-chord
+    travel time of straight_ray_data (NaN for e == r)."""
+    rows = _chord_integrals(geom, c, np.zeros_like(c))
+    T = np.stack([r[1] for r in rows])
+    T[np.arange(geom.m), np.arange(geom.m)] = np.nan
+    return T
+
+
+def _chord_integrals(geom: Geometry, c: np.ndarray, alpha: np.ndarray):
+    """Per emitter: chord lengths, travel times and absorption integrals to
+    every element (midpoint rule, nearest-pixel values, water outside)."""
+    m = geom.m
+    pos = geom.element_positions()
+    s = 1.0 / c
+    nsamp = int(math.ceil(2.0 * geom.ring_radius / (0.5 * geom.h)))
+    t_mid = (np.arange(nsamp) + 0.5) / nsamp
     s_bg = 1.0 / geom.c_background
 
     def emitter_row(e):
@@ -267,23 +297,8 @@ def straight_ray_data(geom: Geometry, c: np.ndarray, alpha: np.ndarray,
     workers = max(1, min(16, os.cpu_count() or 1)) if m >= 128 else 1
     if workers > 1:
         with ThreadPoolExecutor(workers) as ex:
-            rows = list(ex.map(emitter_row, range(m)))
-    else:
-        rows = [emitter_row(e) for e in range(m)]
-    for e in range(m):
-        L, T, Bab = rows[e]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            for k in range(nf):
-                amp = np.sqrt(geom.c_background / (8.0 * math.pi * omega[k] * L))
-                val = amp * np.exp(-Bab * fm[k]) * np.exp(1j * (omega[k] * T + 0.25 * math.pi))
-                val[L == 0.0] = 0.0
-                out[k, e, :] = val
-    if noise_rel > 0.0:
-        rng = np.random.default_rng(seed)
-        rms = np.sqrt(np.mean(np.abs(out) ** 2, axis=(1, 2), keepdims=True))
-        out = out + noise_rel * rms * (rng.standard_normal(out.shape)
-                                       + 1j * rng.standard_normal(out.shape)) / math.sqrt(2.0)
-    return out
+            return list(ex.map(emitter_row, range(m)))
+    return [emitter_row(e) for e in range(m)]
 
 
 def random_tables(geom: Geometry, seed: int, t_scale: float | None = None,
