@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=24)
     ap.add_argument("--cg-iters", type=int, default=10,
                     help="CG iterations for the CG-solved set timing (0: skip)")
+    ap.add_argument("--tof-iters", type=int, default=3,
+                    help="iterations of the ToF starting-model timing (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -257,6 +259,29 @@ def main():
         del cws, ccg
         fws = None
 
+    # ---- the ToF starting model: bent-ray ToF inversion from water against
+    # straight-chord ToFs of the true phantom (the stand-in for picked ToFs)
+    tof = None
+    if args.tof_iters > 0:
+        T_meas = torch.as_tensor(W.straight_ray_tof(g, prob.c_true), device=dev)
+        c_w = torch.full_like(c_start, g.c_background)
+        c_t = torch.empty_like(c_start)
+        tws_tof = torch.empty(rb.tof_workspace_bytes(g, topts), dtype=torch.uint8, device=dev)
+        rb.tof_invert(g, topts, prob.inv, c_w, T_meas, 1, c_t, ws=tws_tof, stream=stream)   # warm-up
+        t_tof = timed(lambda: rb.tof_invert(g, topts, prob.inv, c_w, T_meas, args.tof_iters, c_t, ws=tws_tof,
+                                            stream=stream), reps=2)
+        rms, betas = rb.tof_invert(g, topts, prob.inv, c_w, T_meas, args.tof_iters, c_t, ws=tws_tof, stream=stream)
+        ct = torch.as_tensor(prob.c_true.reshape(-1), device=dev)
+        err0 = float(torch.linalg.vector_norm(c_w - ct)) / math.sqrt(N)
+        err1 = float(torch.linalg.vector_norm(c_t - ct)) / math.sqrt(N)
+        tof = {"iters": args.tof_iters, "ms": round(t_tof, 3), "ms_per_iteration": round(t_tof / args.tof_iters, 3),
+               "rms_tof_residual_s": [float("%.4g" % r) for r in rms],
+               "rms_speed_error_m_s": [round(err0, 3), round(err1, 3)]}
+        print(f"[bench] ToF start: {args.tof_iters} iterations {t_tof:.2f} ms, rms residual "
+              f"{rms[0]:.3g} -> {rms[-1]:.3g} s, speed error {err0:.2f} -> {err1:.2f} m/s", file=sys.stderr,
+              flush=True)
+        del T_meas, c_w, c_t, tws_tof, ct
+
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpixel·pair·freq/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
@@ -271,6 +296,8 @@ def main():
            "roofline": roofline, "stages_ms_per_set": stages}
     if cg is not None:
         out["cg"] = cg
+    if tof is not None:
+        out["tof"] = tof
 
     if large:
         out["config"]["emitter_batch"] = batch

@@ -7,8 +7,9 @@
  * high-frequency Green's functions (Forward Problem section, Eqs. 4-7), the
  * Born forward and weighted adjoint contractions and the diagonally weighted
  * single step (Inverse Problem section, Eqs. 8-10 and the single-step
- * paragraph), and the conjugate-gradient solution of the same linear
- * subproblem that the single step replaces.
+ * paragraph), the conjugate-gradient solution of the same linear
+ * subproblem that the single step replaces, and the bent-ray time-of-flight
+ * inversion that provides the starting model.
  *
  * Conventions shared by every entry point:
  *  - Pointers are DEVICE pointers unless marked [host].  The caller owns and
@@ -256,6 +257,45 @@ rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *
                                      const double *p_meas, int32_t n_iter, double *c_out,
                                      double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes,
                                      void *stream);
+
+/*
+ * Starting model by bent-ray time-of-flight (ToF) inversion (Results
+ * section: the ray-Born sweep starts from a low-resolution image from three
+ * iterations of a ToF-based method that fits measured ToFs with ToFs
+ * modelled along rays; Discussion: ray linking).  Per iteration:
+ *  1. trace rays in c (s = 1/c, no absorption); the modelled ToF T_er is the
+ *     first-arrival time at element r (the T_rx table of rb_trace_rays);
+ *  2. linking path of (e, r): the first-arrival triangle at r, of cell
+ *     (n, j), gives the step index u and the weight w of ray j + 1
+ *     (triangle (P[n][j], P[n][j+1], P[n+1][j+1]): w = lb + lc; triangle
+ *     (P[n][j], P[n+1][j+1], P[n+1][j]): w = lb); the path is ray j with
+ *     weight 1 - w plus ray j + 1 with weight w, each from the emitter to
+ *     parameter u (nodes 0 .. floor(u), then the point at frac(u) along
+ *     the next segment);
+ *  3. used pairs: circular index distance >= ceil((1 - recv_fraction) m / 2),
+ *     T_meas finite and r covered; residual dT = T_meas - T on them;
+ *  4. Fermat linearisation dT = L ds: L[er][p] = sum over the path's points
+ *     of (path weight) x (half the two adjacent segment lengths) x (bilinear
+ *     weight of pixel centre p at the point);
+ *  5. g = L^T dT, ray density C = L^T 1; on S (|x| < R - margin and C > 0)
+ *     v = g / (C + eps max_S C), 0 elsewhere;
+ *  6. beta = <L v, dT> / <L v, L v> (0 if the denominator is 0);
+ *     s += beta v, c = 1/s where beta v != 0.
+ * o: recv_fraction and eps are used (the other fields are ignored).
+ * c_in, c_out: [N] FP64 m/s (may alias).  T_meas: [m][m] FP64 seconds,
+ * NaN where no ToF was measured.  n_iter: 1 .. 64.  hist: [host][2 n_iter]
+ * or NULL; receives (rms dT over the used pairs before the update, beta)
+ * per iteration.  The call synchronises `stream` once per iteration.
+ * Every emitter's fan stays resident: ws: rb_tof_workspace_bytes() (about
+ * the trace workspace of one batch of all m emitters).  The back-projection
+ * uses floating-point atomics, so repeated calls agree to rounding, not
+ * bitwise.  Returns RB_ENUMERIC, leaving c_out unwritten, if an update would
+ * make s <= 0 somewhere.
+ */
+size_t rb_tof_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t);
+rb_status rb_tof_invert(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                        const double *c_in, const double *T_meas, int32_t n_iter, double *c_out,
+                        double *hist, void *ws, size_t ws_bytes, void *stream);
 
 /* Static description of a status code. */
 const char *rb_status_string(rb_status s);

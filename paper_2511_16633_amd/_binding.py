@@ -88,6 +88,9 @@ def lib():
         "rb_invert_frequency_set_cg": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp,
                                                       _vp, _P(_d), _i32, _vp, _i32, _vp, _P(_d), _P(_d), _vp,
                                                       _sz, _vp]),
+        "rb_tof_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts)]),
+        "rb_tof_invert": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp, _vp, _i32, _vp,
+                                         _P(_d), _vp, _sz, _vp]),
         "rb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "rb_last_error": (ctypes.c_char_p, []),
         "rb_version": (ctypes.c_char_p, []),
@@ -281,3 +284,21 @@ def invert_frequency_set_cg(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional
                                             hist, _ptr(ws), ws.numel(), _stream(stream)))
     h = list(hist)
     return out.value, h[0::2][:n_iter], h[1::2][:n_iter]
+
+
+def tof_workspace_bytes(g, t) -> int:
+    return int(lib().rb_tof_workspace_bytes(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t))))
+
+
+def tof_invert(g, t, o, c_in: torch.Tensor, T_meas: torch.Tensor, n_iter: int, c_out: torch.Tensor,
+               ws: Optional[torch.Tensor] = None, stream=None):
+    """Bent-ray ToF starting model.  Returns (rms ToF residual before each
+    iteration, beta of each iteration); synchronises the stream."""
+    if ws is None:
+        ws = _ws(tof_workspace_bytes(g, t), c_in.device)
+    hist = (ctypes.c_double * (2 * max(int(n_iter), 1)))()
+    _check(lib().rb_tof_invert(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                               ctypes.byref(invert_opts_struct(o, "f64")), _ptr(c_in), _ptr(T_meas), int(n_iter),
+                               _ptr(c_out), hist, _ptr(ws), ws.numel(), _stream(stream)))
+    h = list(hist)
+    return h[0::2][:n_iter], h[1::2][:n_iter]

@@ -626,6 +626,33 @@ TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int
     return w;
 }
 
+TP make_tp(const rb_geometry *g, const rb_trace_opts *t) {
+    TP P;
+    P.nx = g->nx; P.ny = g->ny; P.h = g->h; P.x0 = g->x0; P.y0 = g->y0;
+    P.inv_h = 1.0 / g->h;
+    P.m = g->m; P.R = g->ring_radius; P.s_bg = 1.0 / g->c_background;
+    P.nr = t->n_rays; P.dtau = t->dtau; P.nmax = (int)trace_nmax(t);
+    const double r_die = g->ring_radius + 2.0 * g->h;
+    P.rdie2 = r_die * r_die;
+    P.j_min = t->j_min > 0.0 ? t->j_min : 0.25 * g->h;
+    P.bary_tol = 1e-12;
+    const double dpsi = M_PI / (double)t->n_rays;
+    P.inv_chord_full = 1.0 / (2.0 * std::sin(dpsi));
+    P.inv_chord_half = 1.0 / (2.0 * std::sin(0.5 * dpsi));
+    P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
+    P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
+    {
+        // arrival keys: triangle index in the low bits, fixed-point step index above
+        auto bit_length = [](uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; };
+        const uint64_t nidx = 2ull * (uint64_t)P.nmax * (uint64_t)P.nr;
+        P.idx_bits = bit_length(nidx - 1);
+        P.qscale = std::ldexp(1.0, 64 - P.idx_bits - bit_length((uint64_t)P.nmax));
+    }
+    P.e0 = 0;
+    P.ne = 0;
+    return P;
+}
+
 }  // namespace
 
 size_t trace_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int batch) {
@@ -664,29 +691,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     char *base = reinterpret_cast<char *>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     Carver c(base, ws_bytes - (size_t)(base - (char *)ws));
     TraceWs w = carve_trace(c, g, t, batch);
-
-    TP P;
-    P.nx = g->nx; P.ny = g->ny; P.h = g->h; P.x0 = g->x0; P.y0 = g->y0;
-    P.inv_h = 1.0 / g->h;
-    P.m = g->m; P.R = g->ring_radius; P.s_bg = 1.0 / g->c_background;
-    P.nr = t->n_rays; P.dtau = t->dtau; P.nmax = (int)trace_nmax(t);
-    const double r_die = g->ring_radius + 2.0 * g->h;
-    P.rdie2 = r_die * r_die;
-    P.j_min = t->j_min > 0.0 ? t->j_min : 0.25 * g->h;
-    P.bary_tol = 1e-12;
-    const double dpsi = M_PI / (double)t->n_rays;
-    P.inv_chord_full = 1.0 / (2.0 * std::sin(dpsi));
-    P.inv_chord_half = 1.0 / (2.0 * std::sin(0.5 * dpsi));
-    P.ring2_lo = (g->ring_radius * (1.0 - 2e-9)) * (g->ring_radius * (1.0 - 2e-9));
-    P.ring2_hi = (g->ring_radius * (1.0 + 2e-9)) * (g->ring_radius * (1.0 + 2e-9));
-    {
-        // arrival keys: triangle index in the low bits, fixed-point step index above
-        auto bit_length = [](uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; };
-        const uint64_t nidx = 2ull * (uint64_t)P.nmax * (uint64_t)P.nr;
-        P.idx_bits = bit_length(nidx - 1);
-        P.qscale = std::ldexp(1.0, 64 - P.idx_bits - bit_length((uint64_t)P.nmax));
-    }
-
+    TP P = make_tp(g, t);
     const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
     k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, 1.0 / g->c_background, slowness, alpha0, w.sa);
     RB_LAUNCHED();
@@ -735,6 +740,418 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     return RB_OK;
 }
 
+// ------------------------------------------------------------- ToF model
+// Bent-ray time-of-flight inversion for the starting model (Results
+// section: a low-resolution image from three iterations of a ToF-based
+// method that fits measured ToFs with ToFs modelled along rays).  The
+// modelled ToF is the first-arrival time at a ring element; its linking
+// path is read from the first-arrival triangle there: rays j and j + 1 of
+// the cell, weighted 1 - w and w by the element's barycentrics, from the
+// emitter to the step index u of the arrival.  Fermat's principle gives the
+// linearisation dT = integral of ds along the path, with ds bilinear in the
+// pixel values; along each polyline every point carries half of its two
+// adjacent segment lengths (trapezoid rule).
+namespace {
+
+constexpr int kTofRB = kReduceBlocks;
+
+__global__ void k_tof_slowness(const double *__restrict__ c, int64_t n, double *__restrict__ s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = 1.0 / c[i];
+}
+
+// Per ordered pair (e, r): modelled ToF from the arrival key, the linking
+// path (j, u, w; j = -1 if the pair is not used) and the residual
+// dT = T_meas - T on the used pairs (selected, measured, covered), with
+// used[] = 1.0 / 0.0.
+__global__ void k_tof_link(TP P, int dmin, const double2 *__restrict__ XY, const double2 *__restrict__ rxy,
+                           const uint64_t *__restrict__ akey_rx, const double *__restrict__ T_meas,
+                           int *__restrict__ lj, double2 *__restrict__ luw, double *__restrict__ dT,
+                           double *__restrict__ used) {
+    const int64_t mm = (int64_t)P.m * P.m;
+    const int64_t pr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pr >= mm) return;
+    const int e = (int)(pr / P.m), r = (int)(pr - (int64_t)e * P.m);
+    const int d0 = e > r ? e - r : r - e;
+    const int dist = d0 < P.m - d0 ? d0 : P.m - d0;
+    const uint64_t key = akey_rx[pr];
+    const double tm = T_meas[pr];
+    int j = -1;
+    double u = 0.0, w = 0.0, res = 0.0;
+    if (dist >= dmin && key != ~0ull && isfinite(tm)) {
+        const uint32_t wk = (uint32_t)(key & ((1ull << P.idx_bits) - 1ull));
+        const int tri = (int)(wk & 1u);
+        const uint32_t cell = wk >> 1;
+        const int n = (int)(cell / (uint32_t)P.nr);
+        const int jc = (int)(cell - (uint32_t)n * (uint32_t)P.nr);
+        if (n < P.nmax && jc < P.nr - 1) {
+            const int64_t base = (int64_t)e * (P.nmax + 1) * P.nr;
+            int64_t ka, kb, kc;
+            int na, nb, nc;
+            tri_nodes(base, n, jc, P.nr, tri, ka, kb, kc, na, nb, nc);
+            Tri t;
+            const double2 pa = XY[ka], pb = XY[kb], pc = XY[kc];
+            make_tri(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, t);
+            const double2 q = rxy[r];
+            double la, lb, lc;
+            bary(t, q.x, q.y, -P.bary_tol, la, lb, lc);
+            const double tv = la * ((double)na * P.dtau) + lb * ((double)nb * P.dtau) + lc * ((double)nc * P.dtau);
+            u = la * (double)na + lb * (double)nb + lc * (double)nc;
+            u = fmin(fmax(u, 0.0), (double)(n + 1));
+            w = tri == 0 ? lb + lc : lb;
+            j = jc;
+            res = tm - tv;
+        }
+    }
+    lj[pr] = j;
+    luw[pr] = make_double2(u, w);
+    dT[pr] = res;
+    used[pr] = j >= 0 ? 1.0 : 0.0;
+}
+
+// Point i of ray q's path to parameter u (K = floor(u) nodes, then the
+// fractional end point).
+__device__ __forceinline__ double2 tof_point(const double2 *__restrict__ XY, int64_t base, int nr, int q, int i,
+                                             int K, double fr) {
+    if (i <= K) return XY[base + (int64_t)i * nr + q];
+    const double2 a = XY[base + (int64_t)K * nr + q], b = XY[base + (int64_t)(K + 1) * nr + q];
+    return make_double2(a.x + fr * (b.x - a.x), a.y + fr * (b.y - a.y));
+}
+
+// Bilinear weights of the four pixel centres around (x, y); idx = -1 for
+// corners outside the grid.
+__device__ __forceinline__ void tof_hat(const TP &P, double x, double y, int idx[4], double wt[4]) {
+    const double u = (x - P.x0) * P.inv_h, v = (y - P.y0) * P.inv_h;
+    const double fi = floor(u), fj = floor(v);
+    const double fu = u - fi, fv = v - fj;
+    const int i = (int)fmax(fmin(fi, 2e9), -2e9), jj = (int)fmax(fmin(fj, 2e9), -2e9);
+    const int ci[4] = {i, i + 1, i, i + 1}, cj[4] = {jj, jj, jj + 1, jj + 1};
+    const double w4[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - fv), (1.0 - fu) * fv, fu * fv};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool ok = ci[c] >= 0 && ci[c] < P.nx && cj[c] >= 0 && cj[c] < P.ny;
+        idx[c] = ok ? cj[c] * P.nx + ci[c] : -1;
+        wt[c] = ok ? w4[c] : 0.0;
+    }
+}
+
+// One wave per pair.  SCATTER: g += L^T dT and C += L^T 1 (atomics);
+// otherwise Lv[pair] = L v (fixed-order wave sum).
+template <bool SCATTER>
+__global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restrict__ XY, const int *__restrict__ lj,
+                                                  const double2 *__restrict__ luw, const double *__restrict__ dT,
+                                                  double *__restrict__ g, double *__restrict__ C,
+                                                  const double *__restrict__ v, double *__restrict__ Lv) {
+    const int lane = threadIdx.x & 63;
+    const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t mm = (int64_t)P.m * P.m;
+    if (pr >= mm) return;   // wave-uniform
+    const int j = lj[pr];
+    if (j < 0) {
+        if (!SCATTER && lane == 0) Lv[pr] = 0.0;
+        return;
+    }
+    const int e = (int)(pr / P.m);
+    const double2 uw = luw[pr];
+    const double u = uw.x;
+    const int K = (int)floor(u);
+    const double fr = u - (double)K;
+    const int npts = K + 1 + (fr > 0.0 ? 1 : 0);
+    const int64_t base = (int64_t)e * (P.nmax + 1) * P.nr;
+    const double res = SCATTER ? dT[pr] : 0.0;
+    double acc = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int q = j + side;
+        const double wq = side ? uw.y : 1.0 - uw.y;
+        for (int i = lane; i < npts; i += 64) {
+            const double2 pc = tof_point(XY, base, P.nr, q, i, K, fr);
+            double om = 0.0;
+            if (i > 0) {
+                const double2 pp = tof_point(XY, base, P.nr, q, i - 1, K, fr);
+                om += 0.5 * sqrt((pc.x - pp.x) * (pc.x - pp.x) + (pc.y - pp.y) * (pc.y - pp.y));
+            }
+            if (i + 1 < npts) {
+                const double2 pn = tof_point(XY, base, P.nr, q, i + 1, K, fr);
+                om += 0.5 * sqrt((pn.x - pc.x) * (pn.x - pc.x) + (pn.y - pc.y) * (pn.y - pc.y));
+            }
+            int idx[4];
+            double wt[4];
+            tof_hat(P, pc.x, pc.y, idx, wt);
+            const double f = wq * om;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (idx[c] < 0) continue;
+                if (SCATTER) {
+                    unsafeAtomicAdd(&g[idx[c]], f * wt[c] * res);
+                    unsafeAtomicAdd(&C[idx[c]], f * wt[c]);
+                } else {
+                    acc += f * wt[c] * v[idx[c]];
+                }
+            }
+        }
+    }
+    if (!SCATTER) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) Lv[pr] = acc;
+    }
+}
+
+// Support: inside |x| < R - margin and crossed by some used path (C > 0).
+__global__ void k_tof_support(TP P, double rs, const double *__restrict__ C, uint8_t *__restrict__ S) {
+    const int64_t N = (int64_t)P.nx * P.ny;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int64_t jj = p / P.nx, ii = p - jj * P.nx;
+    const double px = P.x0 + (double)ii * P.h, py = P.y0 + (double)jj * P.h;
+    S[p] = (px * px + py * py < rs * rs && C[p] > 0.0) ? 1 : 0;
+}
+
+__global__ void k_tof_direction(int64_t n, const double *__restrict__ g, const double *__restrict__ C,
+                                const uint8_t *__restrict__ S, const double *__restrict__ cmax, double eps,
+                                double *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double cm = cmax[0] > -INFINITY ? cmax[0] : 0.0;
+    v[i] = S[i] ? g[i] / (C[i] + eps * cm) : 0.0;
+}
+
+// Fixed-order block sums of a.b, b.b and a.a over [0, n): part[3 b + 0..2].
+__global__ void k_tof_sums(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                           double *__restrict__ part) {
+    __shared__ double s0[256], s1[256], s2[256];
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double ai = a[i], bi = b[i];
+        x0 += ai * bi;
+        x1 += bi * bi;
+        x2 += ai * ai;
+    }
+    s0[threadIdx.x] = x0;
+    s1[threadIdx.x] = x1;
+    s2[threadIdx.x] = x2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s0[threadIdx.x] += s0[threadIdx.x + st];
+            s1[threadIdx.x] += s1[threadIdx.x + st];
+            s2[threadIdx.x] += s2[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = s0[0];
+        part[3 * blockIdx.x + 1] = s1[0];
+        part[3 * blockIdx.x + 2] = s2[0];
+    }
+}
+
+// res[slot + 0..2] = the three sums.
+__global__ void k_tof_sums_final(const double *__restrict__ part, int np, double *__restrict__ res, int slot) {
+    __shared__ double s0[256], s1[256], s2[256];
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) {
+        x0 += part[3 * i];
+        x1 += part[3 * i + 1];
+        x2 += part[3 * i + 2];
+    }
+    s0[threadIdx.x] = x0;
+    s1[threadIdx.x] = x1;
+    s2[threadIdx.x] = x2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s0[threadIdx.x] += s0[threadIdx.x + st];
+            s1[threadIdx.x] += s1[threadIdx.x + st];
+            s2[threadIdx.x] += s2[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        res[slot] = s0[0];
+        res[slot + 1] = s1[0];
+        res[slot + 2] = s2[0];
+    }
+}
+
+// res: [1] sum dT^2, [2] number of used pairs (the (used, dT) sums);
+// [3] <Lv, dT>, [5] <Lv, Lv> (the (Lv, dT) sums).  The update check counts
+// the pixels with s + beta v <= 0, beta = res[3] / res[5].
+__global__ void k_tof_update_check(int64_t n, const double *__restrict__ s, const double *__restrict__ v,
+                                   double *__restrict__ res, double *__restrict__ part) {
+    __shared__ double sb[256];
+    const double beta = res[5] > 0.0 ? res[3] / res[5] : 0.0;
+    double bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double ds = beta * v[i];
+        if (ds != 0.0 && !(s[i] + ds > 0.0)) bad += 1.0;
+    }
+    sb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sb[threadIdx.x] += sb[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sb[0];
+}
+
+// res[6] = beta, res[7] = number of failed pixels
+__global__ void k_tof_update_final(const double *__restrict__ part, int np, double *__restrict__ res) {
+    __shared__ double sb[256];
+    double bad = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) bad += part[i];
+    sb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sb[threadIdx.x] += sb[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        res[6] = res[5] > 0.0 ? res[3] / res[5] : 0.0;
+        res[7] = sb[0];
+    }
+}
+
+// c = 1 / (s + beta v) where beta v != 0, if no pixel failed the check.
+__global__ void k_tof_update_write(int64_t n, const double *__restrict__ s, const double *__restrict__ v,
+                                   const double *__restrict__ res, double *__restrict__ c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || res[7] != 0.0) return;
+    const double ds = res[6] * v[i];
+    if (ds != 0.0) c[i] = 1.0 / (s[i] + ds);
+}
+
+struct TofWs {
+    double *c, *s, *g, *C, *v, *dT, *used, *Lv, *part, *res, *cmax;
+    double2 *luw;
+    int *lj;
+    uint8_t *S;
+    uint64_t *akey_rx;
+    TraceWs tw;
+};
+
+TofWs carve_tof(Carver &c, const rb_geometry *g, const rb_trace_opts *t) {
+    const size_t N = (size_t)g->nx * g->ny, mm = (size_t)g->m * g->m;
+    TofWs w;
+    w.c = c.take<double>(N);
+    w.s = c.take<double>(N);
+    w.g = c.take<double>(N);
+    w.C = c.take<double>(N);
+    w.v = c.take<double>(N);
+    w.S = c.take<uint8_t>(N);
+    w.dT = c.take<double>(mm);
+    w.used = c.take<double>(mm);
+    w.Lv = c.take<double>(mm);
+    w.luw = c.take<double2>(mm);
+    w.lj = c.take<int>(mm);
+    w.akey_rx = c.take<uint64_t>(mm);
+    w.part = c.take<double>(3 * kTofRB);
+    w.res = c.take<double>(8);
+    w.cmax = c.take<double>(1);
+    w.tw = carve_trace(c, g, t, g->m);   // every emitter's fan stays resident
+    return w;
+}
+
+}  // namespace
+
+size_t tof_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t) {
+    Carver c(nullptr, 0);
+    carve_tof(c, g, t);
+    return c.used + 256;
+}
+
+// n_iter linearised ToF iterations from c_in; hist [host][2 n_iter] (nullable)
+// receives (rms dT before the update, beta) per iteration.
+rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                          const double *c_in, const double *T_meas, int n_iter, double *c_out, double *hist,
+                          void *ws, size_t ws_bytes, hipStream_t st) {
+    if (tof_workspace_bytes(g, t) > ws_bytes) {
+        set_error("ToF workspace too small: need %zu bytes, got %zu", tof_workspace_bytes(g, t), ws_bytes);
+        return RB_ENOMEM;
+    }
+    char *base = reinterpret_cast<char *>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    Carver cv(base, ws_bytes - (size_t)(base - (char *)ws));
+    TofWs w = carve_tof(cv, g, t);
+    TP P = make_tp(g, t);
+    P.e0 = 0;
+    P.ne = g->m;
+    const int64_t N = (int64_t)g->nx * g->ny;
+    const int m = g->m;
+    const int64_t mm = (int64_t)m * m;
+    const int dmin = (int)std::ceil((1.0 - o->recv_fraction) * 0.5 * m - 1e-9);
+    const double rs = g->ring_radius - g->support_margin;
+    RB_HIP(hipMemcpyAsync(w.c, c_in, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    k_rx_pos<<<blocks_for(m, 256), 256, 0, st>>>(P, w.tw.rxy);
+    RB_LAUNCHED();
+    const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
+    const int waves = (P.nr + kOwn - 1) / kOwn;
+    const int cap = cell_seg_cap(t);
+    const int nseg = (int)cell_segments(g, t, m);
+    for (int it = 0; it < n_iter; ++it) {
+        // rays and first arrivals at the ring elements in the current model
+        k_tof_slowness<<<blocks_for(N, 256), 256, 0, st>>>(w.c, N, w.s);
+        RB_LAUNCHED();
+        k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, P.s_bg, w.s, nullptr, w.tw.sa);
+        RB_LAUNCHED();
+        RB_TRY(fill_u64(w.akey_rx, ~0ull, mm, st));
+        k_trace<<<dim3((waves + 3) / 4, m), 256, 0, st>>>(P, w.tw.sa, w.tw.XY, w.tw.AB, w.tw.L);
+        RB_LAUNCHED();
+        const unsigned gc = blocks_for(P.nr - 1, 64) * kCellGroupsY * m;
+        k_cells<<<gc, 256, 0, st>>>(P, w.tw.XY, w.tw.L, cap, w.tw.list_px, w.tw.list_rx, w.tw.seg_px,
+                                    w.tw.seg_rx);
+        RB_LAUNCHED();
+        k_raster_rx<<<blocks_for(nseg, 4), 256, 0, st>>>(P, w.tw.XY, nseg, cap, w.tw.list_rx, w.tw.seg_rx,
+                                                          w.tw.rxy, w.akey_rx);
+        RB_LAUNCHED();
+        // linking paths and residuals
+        k_tof_link<<<blocks_for(mm, 256), 256, 0, st>>>(P, dmin, w.tw.XY, w.tw.rxy, w.akey_rx, T_meas, w.lj,
+                                                         w.luw, w.dT, w.used);
+        RB_LAUNCHED();
+        k_tof_sums<<<kTofRB, 256, 0, st>>>(mm, w.used, w.dT, w.part);
+        RB_LAUNCHED();
+        k_tof_sums_final<<<1, 256, 0, st>>>(w.part, kTofRB, w.res, 0);   // res[1] sum dT^2, [2] used pairs
+        RB_LAUNCHED();
+        // back-projection of the residuals and the ray density
+        RB_TRY(fill_f64(w.g, 0.0, N, st));
+        RB_TRY(fill_f64(w.C, 0.0, N, st));
+        const unsigned gp = (unsigned)((mm + 3) / 4);
+        k_tof_path<true><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, w.dT, w.g, w.C, nullptr, nullptr);
+        RB_LAUNCHED();
+        k_tof_support<<<blocks_for(N, 256), 256, 0, st>>>(P, rs, w.C, w.S);
+        RB_LAUNCHED();
+        RB_TRY(reduce_max_f64(w.C, w.S, N, w.part, w.cmax, st));
+        k_tof_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.g, w.C, w.S, w.cmax, o->eps, w.v);
+        RB_LAUNCHED();
+        // exact step along v
+        k_tof_path<false><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, nullptr, nullptr, nullptr, w.v, w.Lv);
+        RB_LAUNCHED();
+        k_tof_sums<<<kTofRB, 256, 0, st>>>(mm, w.Lv, w.dT, w.part);
+        RB_LAUNCHED();
+        k_tof_sums_final<<<1, 256, 0, st>>>(w.part, kTofRB, w.res, 3);   // res[3] <Lv,dT>, [4] dT^2, [5] <Lv,Lv>
+        RB_LAUNCHED();
+        k_tof_update_check<<<kTofRB, 256, 0, st>>>(N, w.s, w.v, w.res, w.part);
+        RB_LAUNCHED();
+        k_tof_update_final<<<1, 256, 0, st>>>(w.part, kTofRB, w.res);
+        RB_LAUNCHED();
+        k_tof_update_write<<<blocks_for(N, 256), 256, 0, st>>>(N, w.s, w.v, w.res, w.c);
+        RB_LAUNCHED();
+        double res[8];
+        RB_HIP(hipMemcpyAsync(res, w.res, sizeof(res), hipMemcpyDeviceToHost, st));
+        RB_HIP(hipStreamSynchronize(st));
+        if (hist) {
+            hist[2 * it] = res[2] > 0.0 ? std::sqrt(res[1] / res[2]) : 0.0;
+            hist[2 * it + 1] = res[6];
+        }
+        if (res[7] != 0.0) {
+            set_error("slowness update not positive at %.0f pixels (iteration %d); c_out not written", res[7], it);
+            return RB_ENUMERIC;
+        }
+    }
+    RB_HIP(hipMemcpyAsync(c_out, w.c, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    RB_HIP(hipStreamSynchronize(st));
+    return RB_OK;
+}
+
 rb_status check_tables(const rb_tables *t) {
     RB_CHECK_ARG(t != nullptr, "tables are NULL");
     RB_CHECK_ARG(t->T && t->amp && t->att && t->T_rx && t->amp_rx && t->att_rx,
@@ -760,6 +1177,25 @@ rb_status rb_trace_rays(const rb_geometry *g, const rb_trace_opts *t, const doub
     RB_CHECK_ARG(ws != nullptr, "workspace is NULL");
     return rb::trace_rays_impl(g, t, slowness, alpha0, out, ws, ws_bytes, rb::as_stream(stream), nullptr,
                                nullptr);
+}
+
+size_t rb_tof_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t) {
+    if (rb::check_trace(g, t) != RB_OK) return 0;
+    return rb::tof_workspace_bytes(g, t);
+}
+
+rb_status rb_tof_invert(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                        const double *c_in, const double *T_meas, int32_t n_iter, double *c_out, double *hist,
+                        void *ws, size_t ws_bytes, void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_trace(g, t));
+    RB_CHECK_ARG(o != nullptr, "invert options are NULL");
+    RB_CHECK_ARG(o->recv_fraction > 0.0 && o->recv_fraction <= 1.0, "recv_fraction must be in (0, 1]");
+    RB_CHECK_ARG(std::isfinite(o->eps) && o->eps >= 0.0, "eps must be >= 0");
+    RB_CHECK_ARG(n_iter >= 1 && n_iter <= 64, "n_iter must be in [1, 64]");
+    RB_CHECK_ARG(c_in && T_meas && c_out, "c_in/T_meas/c_out are NULL");
+    RB_CHECK_ARG(ws != nullptr, "workspace is NULL");
+    return rb::tof_invert_impl(g, t, o, c_in, T_meas, n_iter, c_out, hist, ws, ws_bytes, rb::as_stream(stream));
 }
 
 }  // extern "C"
