@@ -19,6 +19,7 @@
 //    on the (step, ray, triangle) index among the triangles that attain it,
 //    pass 3 recomputes the winner's barycentrics per point.  The result is
 //    independent of scheduling.
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -818,25 +819,40 @@ __device__ __forceinline__ double2 tof_point(const double2 *__restrict__ XY, int
     return make_double2(a.x + fr * (b.x - a.x), a.y + fr * (b.y - a.y));
 }
 
-// Bilinear weights of the four pixel centres around (x, y); idx = -1 for
-// corners outside the grid.
-__device__ __forceinline__ void tof_hat(const TP &P, double x, double y, int idx[4], double wt[4]) {
-    const double u = (x - P.x0) * P.inv_h, v = (y - P.y0) * P.inv_h;
-    const double fi = floor(u), fj = floor(v);
-    const double fu = u - fi, fv = v - fj;
-    const int i = (int)fmax(fmin(fi, 2e9), -2e9), jj = (int)fmax(fmin(fj, 2e9), -2e9);
-    const int ci[4] = {i, i + 1, i, i + 1}, cj[4] = {jj, jj, jj + 1, jj + 1};
-    const double w4[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - fv), (1.0 - fu) * fv, fu * fv};
+// One wave per pair.  SCATTER: g += L^T dT and C += L^T 1 (atomics);
+// otherwise Lv[pair] = L v (fixed-order wave sum).  Every lane walks one
+// contiguous run of point indices on both rays of the path at once; the
+// points go into two register accumulators keyed by grid cell, so the
+// points that share a cell (two to three consecutive ones at a step of
+// about half a pixel, and mostly the neighbouring ray's as well) reach
+// memory as one atomic per corner.
+struct TofAcc {
+    int ci, cj;
+    int idx[4];
+    double ag[4], ac[4];
+};
+
+__device__ __forceinline__ void tof_acc_flush(TofAcc &a, double *__restrict__ g, double *__restrict__ C) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const bool ok = ci[c] >= 0 && ci[c] < P.nx && cj[c] >= 0 && cj[c] < P.ny;
-        idx[c] = ok ? cj[c] * P.nx + ci[c] : -1;
-        wt[c] = ok ? w4[c] : 0.0;
+        if (a.idx[c] < 0) continue;
+        unsafeAtomicAdd(&g[a.idx[c]], a.ag[c]);
+        unsafeAtomicAdd(&C[a.idx[c]], a.ac[c]);
     }
 }
 
-// One wave per pair.  SCATTER: g += L^T dT and C += L^T 1 (atomics);
-// otherwise Lv[pair] = L v (fixed-order wave sum).
+__device__ __forceinline__ void tof_acc_open(const TP &P, TofAcc &a, int ci, int cj) {
+    a.ci = ci;
+    a.cj = cj;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int ii = ci + (c & 1), jj = cj + (c >> 1);
+        a.idx[c] = (ii >= 0 && ii < P.nx && jj >= 0 && jj < P.ny) ? jj * P.nx + ii : -1;
+        a.ag[c] = 0.0;
+        a.ac[c] = 0.0;
+    }
+}
+
 template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restrict__ XY, const int *__restrict__ lj,
                                                   const double2 *__restrict__ luw, const double *__restrict__ dT,
@@ -859,38 +875,88 @@ __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restric
     const int npts = K + 1 + (fr > 0.0 ? 1 : 0);
     const int64_t base = (int64_t)e * (P.nmax + 1) * P.nr;
     const double res = SCATTER ? dT[pr] : 0.0;
+    const int per = (npts + 63) >> 6;
+    const int i0 = lane * per, i1 = min(npts, i0 + per);
+    const double wq[2] = {1.0 - uw.y, uw.y};
     double acc = 0.0;
-    for (int side = 0; side < 2; ++side) {
-        const int q = j + side;
-        const double wq = side ? uw.y : 1.0 - uw.y;
-        for (int i = lane; i < npts; i += 64) {
-            const double2 pc = tof_point(XY, base, P.nr, q, i, K, fr);
-            double om = 0.0;
-            if (i > 0) {
-                const double2 pp = tof_point(XY, base, P.nr, q, i - 1, K, fr);
-                om += 0.5 * sqrt((pc.x - pp.x) * (pc.x - pp.x) + (pc.y - pp.y) * (pc.y - pp.y));
-            }
-            if (i + 1 < npts) {
-                const double2 pn = tof_point(XY, base, P.nr, q, i + 1, K, fr);
-                om += 0.5 * sqrt((pn.x - pc.x) * (pn.x - pc.x) + (pn.y - pc.y) * (pn.y - pc.y));
-            }
-            int idx[4];
-            double wt[4];
-            tof_hat(P, pc.x, pc.y, idx, wt);
-            const double f = wq * om;
+    // two accumulators held in registers (no dynamic indexing)
+    TofAcc A0, A1;
+    A0.ci = A1.ci = INT_MIN;
+    A0.cj = A1.cj = INT_MIN;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (idx[c] < 0) continue;
-                if (SCATTER) {
-                    unsafeAtomicAdd(&g[idx[c]], f * wt[c] * res);
-                    unsafeAtomicAdd(&C[idx[c]], f * wt[c]);
-                } else {
-                    acc += f * wt[c] * v[idx[c]];
+    for (int c = 0; c < 4; ++c) {
+        A0.idx[c] = A1.idx[c] = -1;
+        A0.ag[c] = A0.ac[c] = A1.ag[c] = A1.ac[c] = 0.0;
+    }
+    bool victim1 = false;   // A1 (else A0) is replaced next
+    if (i0 < i1) {
+        double2 pc[2];
+        double lprev[2] = {0.0, 0.0};
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            pc[sd] = tof_point(XY, base, P.nr, j + sd, i0, K, fr);
+            if (i0 > 0) {
+                const double2 pp = tof_point(XY, base, P.nr, j + sd, i0 - 1, K, fr);
+                lprev[sd] = sqrt((pc[sd].x - pp.x) * (pc[sd].x - pp.x) + (pc[sd].y - pp.y) * (pc[sd].y - pp.y));
+            }
+        }
+        for (int i = i0; i < i1; ++i) {
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+                double lnext = 0.0;
+                double2 pn = pc[sd];
+                if (i + 1 < npts) {
+                    pn = tof_point(XY, base, P.nr, j + sd, i + 1, K, fr);
+                    lnext = sqrt((pn.x - pc[sd].x) * (pn.x - pc[sd].x) + (pn.y - pc[sd].y) * (pn.y - pc[sd].y));
                 }
+                const double f = wq[sd] * (0.5 * lprev[sd] + 0.5 * lnext);
+                // bilinear weights of the four pixel centres around the point
+                const double uu = (pc[sd].x - P.x0) * P.inv_h, vv = (pc[sd].y - P.y0) * P.inv_h;
+                const double fi = floor(uu), fj = floor(vv);
+                const double fu = uu - fi, fv = vv - fj;
+                const int ci = (int)fmax(fmin(fi, 1e9), -1e9), cj = (int)fmax(fmin(fj, 1e9), -1e9);
+                const double wt[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - fv), (1.0 - fu) * fv, fu * fv};
+                if (SCATTER) {
+                    bool use1;
+                    if (A0.ci == ci && A0.cj == cj) {
+                        use1 = false;
+                    } else if (A1.ci == ci && A1.cj == cj) {
+                        use1 = true;
+                    } else {
+                        use1 = victim1;
+                        if (use1) {
+                            tof_acc_flush(A1, g, C);
+                            tof_acc_open(P, A1, ci, cj);
+                        } else {
+                            tof_acc_flush(A0, g, C);
+                            tof_acc_open(P, A0, ci, cj);
+                        }
+                    }
+                    victim1 = !use1;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double x = f * wt[c];
+                        A0.ag[c] += use1 ? 0.0 : x * res;
+                        A0.ac[c] += use1 ? 0.0 : x;
+                        A1.ag[c] += use1 ? x * res : 0.0;
+                        A1.ac[c] += use1 ? x : 0.0;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int ii = ci + (c & 1), jj = cj + (c >> 1);
+                        if (ii >= 0 && ii < P.nx && jj >= 0 && jj < P.ny) acc += f * wt[c] * v[jj * P.nx + ii];
+                    }
+                }
+                lprev[sd] = lnext;
+                pc[sd] = pn;
             }
         }
     }
-    if (!SCATTER) {
+    if (SCATTER) {
+        tof_acc_flush(A0, g, C);
+        tof_acc_flush(A1, g, C);
+    } else {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
         if (lane == 0) Lv[pr] = acc;
