@@ -187,3 +187,31 @@ def test_fullsize_cg_three_iterations(rb, prob):
           f"{np.abs(dc_g - dc_o).max():.3e} m/s, norms {l2:.4f} vs {ref['dc_l2']:.4f}", flush=True)
     assert rel <= 1e-4 and ea <= 1e-4
     assert abs(l2 - ref["dc_l2"]) <= 1e-4 * ref["dc_l2"]
+
+
+def test_fullsize_tof_start(rb, prob):
+    """The ToF starting model at the bench workload's size, from water:
+    before the first update every ray is straight, so the rms residual
+    equals that of the straight-ray times chord / c (to the wavefront sag);
+    the residual then falls at every iteration and the model moves toward
+    the phantom."""
+    g = prob.geom
+    c0 = np.full((g.ny, g.nx), g.c_background)
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    T_meas = W.straight_ray_tof(g, prob.c_true)
+    pos = g.element_positions()
+    chord = np.hypot(pos[:, None, 0] - pos[None, :, 0], pos[:, None, 1] - pos[None, :, 1])
+    sel = invert.receiver_mask(g.m, prob.inv.recv_fraction)
+    rms_water = math.sqrt(float(np.mean((T_meas - chord / g.c_background)[sel] ** 2)))
+    _say("full-size ToF start, 3 iterations from water")
+    c_in = _t(c0.reshape(-1))
+    c_out = torch.empty_like(c_in)
+    rms, betas = rb.tof_invert(g, topts, prob.inv, c_in, _t(T_meas), 3, c_out)
+    c = c_out.cpu().numpy()
+    print(f"[gpu-case] full-size ToF: rms {rms} (straight rays {rms_water:.4e}), beta {betas}", flush=True)
+    assert abs(rms[0] / rms_water - 1.0) <= 1e-2
+    assert rms[1] < rms[0] and rms[2] < rms[1]
+    assert all(b > 0 for b in betas)
+    ct = prob.c_true.reshape(-1)
+    assert np.linalg.norm(c - ct) < 0.6 * np.linalg.norm(c0.reshape(-1) - ct)
+    assert np.all(np.isfinite(c)) and c.min() > 1300.0 and c.max() < 1700.0
