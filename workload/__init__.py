@@ -367,6 +367,18 @@ def small_ring(seed: int = 1000, with_data: bool = True) -> Problem:
     return p
 
 
+def small_ring_fullwave(seed: int = 1000, refine: int = 4) -> Problem:
+    """The 64-element workload with full-wave data (Helmholtz FD on a grid
+    `refine` times finer than the pixels) in place of the straight-ray
+    stand-in: measured data from a wave model other than the inversion's."""
+    from .fullwave import helmholtz_data
+    p = small_ring(seed, with_data=False)
+    p.p_meas = [helmholtz_data(p.geom, p.c_true, p.alpha0, f, y_pow=p.inv.y_pow, refine=refine)
+                for f in p.freq_sets]
+    p.name = p.name + "_fullwave"
+    return p
+
+
 def breast_ring256(seed: int = 1001, with_data: bool = True, dtype: str = "f32") -> Problem:
     """256-element ring, R = 110 mm, 480x480 grid at 0.5 mm, breast phantom;
     24 frequencies 0.3-1.25 MHz in 8 sets of 3; start = truth smoothed 4 mm."""
