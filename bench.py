@@ -345,10 +345,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# Contraction type per serving size class: FP32 for the 64- and 256-element
+# jobs, BF16 (FP32 accumulation, FP64 phase) for the 1024-element jobs, as
+# the large instance is specified.
+SERVING_DTYPES = ("f32", "f32", "bf16")
+
+
 def serving_report(dev, n_jobs):
     """Latency of the serving loop on a Poisson stream (0.5 jobs/s, sizes
-    64/256/1024 elements in the ratio 5:4:1, FP32 contractions), against the
-    same jobs served one at a time (plain sequential runs)."""
+    64/256/1024 elements in the ratio 5:4:1; contraction type per class as
+    in SERVING_DTYPES), against the same jobs run one at a time in plain
+    FP32 (sequential baseline)."""
     import copy
     import torch
     import workload as W
@@ -359,9 +366,9 @@ def serving_report(dev, n_jobs):
     for sp in specs:
         p = W.serving_job(sp["size_class"], sp["seed"], sp["ring_radius"])
         topts = W.resolve_trace_opts(p.geom, p.c_start, p.trace.n_rays)
-        jobs.append(S.Job(jid=sp["job"], arrival=sp["arrival_s"], geom=p.geom, topts=topts, inv=p.inv, dtype="f32",
-                          c_start=p.c_start, alpha0=p.alpha0, freq_sets=p.freq_sets, p_meas=p.p_meas,
-                          size_class=sp["size_class"]))
+        jobs.append(S.Job(jid=sp["job"], arrival=sp["arrival_s"], geom=p.geom, topts=topts, inv=p.inv,
+                          dtype=SERVING_DTYPES[sp["size_class"]], c_start=p.c_start, alpha0=p.alpha0,
+                          freq_sets=p.freq_sets, p_meas=p.p_meas, size_class=sp["size_class"]))
     print(f"[bench] serving: {n_jobs} jobs generated in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
     srv = S.Server(dev, max_running=4)
     mixed = srv.run(jobs, realtime=True)
@@ -369,18 +376,30 @@ def serving_report(dev, n_jobs):
           file=sys.stderr, flush=True)
     service, same = [], True
     for j in jobs:
+        # alone, as served (bitwise check), then alone in plain FP32 (baseline)
         a = copy.copy(j)
         a.result = None
         torch.cuda.synchronize()
         t = time.perf_counter()
         S.run_job(a, dev)
-        service.append(time.perf_counter() - t)
+        t_alone = time.perf_counter() - t
         same = same and a.result is not None and j.result is not None and bool(np.array_equal(a.result, j.result))
+        if j.dtype != "f32":
+            a = copy.copy(j)
+            a.result = None
+            a.dtype = "f32"
+            S.plan(a, srv.budget // 2)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.run_job(a, dev)
+            t_alone = time.perf_counter() - t
+        service.append(t_alone)
     seq = S.sequential_baseline(jobs, service)
     counts = [sum(1 for j in jobs if j.size_class == c) for c in range(3)]
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
     return {"stream": f"Poisson 0.5 jobs/s, {n_jobs} jobs, seed 42; ring64_grid128 / ring256_grid480 / "
-                      f"ring1024_grid1100 = {counts[0]} / {counts[1]} / {counts[2]}; ring radius 80-120 mm; f32",
+                      f"ring1024_grid1100 = {counts[0]} / {counts[1]} / {counts[2]}; ring radius 80-120 mm; "
+                      f"served in {' / '.join(SERVING_DTYPES)}, baseline plain f32 one job at a time",
             "budget_gib": round(srv.budget / 2**30, 1), "max_running": srv.max_running,
             "served": rnd(mixed), "sequential_plain": rnd(seq), "same_alone_and_mixed": same}
 
