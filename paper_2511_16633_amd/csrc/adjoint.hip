@@ -391,7 +391,9 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
             auto load_a = [&](int rc, f4 (&va)[2][2], f4 (&vi)[2][2], f4 (&vw)[2][2]) {
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const int64_t off = (int64_t)(ec + 32 * we + 16 * b + row) * P.mp + rc + 8 * kk;
+                    // rows beyond mp (when mp is not a multiple of 64) read row
+                    // mp - 1: finite values whose products the epilogue drops
+                    const int64_t off = (int64_t)min(ec + 32 * we + 16 * b + row, P.mp - 1) * P.mp + rc + 8 * kk;
                     va[b][0] = *reinterpret_cast<const f4 *>(ar + off);
                     va[b][1] = *reinterpret_cast<const f4 *>(ar + off + 4);
                     vi[b][0] = *reinterpret_cast<const f4 *>(ai + off);

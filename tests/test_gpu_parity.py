@@ -172,7 +172,8 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
-@pytest.mark.parametrize("shape", [(37, 29, 40), (64, 64, 64), (21, 50, 97), (30, 30, 48), (24, 23, 300)])
+@pytest.mark.parametrize("shape", [(37, 29, 40), (64, 64, 64), (21, 50, 97), (30, 30, 48), (24, 23, 300),
+                                   (26, 19, 90)])
 def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
     nx, ny, m = shape
     geom = W.centred_grid(nx, 0.5e-3, m, 12e-3, 1500.0)
