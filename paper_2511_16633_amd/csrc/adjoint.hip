@@ -377,16 +377,25 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = z[b][c] = f4{0, 0, 0, 0};
+            // Chunks of 32 receivers in which one of this wave's two 16-row
+            // blocks has a nonzero weight, as wave-uniform bit masks
+            // (nch <= 128): a flag load inside the loop would make the MFMAs
+            // of a chunk wait for the next chunk's tile, which is issued first.
+            uint64_t cm[2] = {0, 0};
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int eb = (ec >> 4) + 2 * we + b, c = 64 * h + lane;
+                    const bool on =
+                        eb < P.nb && c < nch && (fl[eb * P.nb + 2 * c] | fl[eb * P.nb + 2 * c + 1]) != 0;
+                    cm[h] |= __ballot(on);
+                }
             // The A fragments of chunk c + 1 are loaded during chunk c, along
             // with its G tile, so the MFMAs of a chunk wait only for LDS.
             auto chunk_on = [&](int rc) {
-                bool any = false;
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int eb = (ec >> 4) + 2 * we + b;
-                    any |= (eb < P.nb) && (fl[eb * P.nb + (rc >> 4)] | fl[eb * P.nb + (rc >> 4) + 1]);
-                }
-                return any;
+                const int c = rc / kAdjKC;
+                return ((((c < 64) ? cm[0] : cm[1]) >> (c & 63)) & 1) != 0;
             };
             auto load_a = [&](int rc, f4 (&va)[2][2], f4 (&vi)[2][2], f4 (&vw)[2][2]) {
 #pragma unroll
