@@ -14,6 +14,7 @@ struct AdjParams {
 
 struct FwdParams {
     int m, mp, nf, ntl, ntri, nsplit;
+    int dmin;              // >= 32: diagonal 32 x 32 blocks need not be computed
     int64_t N, kchunk;
     double cg[RB_MAX_NF];  // omega^2 h^2
 };
@@ -25,10 +26,13 @@ size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt);
 rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
                        rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
                        double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st);
-// d_out = J delta, [nf][m][m] complex.
+// d_out = J delta, [nf][m][m] complex.  With dmin >= 32 (a caller that
+// weights every pair of circular index distance below dmin by zero) the
+// 32/16-bit kernels may return 0 for the pairs of a diagonal 32 x 32 block,
+// all of which lie below that distance.
 rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
                        rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
-                       size_t ws_bytes, hipStream_t st);
+                       size_t ws_bytes, hipStream_t st, int dmin = 0);
 
 // hdiag += Hessian diagonal for band-selection weights with zeroed pairs
 // (see rb_born_hessian_banded); zeroed: [nf][zcap] (e, r), nzero: [nf].

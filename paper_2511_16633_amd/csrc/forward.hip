@@ -230,6 +230,10 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
     const int nch = (int)((ke - ks + kFwdKC - 1) / kFwdKC);
     const int srow = tid >> 2, c8 = (tid & 3) * 8;
     const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
+    // On a diagonal tile the block below the diagonal (e > r) is never
+    // read, and with dmin >= 32 neither are the two diagonal blocks: those
+    // waves only stage (wave-uniform).
+    const bool idle = te == tr && (we > wr || (we == wr && P.dmin >= 32));
     // (a + ib)(c + id) with three real products: P1 = ac, P2 = bd,
     // P3 = (a + b)(c + d); re = P1 - P2, im = P3 - P1 - P2
     f4 p1[2][2], p2[2][2], p3[2][2];
@@ -258,6 +262,7 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
         const int buf = c & 1;
         const int64_t xn = ks + (int64_t)(c + 1) * kFwdKC;
         if (c + 1 < nch) fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, xn, ke, vec_ok(xn), stg);
+        if (!idle) {
         f4 a_r[2][2], a_i[2][2], b_r[2][2], b_i[2][2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -288,6 +293,7 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
                     p3[b][cb] = MM<float>::mma(xs, ys[cb], p3[b][cb]);
                 }
             }
+        }
         }
         if (c + 1 < nch) store(buf ^ 1);
         __syncthreads();
@@ -409,6 +415,8 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
     const int srow = tid >> 2, sch = tid & 3;
     const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
     const int so = f16_off(srow, sch);
+    // waves whose block is never read only stage (see k_forward_f32)
+    const bool idle = te == tr && (we > wr || (we == wr && P.dmin >= 32));
     f4 re[2][2], im[2][2];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -431,6 +439,7 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
         const int buf = c & 1;
         const int64_t xn = ks + (int64_t)(c + 1) * kF16KC;
         if (c + 1 < nch) f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, xn + 8 * sch, ke, vec_ok(xn), stg);
+        if (!idle) {
         V a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -451,6 +460,7 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
                 im[b][cb] = MM16<S>::mma(a_r[b], b_i[cb], im[b][cb]);
                 im[b][cb] = MM16<S>::mma(a_i[b], b_r[cb], im[b][cb]);
             }
+        }
         if (c + 1 < nch) store(buf ^ 1);
         __syncthreads();
     }
@@ -508,6 +518,7 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
     P.nsplit = nsplit;
     P.kchunk = kchunk;
     P.ntri = ntri;
+    P.dmin = 0;
     const double dA = g->h * g->h;
     for (int k = 0; k < nf; ++k) {
         const double om = 2.0 * M_PI * (freqs ? freqs[k] : 1.0);
@@ -542,12 +553,13 @@ size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
 
 rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
                        rb_dtype dt, const double *freqs, int nf, const double *delta, double *d_out, void *ws,
-                       size_t ws_bytes, hipStream_t st) {
+                       size_t ws_bytes, hipStream_t st, int dmin) {
     if (ws_bytes < forward_workspace_bytes(g, nf, dt)) {
         set_error("forward workspace too small: need %zu bytes", forward_workspace_bytes(g, nf, dt));
         return RB_ENOMEM;
     }
     FwdParams P = fwd_params(g, freqs, nf, dt);
+    P.dmin = dmin;
     Carver c(ws, ws_bytes);
     FwdWs w = carve_fwd(c, P, dt);
     const unsigned nblk = (unsigned)((int64_t)P.ntri * P.nsplit * nf);

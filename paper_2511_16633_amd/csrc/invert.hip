@@ -742,7 +742,7 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
         RB_LAUNCHED();
         // 5. exact step length along v
         RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.v, w.Jv, scratch, scratch_bytes,
-                            st));
+                            st, dmin));
         k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.D, w.part);
         RB_LAUNCHED();
         k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
@@ -755,7 +755,7 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
         RB_LAUNCHED();
         for (int it = 0; it < cg_iters; ++it) {
             RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.p, w.Jv, scratch, scratch_bytes,
-                                st));
+                                st, dmin));
             // second partial component: <J p, W J p>
             k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.Jv, w.part);
             RB_LAUNCHED();
