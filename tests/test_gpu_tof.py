@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workload as W
+from oracle import invert as invert_mod
 from oracle import tof
 
 torch = pytest.importorskip("torch")
@@ -98,3 +99,34 @@ def test_tof_in_place(rb):
     rb.tof_invert(p.geom, topts, p.inv, a, _t(T_meas), 1, b)
     rb.tof_invert(p.geom, topts, p.inv, a, _t(T_meas), 1, a)
     assert np.allclose(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_tof_no_measured_pairs_leaves_model(rb):
+    """Every ToF unmeasured: no used pair, empty support, zero step."""
+    p = W.small_ring(with_data=False)
+    c0 = np.full_like(p.c_true, p.geom.c_background)
+    topts = W.resolve_trace_opts(p.geom, c0, 360)
+    T_meas = np.full((p.geom.m, p.geom.m), np.nan)
+    _say("tof with no measured pair")
+    c_in = _t(c0.reshape(-1))
+    c_out = _t(np.zeros(p.geom.n_pixels))
+    rms, beta = rb.tof_invert(p.geom, topts, p.inv, c_in, _t(T_meas), 2, c_out)
+    assert rms == [0.0, 0.0] and beta == [0.0, 0.0]
+    assert np.array_equal(c_out.cpu().numpy(), c0.reshape(-1))
+
+
+def test_tof_refuses_nonpositive_slowness(rb):
+    """ToFs a tenth of the modelled ones ask for a negative slowness: the
+    oracle raises, the library returns RB_ENUMERIC and leaves c_out alone."""
+    p = W.small_ring(with_data=False)
+    c0 = np.full_like(p.c_true, p.geom.c_background)
+    topts = W.resolve_trace_opts(p.geom, c0, 360)
+    T_meas = 0.1 * W.straight_ray_tof(p.geom, c0)
+    with pytest.raises(invert_mod.NumericError):
+        tof.tof_step(p.geom, topts, p.inv, c0, T_meas)
+    _say("tof numeric refusal")
+    c_in = _t(c0.reshape(-1))
+    c_out = _t(np.full(p.geom.n_pixels, 7.0))
+    with pytest.raises(rb.NumericError):
+        rb.tof_invert(p.geom, topts, p.inv, c_in, _t(T_meas), 1, c_out)
+    assert np.all(c_out.cpu().numpy() == 7.0)
