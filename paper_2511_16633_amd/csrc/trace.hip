@@ -14,11 +14,14 @@
 //    corner is one load, served from L2/MALL (a 480x480 map is 3.7 MB);
 //  * wavefront nodes are stored [emitter][step][ray] so the lanes of a wave
 //    write consecutive addresses at every step;
-//  * first arrival without floating-point atomics: pass 1 takes an integer
-//    atomicMin on an order-preserving 64-bit image of T, pass 2 an atomicMin
-//    on the (step, ray, triangle) index among the triangles that attain it,
-//    pass 3 recomputes the winner's barycentrics per point.  The result is
-//    independent of scheduling.
+//  * first arrival without floating-point atomics: a classification pass
+//    lists the mesh cells whose bounding box holds a pixel centre or
+//    straddles the ring; the raster passes take one 64-bit atomicMin per
+//    candidate on the arrival key (fixed-point step index above the
+//    triangle index), and the write pass decodes each point's winner and
+//    recomputes its barycentrics.  The result is independent of scheduling;
+//  * the bent-ray ToF starting model reads each pair's linking path from the
+//    arrival key at the receiving element (end of this file).
 #include <climits>
 #include <cmath>
 #include <type_traits>
