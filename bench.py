@@ -223,7 +223,7 @@ def main():
     # ---- the linear subproblem of set 0 solved by CG instead of the single
     # step: whole set (trace, tables, CG) for 1 and for K iterations
     cg = None
-    if args.cg_iters > 0:
+    if args.cg_iters > 0 and not large:
         del fws
         cws = torch.empty(rb.invert_cg_workspace_bytes(g, topts, nf, args.dtype, batch), dtype=torch.uint8,
                           device=dev)
@@ -262,7 +262,8 @@ def main():
     # ---- the ToF starting model: bent-ray ToF inversion from water against
     # straight-chord ToFs of the true phantom (the stand-in for picked ToFs)
     tof = None
-    if args.tof_iters > 0:
+    # (the large instance's fans, all resident at once, would not fit)
+    if args.tof_iters > 0 and not large:
         T_meas = torch.as_tensor(W.straight_ray_tof(g, prob.c_true), device=dev)
         c_w = torch.full_like(c_start, g.c_background)
         c_t = torch.empty_like(c_start)

@@ -30,6 +30,32 @@ __device__ __forceinline__ void tri_tile(int t, int ntl, int &te, int &tr) {
     tr = a + t;
 }
 
+// Largest circular index distance min(|e - r|, m - |e - r|) over the pairs
+// e in [e0, e0 + ne), r in [r0, r0 + nr): the distance is piecewise linear
+// in r - e with its peaks at +-m/2, so the maximum is at an end of the
+// difference range or at a peak inside it.
+__device__ __forceinline__ int max_circ_dist(int m, int e0, int ne, int r0, int nr) {
+    const int lo = r0 - (e0 + ne - 1), hi = (r0 + nr - 1) - e0;
+    auto cd = [m](int d) {
+        d = d < 0 ? -d : d;
+        d %= m;
+        return d < m - d ? d : m - d;
+    };
+    int best = cd(lo) > cd(hi) ? cd(lo) : cd(hi);
+    const int h = m / 2;
+    if ((lo <= h && h <= hi) || (lo <= -h && -h <= hi)) best = h;
+    return best;
+}
+
+// A 32 x 32 (e, r) block of a tile whose value is never used: below the
+// diagonal of a diagonal tile (the reduction reads e <= r), or, with
+// dmin >= 32, every pair of the block closer than dmin (weighted by zero).
+__device__ __forceinline__ bool fwd_block_idle(const FwdParams &P, int te, int tr, int we, int wr) {
+    if (te == tr && we > wr) return true;
+    return P.dmin >= 32 &&
+           max_circ_dist(P.m, te * 64 + 32 * we, 32, tr * 64 + 32 * wr, 32) < P.dmin;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_forward(FwdParams P, const T *__restrict__ Gr, const T *__restrict__ Gi,
                                                  const double *__restrict__ delta, T *__restrict__ part) {
@@ -103,6 +129,12 @@ __global__ void k_forward_reduce(FwdParams P, const T *__restrict__ part, const 
     const int64_t rem = idx - (int64_t)k * mm;
     const int e = (int)(rem / P.m), r = (int)(rem - (int64_t)e * P.m);
     if (e > r) return;
+    if (P.dmin >= 32 && min(r - e, P.m - (r - e)) < P.dmin) {
+        // weighted by zero by the caller; its tile may not have been computed
+        const int64_t o1 = ((int64_t)k * P.m + e) * P.m + r, o2 = ((int64_t)k * P.m + r) * P.m + e;
+        d[2 * o1] = d[2 * o1 + 1] = d[2 * o2] = d[2 * o2 + 1] = 0.0;
+        return;
+    }
     const int64_t stride = (int64_t)P.nf * P.mp * P.mp * 2;   // one split
     const T *pp = part + (int64_t)k * P.mp * P.mp * 2 + ((int64_t)e * P.mp + r) * 2;
     double sr = 0.0, si = 0.0;
@@ -230,10 +262,10 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
     const int nch = (int)((ke - ks + kFwdKC - 1) / kFwdKC);
     const int srow = tid >> 2, c8 = (tid & 3) * 8;
     const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
-    // On a diagonal tile the block below the diagonal (e > r) is never
-    // read, and with dmin >= 32 neither are the two diagonal blocks: those
-    // waves only stage (wave-uniform).
-    const bool idle = te == tr && (we > wr || (we == wr && P.dmin >= 32));
+    // Waves whose block is never used only stage (wave-uniform); a tile
+    // with no used block returns at once (the reduction does not read it).
+    if (P.dmin >= 32 && max_circ_dist(P.m, te * 64, 64, tr * 64, 64) < P.dmin) return;
+    const bool idle = fwd_block_idle(P, te, tr, we, wr);
     // (a + ib)(c + id) with three real products: P1 = ac, P2 = bd,
     // P3 = (a + b)(c + d); re = P1 - P2, im = P3 - P1 - P2
     f4 p1[2][2], p2[2][2], p3[2][2];
@@ -415,8 +447,9 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
     const int srow = tid >> 2, sch = tid & 3;
     const int e_row = te * 64 + srow, r_row = tr * 64 + srow;
     const int so = f16_off(srow, sch);
-    // waves whose block is never read only stage (see k_forward_f32)
-    const bool idle = te == tr && (we > wr || (we == wr && P.dmin >= 32));
+    // waves whose block is never used only stage (see k_forward_f32)
+    if (P.dmin >= 32 && max_circ_dist(P.m, te * 64, 64, tr * 64, 64) < P.dmin) return;
+    const bool idle = fwd_block_idle(P, te, tr, we, wr);
     f4 re[2][2], im[2][2];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
