@@ -8,6 +8,7 @@
 // split partials are reduced in a fixed order.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "born.h"
 #include "common.h"
@@ -455,48 +456,74 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) re[b][c] = im[b][c] = f4{0, 0, 0, 0};
-    F16Stage stg;
     auto vec_ok = [&](int64_t xc) { return ((N & 7) == 0) && (xc + kF16KC <= ke); };
-    auto store = [&](int buf) {
-        *reinterpret_cast<u32x4 *>(sA[buf] + so) = stg.ar;
-        *reinterpret_cast<u32x4 *>(sA[buf] + kF16Arr + so) = stg.ai;
-        *reinterpret_cast<u32x4 *>(sB[buf] + so) = f16_scale<S, V>(stg.br, stg.d0, stg.d1);
-        *reinterpret_cast<u32x4 *>(sB[buf] + kF16Arr + so) = f16_scale<S, V>(stg.bi, stg.d0, stg.d1);
+    auto load = [&](int c, F16Stage &v) {
+        const int64_t xc = ks + (int64_t)c * kF16KC;
+        f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, xc + 8 * sch, ke, vec_ok(xc), v);
     };
-    if (nch > 0) {
-        f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, ks + 8 * sch, ke, vec_ok(ks), stg);
-        store(0);
-    }
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
+    auto store = [&](int buf, const F16Stage &v) {
+        *reinterpret_cast<u32x4 *>(sA[buf] + so) = v.ar;
+        *reinterpret_cast<u32x4 *>(sA[buf] + kF16Arr + so) = v.ai;
+        *reinterpret_cast<u32x4 *>(sB[buf] + so) = f16_scale<S, V>(v.br, v.d0, v.d1);
+        *reinterpret_cast<u32x4 *>(sB[buf] + kF16Arr + so) = f16_scale<S, V>(v.bi, v.d0, v.d1);
+    };
+    // Tiles are loaded two steps ahead into two register sets used in turn:
+    // step c computes on tile c (LDS), issues the loads of tile c + 2 and
+    // stores tile c + 1, loaded a step earlier, to the other buffer.  Each
+    // load then has two steps of MFMAs to arrive in.
+    // FUT: tile c + 2 exists and is whole (16-byte loads, no tests), so the
+    // steady state has unconditional loads and exact load-counter waits.
+    auto step = [&](int c, F16Stage &next, F16Stage &fut, auto fut_tag) {
         const int buf = c & 1;
-        const int64_t xn = ks + (int64_t)(c + 1) * kF16KC;
-        if (c + 1 < nch) f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, xn + 8 * sch, ke, vec_ok(xn), stg);
+        if (decltype(fut_tag)::value)
+            f16_stage_load(gr, gi, df, P.m, N, e_row, r_row, ks + (int64_t)(c + 2) * kF16KC + 8 * sch, ke, true,
+                           fut);
+        else if (c + 2 < nch)
+            load(c + 2, fut);
         if (!idle) {
-        V a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+            V a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int ra = 32 * we + 16 * b + row, rb = 32 * wr + 16 * b + row;
-            a_r[b] = *reinterpret_cast<const V *>(sA[buf] + f16_off(ra, kk));
-            a_i[b] = *reinterpret_cast<const V *>(sA[buf] + kF16Arr + f16_off(ra, kk));
-            a_n[b] = neg(a_i[b]);
-            b_r[b] = *reinterpret_cast<const V *>(sB[buf] + f16_off(rb, kk));
-            b_i[b] = *reinterpret_cast<const V *>(sB[buf] + kF16Arr + f16_off(rb, kk));
-        }
-        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                re[b][cb] = MM16<S>::mma(a_r[b], b_r[cb], re[b][cb]);
-                re[b][cb] = MM16<S>::mma(a_n[b], b_i[cb], re[b][cb]);
-                im[b][cb] = MM16<S>::mma(a_r[b], b_i[cb], im[b][cb]);
-                im[b][cb] = MM16<S>::mma(a_i[b], b_r[cb], im[b][cb]);
+            for (int b = 0; b < 2; ++b) {
+                const int ra = 32 * we + 16 * b + row, rb = 32 * wr + 16 * b + row;
+                a_r[b] = *reinterpret_cast<const V *>(sA[buf] + f16_off(ra, kk));
+                a_i[b] = *reinterpret_cast<const V *>(sA[buf] + kF16Arr + f16_off(ra, kk));
+                a_n[b] = neg(a_i[b]);
+                b_r[b] = *reinterpret_cast<const V *>(sB[buf] + f16_off(rb, kk));
+                b_i[b] = *reinterpret_cast<const V *>(sB[buf] + kF16Arr + f16_off(rb, kk));
             }
+            // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    re[b][cb] = MM16<S>::mma(a_r[b], b_r[cb], re[b][cb]);
+                    re[b][cb] = MM16<S>::mma(a_n[b], b_i[cb], re[b][cb]);
+                    im[b][cb] = MM16<S>::mma(a_r[b], b_i[cb], im[b][cb]);
+                    im[b][cb] = MM16<S>::mma(a_i[b], b_r[cb], im[b][cb]);
+                }
         }
-        if (c + 1 < nch) store(buf ^ 1);
+        if (c + 1 < nch) store(buf ^ 1, next);
         __syncthreads();
+    };
+    F16Stage s0, s1;
+    if (nch > 0) {
+        load(0, s0);
+        store(0, s0);
     }
+    if (nch > 1) load(1, s1);
+    __syncthreads();
+    int c = 0;
+    // tiles 0 .. nch - 2 are whole; the last may be partial
+    const int nwhole = ((N & 7) == 0) ? nch - 1 : 0;
+    for (; c + 4 <= nwhole; c += 2) {
+        step(c, s1, s0, std::true_type());       // tile c + 1 in s1, tile c + 2 into s0
+        step(c + 1, s0, s1, std::true_type());   // tile c + 2 in s0, tile c + 3 into s1
+    }
+    for (; c + 1 < nch; c += 2) {
+        step(c, s1, s0, std::false_type());
+        step(c + 1, s0, s1, std::false_type());
+    }
+    if (c < nch) step(c, s1, s0, std::false_type());
     float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
