@@ -190,8 +190,13 @@ __device__ __forceinline__ void fwd_block(const FwdParams &P, int &te, int &tr, 
 // buffered; a lane reads its eight k values of a row as two b128 reads.
 constexpr int kFwdKC = 32, kFwdLD = 36;
 
+// One thread's staging registers: eight pixels of one row of G_e and of
+// G_r, and delta at those pixels.  G_r delta is formed when the tile is
+// stored, not when it is loaded, so the loads stay in flight during the
+// MFMAs of the current tile.
 struct FwdStage {
     f4 ar[2], ai[2], br[2], bi[2];
+    double dl[8];
 };
 
 __device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, const float *__restrict__ gi,
@@ -200,9 +205,8 @@ __device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, con
     const int c8 = (threadIdx.x & 3) * 8;
     const int64_t xs = xc + c8;
     if (vec) {
-        double dl[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) dl[q] = delta[xs + q];
+        for (int q = 0; q < 8; ++q) v.dl[q] = delta[xs + q];
         if (e_row < m) {
             const float *pr = gr + (int64_t)e_row * N + xs;
             const float *pi = gi + (int64_t)e_row * N + xs;
@@ -216,15 +220,10 @@ __device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, con
         if (r_row < m) {
             const float *pr = gr + (int64_t)r_row * N + xs;
             const float *pi = gi + (int64_t)r_row * N + xs;
-            f4 t0 = *reinterpret_cast<const f4 *>(pr), t1 = *reinterpret_cast<const f4 *>(pr + 4);
-            f4 u0 = *reinterpret_cast<const f4 *>(pi), u1 = *reinterpret_cast<const f4 *>(pi + 4);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                v.br[0][q] = t0[q] * (float)dl[q];
-                v.br[1][q] = t1[q] * (float)dl[q + 4];
-                v.bi[0][q] = u0[q] * (float)dl[q];
-                v.bi[1][q] = u1[q] * (float)dl[q + 4];
-            }
+            v.br[0] = *reinterpret_cast<const f4 *>(pr);
+            v.br[1] = *reinterpret_cast<const f4 *>(pr + 4);
+            v.bi[0] = *reinterpret_cast<const f4 *>(pi);
+            v.bi[1] = *reinterpret_cast<const f4 *>(pi + 4);
         } else {
             v.br[0] = v.br[1] = v.bi[0] = v.bi[1] = f4{0, 0, 0, 0};
         }
@@ -233,12 +232,12 @@ __device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, con
         for (int q = 0; q < 8; ++q) {
             const int64_t x = xs + q;
             const bool okx = x < ke;
-            const float dl = okx ? (float)delta[x] : 0.0f;
+            v.dl[q] = okx ? delta[x] : 0.0;
             const bool oka = okx && e_row < m, okb = okx && r_row < m;
             v.ar[q >> 2][q & 3] = oka ? gr[(int64_t)e_row * N + x] : 0.0f;
             v.ai[q >> 2][q & 3] = oka ? gi[(int64_t)e_row * N + x] : 0.0f;
-            v.br[q >> 2][q & 3] = okb ? gr[(int64_t)r_row * N + x] * dl : 0.0f;
-            v.bi[q >> 2][q & 3] = okb ? gi[(int64_t)r_row * N + x] * dl : 0.0f;
+            v.br[q >> 2][q & 3] = okb ? gr[(int64_t)r_row * N + x] : 0.0f;
+            v.bi[q >> 2][q & 3] = okb ? gi[(int64_t)r_row * N + x] : 0.0f;
         }
     }
 }
@@ -281,10 +280,18 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
         *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8 + 4]) = stg.ar[1];
         *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8]) = stg.ai[0];
         *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8 + 4]) = stg.ai[1];
-        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8]) = stg.br[0];
-        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8 + 4]) = stg.br[1];
-        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8]) = stg.bi[0];
-        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8 + 4]) = stg.bi[1];
+        f4 br0, br1, bi0, bi1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            br0[q] = stg.br[0][q] * (float)stg.dl[q];
+            br1[q] = stg.br[1][q] * (float)stg.dl[q + 4];
+            bi0[q] = stg.bi[0][q] * (float)stg.dl[q];
+            bi1[q] = stg.bi[1][q] * (float)stg.dl[q + 4];
+        }
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8]) = br0;
+        *reinterpret_cast<f4 *>(&sBm[buf][0][srow][c8 + 4]) = br1;
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8]) = bi0;
+        *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8 + 4]) = bi1;
     };
     if (nch > 0) {
         fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, ks, ke, vec_ok(ks), stg);
