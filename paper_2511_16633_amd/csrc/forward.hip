@@ -273,9 +273,8 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = f4{0, 0, 0, 0};
-    FwdStage stg;
     auto vec_ok = [&](int64_t xc) { return ((N & 3) == 0) && (xc + kFwdKC <= ke); };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const FwdStage &stg) {
         *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8]) = stg.ar[0];
         *reinterpret_cast<f4 *>(&sA[buf][0][srow][c8 + 4]) = stg.ar[1];
         *reinterpret_cast<f4 *>(&sA[buf][1][srow][c8]) = stg.ai[0];
@@ -293,15 +292,18 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
         *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8]) = bi0;
         *reinterpret_cast<f4 *>(&sBm[buf][1][srow][c8 + 4]) = bi1;
     };
-    if (nch > 0) {
-        fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, ks, ke, vec_ok(ks), stg);
-        store(0);
-    }
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
+    auto load = [&](int c, FwdStage &v) {
+        const int64_t xc = ks + (int64_t)c * kFwdKC;
+        fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, xc, ke, vec_ok(xc), v);
+    };
+    // Tiles are loaded two steps ahead into two register sets used in turn
+    // (as in the 16-bit kernel); FUT: tile c + 2 exists and is whole.
+    auto step = [&](int c, FwdStage &next, FwdStage &fut, auto fut_tag) {
         const int buf = c & 1;
-        const int64_t xn = ks + (int64_t)(c + 1) * kFwdKC;
-        if (c + 1 < nch) fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, xn, ke, vec_ok(xn), stg);
+        if (decltype(fut_tag)::value)
+            fwd_stage_load(gr, gi, delta, P.m, N, e_row, r_row, ks + (int64_t)(c + 2) * kFwdKC, ke, true, fut);
+        else if (c + 2 < nch)
+            load(c + 2, fut);
         if (!idle) {
         f4 a_r[2][2], a_i[2][2], b_r[2][2], b_i[2][2];
 #pragma unroll
@@ -335,9 +337,27 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
             }
         }
         }
-        if (c + 1 < nch) store(buf ^ 1);
+        if (c + 1 < nch) store(buf ^ 1, next);
         __syncthreads();
+    };
+    FwdStage s0, s1;
+    if (nch > 0) {
+        load(0, s0);
+        store(0, s0);
     }
+    if (nch > 1) load(1, s1);
+    __syncthreads();
+    int c = 0;
+    const int nwhole = ((N & 3) == 0) ? nch - 1 : 0;   // tiles 0 .. nch - 2 are whole
+    for (; c + 4 <= nwhole; c += 2) {
+        step(c, s1, s0, std::true_type());
+        step(c + 1, s0, s1, std::true_type());
+    }
+    for (; c + 1 < nch; c += 2) {
+        step(c, s1, s0, std::false_type());
+        step(c + 1, s0, s1, std::false_type());
+    }
+    if (c < nch) step(c, s1, s0, std::false_type());
     float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
