@@ -33,22 +33,22 @@ struct HbParams {
     double ch[RB_MAX_NF];   // omega^4 h^4
 };
 
-// A block holds PB pixels; its 256 threads form 256 / PB groups per pixel.
+// A block holds PB pixels; its NT threads form NT / PB groups per pixel.
 // g for the block's pixels is staged in LDS as [r][PB] values of type L,
 // and every sum is taken in L: FP64 for FP64 tables, else FP32 (the
 // precision of the matrix-core path).  Group q loads receivers
 // r = q (mod groups) and takes emitters [m q / groups, m (q + 1) / groups);
 // partial sums are combined in group order, so the result is deterministic.
-template <typename T, typename L, int PB>
-__global__ void __launch_bounds__(kHbThreads) k_hess_band(HbParams P, const T *__restrict__ Gr,
+template <typename T, typename L, int PB, int NT = kHbThreads>
+__global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restrict__ Gr,
                                                           const T *__restrict__ Gi, const float *__restrict__ gscale,
                                                           const int2 *__restrict__ zeroed,
                                                           const int *__restrict__ nzero, double *__restrict__ hd) {
-    constexpr int NG = kHbThreads / PB;
+    constexpr int NG = NT / PB;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     L *sg = reinterpret_cast<L *>(lds_raw);   // [m][PB]
-    __shared__ L spart[kHbThreads];
-    __shared__ int2 sz[kHbThreads];           // a chunk of the zeroed-pair list
+    __shared__ L spart[NT];
+    __shared__ int2 sz[NT];                   // a chunk of the zeroed-pair list
     const int m = P.m;
     const int t = threadIdx.x;
     const int px = t % PB, grp = t / PB;
@@ -116,11 +116,11 @@ __global__ void __launch_bounds__(kHbThreads) k_hess_band(HbParams P, const T *_
         }
         // zeroed pairs, staged through LDS a chunk at a time
         const int nz = nzero ? min(nzero[k], P.zcap) : 0;   // block-uniform
-        for (int c0 = 0; c0 < nz; c0 += kHbThreads) {
+        for (int c0 = 0; c0 < nz; c0 += NT) {
             __syncthreads();   // the previous chunk has been read
             if (c0 + t < nz) sz[t] = zeroed[(int64_t)k * P.zcap + c0 + t];
             __syncthreads();
-            const int cn = min(kHbThreads, nz - c0);
+            const int cn = min(NT, nz - c0);
             for (int i0 = grp; i0 < cn; i0 += 8 * NG) {
                 L pr[8];
 #pragma unroll
@@ -164,11 +164,15 @@ rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *
     P.N = (int64_t)g->nx * g->ny;
     P.dmin = dmin;
     P.zcap = zcap;
-    // pixels per block: [m][pb] values within 32 KiB (m <= 4096)
+    // pixels per block: [m][pb] values within 32 KiB (m <= 4096).  For
+    // 256 < m <= 1024 and 32/16-bit tables a block of 1024 threads keeps 32
+    // pixels (up to 128 KiB of LDS): reads of a table row then span 64 or
+    // 128 bytes instead of 16 or 32.
     const bool f64 = dt == RB_F64;
-    const int pb = f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2));
+    const bool wide = !f64 && P.m > 256 && P.m <= 1024;
+    const int pb = wide ? 32 : (f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2)));
     const size_t lds = (size_t)P.m * pb * (f64 ? sizeof(double) : sizeof(float));
-    if (lds > kHbLds) {
+    if (lds > (wide ? (size_t)131072 : kHbLds)) {
         set_error("m = %d is too large for the banded Hessian", P.m);
         return RB_EUNSUPPORTED;
     }
@@ -186,6 +190,13 @@ rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *
         using T = decltype(tag);
         using L = decltype(ltag);
         const T *gr = static_cast<const T *>(G_re), *gi = static_cast<const T *>(G_im);
+        if (wide) {
+            auto kfn = k_hess_band<T, L, 32, 1024>;
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kfn),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            kfn<<<nb, 1024, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag);
+            return;
+        }
         switch (pb) {
             case 32: k_hess_band<T, L, 32><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
             case 16: k_hess_band<T, L, 16><<<nb, kHbThreads, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag); break;
