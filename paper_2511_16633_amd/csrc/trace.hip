@@ -52,24 +52,22 @@ struct TP {
 };
 
 // Bilinear slowness s with its exact patch gradient, and bilinear alpha0.
-// `sa` is the (s, alpha0) grid padded with one ring of water cells, row
-// stride nx + 2, so every cell that touches the grid has its four corners in
-// memory and needs no per-corner test; cells farther out are pure water.
+// `sa` is the (s, alpha0) grid padded with two rings of water cells, row
+// stride nx + 4.  Every cell that touches the grid has its four corners in
+// memory, and a point farther out is evaluated in a clamped cell of the
+// outer ring, whose four corners are all water: the value is exactly s_bg
+// with zero gradient and no absorption, with no test or branch.
 __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &P, double x, double y,
                                       double &s, double &gx, double &gy, double &a) {
 #pragma clang fp contract(fast)
     double u = (x - P.x0) * P.inv_h;
     double v = (y - P.y0) * P.inv_h;
     double fi = floor(u), fj = floor(v);
-    // cells with i <= -2, i >= nx, j <= -2 or j >= ny have all four corners
-    // outside the grid: pure water (value s_bg, zero gradient, no absorption)
-    if (!(fi >= -1.0 && fi <= (double)(P.nx - 1) && fj >= -1.0 && fj <= (double)(P.ny - 1))) {
-        s = P.s_bg; gx = 0.0; gy = 0.0; a = 0.0;
-        return;
-    }
-    const int i = (int)fi + 1, j = (int)fj + 1;   // padded indices, 0 .. n; corners up to n + 1
+    // cells -2 .. n (padded 0 .. n + 2, corners up to n + 3)
+    const int i = (int)fmin(fmax(fi, -2.0), (double)P.nx) + 2;
+    const int j = (int)fmin(fmax(fj, -2.0), (double)P.ny) + 2;
     double fu = u - fi, fv = v - fj;
-    const int ld = P.nx + 2;
+    const int ld = P.nx + 4;
     const double2 *q = sa + (j * ld + i);
     const double2 c00 = q[0], c10 = q[1], c01 = q[ld], c11 = q[ld + 1];
     double dx0 = c10.x - c00.x, dx1 = c11.x - c01.x;
@@ -108,11 +106,11 @@ __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P,
 
 __global__ void k_pack(int nx, int ny, double s_bg, const double *__restrict__ s, const double *__restrict__ alpha,
                        double2 *__restrict__ sa) {
-    const int64_t np = (int64_t)(nx + 2) * (ny + 2);
+    const int64_t np = (int64_t)(nx + 4) * (ny + 4);
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= np) return;
-    const int jp = (int)(q / (nx + 2)), ip = (int)(q - (int64_t)jp * (nx + 2));
-    const int i = ip - 1, j = jp - 1;
+    const int jp = (int)(q / (nx + 4)), ip = (int)(q - (int64_t)jp * (nx + 4));
+    const int i = ip - 2, j = jp - 2;
     if (i < 0 || j < 0 || i >= nx || j >= ny) {
         sa[q] = make_double2(s_bg, 0.0);
     } else {
@@ -617,7 +615,7 @@ TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int
     TraceWs w;
     const size_t N = (size_t)g->nx * g->ny;
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays * batch;
-    w.sa = c.take<double2>((size_t)(g->nx + 2) * (g->ny + 2));
+    w.sa = c.take<double2>((size_t)(g->nx + 4) * (g->ny + 4));
     w.rxy = c.take<double2>((size_t)g->m);
     w.XY = c.take<double2>(nodes);
     w.AB = c.take<double2>(nodes);
@@ -696,7 +694,7 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
     Carver c(base, ws_bytes - (size_t)(base - (char *)ws));
     TraceWs w = carve_trace(c, g, t, batch);
     TP P = make_tp(g, t);
-    const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
+    const int64_t npad = (int64_t)(g->nx + 4) * (g->ny + 4);
     k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, 1.0 / g->c_background, slowness, alpha0, w.sa);
     RB_LAUNCHED();
     k_rx_pos<<<blocks_for(g->m, 256), 256, 0, st>>>(P, w.rxy);
@@ -1152,7 +1150,7 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
     RB_HIP(hipMemcpyAsync(w.c, c_in, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     k_rx_pos<<<blocks_for(m, 256), 256, 0, st>>>(P, w.tw.rxy);
     RB_LAUNCHED();
-    const int64_t npad = (int64_t)(g->nx + 2) * (g->ny + 2);
+    const int64_t npad = (int64_t)(g->nx + 4) * (g->ny + 4);
     const int waves = (P.nr + kOwn - 1) / kOwn;
     const int cap = cell_seg_cap(t);
     const int nseg = (int)cell_segments(g, t, m);
