@@ -165,27 +165,32 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
         if (own && alive) {
             const bool lo = j > 0 && al;
             const bool hi = j + 1 < P.nr && ar;
-            double Jv = 0.0, dx, dy;
+            // chord between the neighbours at equal travel time (FP64
+            // differences); J and a = sqrt(c / (8 pi J)) in FP32, the
+            // precision the amplitude tables are stored in
+            double dx = 0.0, dy = 0.0;
+            float chord = 0.0f;
             if (lo && hi) {
                 dx = xr - xl;
                 dy = yr - yl;
-                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_full;
+                chord = (float)P.inv_chord_full;
             } else if (hi) {
                 dx = xr - st[0];
                 dy = yr - st[1];
-                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_half;
+                chord = (float)P.inv_chord_half;
             } else if (lo) {
                 dx = st[0] - xl;
                 dy = st[1] - yl;
-                Jv = sqrt(dx * dx + dy * dy) * P.inv_chord_half;
+                chord = (float)P.inv_chord_half;
             }
-            if (Jv < P.j_min) Jv = P.j_min;
+            float Jv = sqrtf((float)(dx * dx + dy * dy)) * chord;
+            if (Jv < (float)P.j_min) Jv = (float)P.j_min;
+            const float amp = 1.0f / sqrtf((float)s0 * ((float)eight_pi * Jv));
             const size_t k = base + (size_t)n * P.nr;
             // nodes are written once and read by later passes: keep them
             // from displacing the field grid in L2
             __builtin_nontemporal_store(nd2{st[0], st[1]}, reinterpret_cast<nd2 *>(&XY[k]));
-            __builtin_nontemporal_store(nd2{sqrt(recip(s0 * (eight_pi * Jv))), st[4]},
-                                        reinterpret_cast<nd2 *>(&AB[k]));
+            __builtin_nontemporal_store(nd2{(double)amp, st[4]}, reinterpret_cast<nd2 *>(&AB[k]));
         }
         if (alive && (last || n == P.nmax)) {
             if (own) L[(size_t)eb * P.nr + j] = n;
