@@ -24,7 +24,9 @@ its Results section.  Readings taken where the paper is silent:
   c unchanged elsewhere; a non-positive q is an error;
 * reported update norm: sqrt(sum_x (c_new - c)^2) in m/s;
 * CG (the paper's earlier, iterative solution of the linearised equation):
-  see invert_frequency_set_cg for its readings.
+  see invert_frequency_set_cg for its readings;
+* asymptotic (amplitude-normalised) weights: see
+  invert_frequency_set_asymptotic (parity with the cited weights unpinned).
 """
 from __future__ import annotations
 
@@ -215,6 +217,59 @@ def invert_frequency_set_cg(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_m
     if return_parts:
         parts = dict(L)
         parts.update({"c_new": c_new, "dc_l2": dc_l2, "delta": x, "alpha": alphas, "rz": rzs})
+        return parts
+    return c_new, dc_l2
+
+
+def invert_frequency_set_asymptotic(geom, topts, iopts, c: np.ndarray, alpha, freqs, p_meas,
+                                    return_parts: bool = False):
+    """The frequency set with asymptotic (amplitude-normalised) weights in
+    place of the Hessian-diagonal weight (the single-step paragraph's
+    weighting that diagonalises the Hessian, in its ray-Born asymptotic form).
+
+    Readings: each selected pair (e, r) on its own determines a pixel's
+    perturbation exactly, D_er / (omega^2 dA G_e(x) G_r(x)), when the data
+    are the Born data of that pixel alone; the direction is the W-weighted
+    mean of these per-pair estimates over the pairs and frequencies whose
+    Green's functions are nonzero at x,
+        g_A(x) = sum_k Re sum_{e,r} W_er D_er / (omega_k^2 dA G_e(x) G_r(x)),
+        n_A(x) = sum_k sum_{e,r} W_er [G_e(x) != 0] [G_r(x) != 0],
+        v(x)   = g_A(x) / n_A(x) on the support S where n_A > 0, else 0;
+    no obliquity factor.  The step length beta is the exact minimiser of the
+    linearised objective along v and the update is that of the single step.
+    (The cited reference's exact weights are not in the paper.)"""
+    L = linearise(geom, topts, iopts, c, alpha, freqs, p_meas)
+    N = geom.n_pixels
+    gA = np.zeros(N)
+    nA = np.zeros(N)
+    for k, f in enumerate(freqs):
+        G = L["G"][k]
+        om2dA = (2.0 * math.pi * f) ** 2 * L["dA"]
+        nz = G != 0
+        Ginv = np.zeros_like(G)
+        Ginv[nz] = 1.0 / G[nz]
+        Y = (L["W"][k] * L["D"][k]) @ Ginv            # sum over r
+        gA += np.real(np.sum(Ginv * Y, axis=0)) / om2dA
+        ind = nz.astype(np.float64)
+        nA += np.sum(ind * (L["W"][k] @ ind), axis=0)
+    ok = L["support"] & (nA > 0.0)
+    v = np.zeros(N)
+    v[ok] = gA[ok] / nA[ok]
+    num = 0.0
+    dsq = 0.0
+    us = []
+    for k, f in enumerate(freqs):
+        u = born.born_forward(L["G"][k], v, f, L["dA"])
+        us.append(u)
+        num += float(np.sum(L["W"][k] * np.real(np.conj(u) * L["D"][k])))
+        dsq += float(np.sum(L["W"][k] * (u.real * u.real + u.imag * u.imag)))
+    beta = num / dsq if dsq > 0.0 else 0.0
+    delta = beta * v
+    c_new, dc_l2 = apply_update(L["c"], L["s"], delta)
+    if return_parts:
+        parts = dict(L)
+        parts.update({"c_new": c_new, "dc_l2": dc_l2, "direction": v, "beta": beta, "delta": delta,
+                      "g_A": gA, "n_A": nA, "Jv": us})
         return parts
     return c_new, dc_l2
 

@@ -251,3 +251,47 @@ def test_cg_zero_residual_stops_with_zero_steps():
                                         return_parts=True)
     assert np.all(cg["alpha"] == 0.0) and cg["rz"][0] == 0.0
     assert cg["dc_l2"] == 0.0 and np.array_equal(cg["c_new"], c)
+
+
+def test_asymptotic_direction_recovers_a_point_scatterer_at_its_pixel():
+    """Born data of one pixel's perturbation a, no outliers: every selected
+    pair's normalised estimate at that pixel is exactly a, so the direction
+    there is a (before the step length)."""
+    g, c, al, to = _tiny_problem()
+    freqs = np.array([250e3, 320e3])
+    Gs, ps = _model_data(g, to, c, al, freqs)
+    ic = (g.ny // 2) * g.nx + g.nx // 2 + 3
+    a = 4e-9
+    e_c = np.zeros(g.n_pixels)
+    e_c[ic] = a
+    p_meas = np.stack([ps[k] + born.born_forward(Gs[k], e_c, f, g.h ** 2) for k, f in enumerate(freqs)])
+    parts = invert.invert_frequency_set_asymptotic(g, to, W.InvertOpts(outlier_fraction=0.0), c, al, freqs,
+                                                   p_meas, return_parts=True)
+    assert parts["support"][ic]
+    assert abs(parts["direction"][ic] - a) <= 1e-10 * a
+    assert parts["beta"] > 0
+
+
+def test_asymptotic_direction_matches_brute_force_loops():
+    """g_A and n_A by explicit loops over pairs on a tiny problem."""
+    g = W.centred_grid(9, 0.5e-3, 8, 4e-3, 1500.0)
+    c = np.full((g.ny, g.nx), 1500.0)
+    c[4, 4] = 1510.0
+    to = W.resolve_trace_opts(g, c, 60)
+    freqs = np.array([300e3])
+    rng = np.random.default_rng(4)
+    p_meas = (rng.standard_normal((1, g.m, g.m)) + 1j * rng.standard_normal((1, g.m, g.m))) * 1e-3
+    parts = invert.invert_frequency_set_asymptotic(g, to, W.InvertOpts(outlier_fraction=0.0), c, None, freqs,
+                                                   p_meas, return_parts=True)
+    G = parts["G"][0]
+    Wk, Dk = parts["W"][0], parts["D"][0]
+    om2dA = (2 * math.pi * freqs[0]) ** 2 * g.h ** 2
+    for x in range(g.n_pixels):
+        gs, ns = 0.0, 0.0
+        for e in range(g.m):
+            for r in range(g.m):
+                if Wk[e, r] != 0 and G[e, x] != 0 and G[r, x] != 0:
+                    gs += (Wk[e, r] * Dk[e, r] / (om2dA * G[e, x] * G[r, x])).real
+                    ns += Wk[e, r]
+        assert abs(parts["g_A"][x] - gs) <= 1e-9 * max(1e-30, abs(gs)) + 1e-300
+        assert parts["n_A"][x] == ns
