@@ -256,7 +256,22 @@ def main():
               "rz_first_last": [rzs[0], rzs[-1]]}
         print(f"[bench] CG set 0: {args.cg_iters} iterations {t_k:.2f} ms, 1 iteration {t_1:.2f} ms, "
               f"single step {t_one:.2f} ms", file=sys.stderr, flush=True)
-        del cws, ccg
+        del cws
+        # the same set with the asymptotic (amplitude-normalised) weights
+        if args.dtype in ("f32", "f64"):
+            aws = torch.empty(rb.invert_asymptotic_workspace_bytes(g, topts, nf, args.dtype, batch),
+                              dtype=torch.uint8, device=dev)
+
+            def asym_set():
+                ccg.copy_(c_start)
+                return rb.invert_frequency_set_asymptotic(g, topts, prob.inv, args.dtype, ccg, alpha, fs, pms[0],
+                                                          ccg, ws=aws, stream=stream)
+
+            t_as = timed(asym_set)
+            cg["asymptotic_weights_ms_per_set"] = round(t_as, 3)
+            print(f"[bench] asymptotic weights set 0: {t_as:.2f} ms", file=sys.stderr, flush=True)
+            del aws
+        del ccg
         fws = None
 
     # ---- the ToF starting model: bent-ray ToF inversion from water against

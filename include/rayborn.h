@@ -8,7 +8,8 @@
  * Born forward and weighted adjoint contractions and the diagonally weighted
  * single step (Inverse Problem section, Eqs. 8-10 and the single-step
  * paragraph), the conjugate-gradient solution of the same linear
- * subproblem that the single step replaces, and the bent-ray time-of-flight
+ * subproblem that the single step replaces, the single step with asymptotic
+ * (amplitude-normalised) weights, and the bent-ray time-of-flight
  * inversion that provides the starting model.
  *
  * Conventions shared by every entry point:
@@ -257,6 +258,32 @@ rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *
                                      const double *p_meas, int32_t n_iter, double *c_out,
                                      double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes,
                                      void *stream);
+
+/*
+ * The frequency set with asymptotic (amplitude-normalised) weights in place
+ * of the Hessian-diagonal weight (single-step paragraph: weights that
+ * diagonalise the Hessian, here in their ray-Born asymptotic form; the
+ * cited reference's exact weights are not in the paper).  Steps 1-3 and 6-7
+ * are those of rb_invert_frequency_set; the direction is the W-weighted mean
+ * of the per-pair single-pixel estimates D_er / (omega^2 h^2 G_e(x) G_r(x)):
+ *     g_A(x) = sum_k Re sum_{e,r} W_er D_er / (omega_k^2 h^2 G_e(x) G_r(x)),
+ *     n_A(x) = sum_k sum_{e,r} W_er [G_e(x) != 0] [G_r(x) != 0],
+ *     v(x)   = g_A(x) / n_A(x) on the support S where n_A > 0, 0 elsewhere,
+ * then beta = Re<J v, W D> / <J v, W J v> and the update as there.  For
+ * Born data of a single pixel's perturbation, v at that pixel is the
+ * perturbation itself.  Costs one backprojection and one banded pair count
+ * per frequency on the tables H = G / |G|^2 and [G != 0].  dtype must be
+ * RB_F64 or RB_F32 (RB_EUNSUPPORTED otherwise: 1 / G is unbounded).
+ * ws: rb_invert_asymptotic_workspace_bytes().  Other arguments, outputs and
+ * errors as for rb_invert_frequency_set.
+ */
+size_t rb_invert_asymptotic_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t,
+                                            int32_t nf, rb_dtype dtype, int32_t emitter_batch);
+rb_status rb_invert_frequency_set_asymptotic(const rb_geometry *g, const rb_trace_opts *t,
+                                             const rb_invert_opts *o, const double *c_in,
+                                             const double *alpha0, const double *freqs_hz,
+                                             int32_t nf, const double *p_meas, double *c_out,
+                                             double *dc_l2, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Starting model by bent-ray time-of-flight (ToF) inversion (Results

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     adjoint_workspace_bytes,
     invert_workspace_bytes,
     invert_cg_workspace_bytes,
+    invert_asymptotic_workspace_bytes,
     tof_workspace_bytes,
     trace_rays,
     build_green,
@@ -29,6 +30,7 @@ from ._binding import (  # noqa: F401
     born_hessian_banded,
     invert_frequency_set,
     invert_frequency_set_cg,
+    invert_frequency_set_asymptotic,
     tof_invert,
     version,
 )

@@ -91,6 +91,11 @@ def lib():
         "rb_tof_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts)]),
         "rb_tof_invert": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp, _vp, _i32, _vp,
                                          _P(_d), _vp, _sz, _vp]),
+        "rb_invert_asymptotic_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int,
+                                                      _i32]),
+        "rb_invert_frequency_set_asymptotic": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts),
+                                                              _vp, _vp, _P(_d), _i32, _vp, _vp, _P(_d), _vp, _sz,
+                                                              _vp]),
         "rb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "rb_last_error": (ctypes.c_char_p, []),
         "rb_version": (ctypes.c_char_p, []),
@@ -302,3 +307,25 @@ def tof_invert(g, t, o, c_in: torch.Tensor, T_meas: torch.Tensor, n_iter: int, c
                                _ptr(c_out), hist, _ptr(ws), ws.numel(), _stream(stream)))
     h = list(hist)
     return h[0::2][:n_iter], h[1::2][:n_iter]
+
+
+def invert_asymptotic_workspace_bytes(g, t, nf: int, dtype, emitter_batch: int = 0) -> int:
+    return int(lib().rb_invert_asymptotic_workspace_bytes(ctypes.byref(geometry_struct(g)),
+                                                          ctypes.byref(trace_opts_struct(t)), nf, _dt(dtype),
+                                                          emitter_batch))
+
+
+def invert_frequency_set_asymptotic(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[torch.Tensor], freqs,
+                                    p_meas: torch.Tensor, c_out: torch.Tensor, ws: Optional[torch.Tensor] = None,
+                                    stream=None) -> float:
+    """The set with asymptotic weights.  Returns the update norm; synchronises the stream."""
+    fa, nf = _freqs(freqs)
+    if ws is None:
+        ws = _ws(max(invert_asymptotic_workspace_bytes(g, t, nf, dtype), 256), c_in.device)
+    out = ctypes.c_double(0.0)
+    _check(lib().rb_invert_frequency_set_asymptotic(ctypes.byref(geometry_struct(g)),
+                                                    ctypes.byref(trace_opts_struct(t)),
+                                                    ctypes.byref(invert_opts_struct(o, dtype)), _ptr(c_in),
+                                                    _ptr(alpha0), fa, nf, _ptr(p_meas), _ptr(c_out),
+                                                    ctypes.byref(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out.value

@@ -598,6 +598,38 @@ __global__ void k_cg_last(int64_t n, const double *__restrict__ cg, const double
     if (i == 0) res[2] = 1.0;
 }
 
+// ------------------------------------------------------ asymptotic weights
+// Tables for the amplitude-normalised backprojection: H = G / |G|^2 (so
+// conj(H_e H_r) = 1 / (G_e G_r)) and the coverage indicator C = [G != 0].
+template <typename T>
+__global__ void k_asym_tables(int64_t n, const T *__restrict__ Gr, const T *__restrict__ Gi, T *__restrict__ Hr,
+                              T *__restrict__ Hi, T *__restrict__ C) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T a = Gr[i], b = Gi[i];
+    const T h = a * a + b * b;
+    const bool nz = a != T(0) || b != T(0);
+    Hr[i] = nz ? a / h : T(0);
+    Hi[i] = nz ? b / h : T(0);
+    C[i] = nz ? T(1) : T(0);
+}
+
+// gA += sg gk, nA += sn nk
+__global__ void k_asym_accum(int64_t n, const double *__restrict__ gk, const double *__restrict__ nk, double sg,
+                             double sn, double *__restrict__ gA, double *__restrict__ nA) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    gA[i] += sg * gk[i];
+    nA[i] += sn * nk[i];
+}
+
+__global__ void k_asym_direction(int64_t n, const double *__restrict__ gA, const double *__restrict__ nA,
+                                 const uint8_t *__restrict__ S, double *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v[i] = (S[i] && nA[i] > 0.0) ? gA[i] / nA[i] : 0.0;
+}
+
 struct InvWs {
     double *s, *T, *Trx, *D, *W, *Jv, *grad, *hd, *v, *part, *res, *hmax;
     float *amp, *att, *amp_rx, *att_rx, *gscale;
@@ -606,10 +638,12 @@ struct InvWs {
     int2 *zl;   // zeroed pairs [nf][m m]
     int *nz;    // their counts [nf]
     double *x, *r, *z, *p, *q, *cg, *hist;   // CG only
+    void *Hr, *Hi, *C, *C0;                   // asymptotic weights only
+    double *gk, *nk, *gA, *nA;
     void *scratch;
 };
 
-InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt, bool cg) {
+InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt, bool cg, bool asym = false) {
     const size_t N = (size_t)g->nx * g->ny, m = g->m, mm = m * m;
     const size_t es = dtype_size(dt);
     InvWs w;
@@ -645,6 +679,18 @@ InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt, bool cg) {
         w.cg = c.take<double>(8);
         w.hist = c.take<double>(2 * RB_MAX_CG_ITERS);
     }
+    w.Hr = w.Hi = w.C = w.C0 = nullptr;
+    w.gk = w.nk = w.gA = w.nA = nullptr;
+    if (asym) {
+        w.Hr = c.take<char>((size_t)nf * m * N * es);
+        w.Hi = c.take<char>((size_t)nf * m * N * es);
+        w.C = c.take<char>((size_t)nf * m * N * es);
+        w.C0 = c.take<char>((size_t)m * N * es);
+        w.gk = c.take<double>(N);
+        w.nk = c.take<double>(N);
+        w.gA = c.take<double>(N);
+        w.nA = c.take<double>(N);
+    }
     w.scratch = c.take<char>(0);
     return w;
 }
@@ -669,18 +715,20 @@ int selected_count(int m, int dmin) {
 }  // namespace
 
 size_t invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int nf, rb_dtype dt, int batch,
-                              bool cg) {
+                              bool cg, bool asym = false) {
     Carver c(nullptr, 0);
-    carve_inv(c, g, nf, dt, cg);
+    carve_inv(c, g, nf, dt, cg, asym);
     return c.used + 256 + scratch_need(g, t, nf, dt, batch);
 }
 
-// cg_iters = 0: the single step; cg_iters >= 1: CG (cg_hist [host] may be null).
+// cg_iters = 0: the single step; cg_iters >= 1: CG (cg_hist [host] may be
+// null); asym: the single step with the asymptotic weights (32/64-bit).
 rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o, const double *c_in,
                       const double *alpha0, const double *freqs, int nf, const double *p_meas, int cg_iters,
-                      double *c_out, double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes, hipStream_t st) {
+                      double *c_out, double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes, hipStream_t st,
+                      bool asym = false) {
     Carver c(ws, ws_bytes);
-    InvWs w = carve_inv(c, g, nf, o->dtype, cg_iters > 0);
+    InvWs w = carve_inv(c, g, nf, o->dtype, cg_iters > 0, asym);
     if (c.used + 256 + trace_workspace_bytes(g, t, 1) > ws_bytes ||
         c.used + 256 + std::max(adjoint_workspace_bytes(g, nf, o->dtype),
                                 forward_workspace_bytes(g, nf, o->dtype)) > ws_bytes) {
@@ -728,6 +776,53 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     // backprojection computes the gradient only
     k_zero_list<<<nf, kWThreads, 0, st>>>(m, dmin, w.W, m * m, w.zl, w.nz);
     RB_LAUNCHED();
+    const double *delta_dir = w.v;  // the update is res[2] * delta_dir
+    if (asym) {
+        // 3-4. amplitude-normalised backprojection g_A and pair count n_A,
+        // one frequency at a time (each with its own 1 / (omega^2 h^2)^2),
+        // then v = g_A / n_A on the support
+        const int64_t mN = (int64_t)m * N, tot = mN * nf;
+        if (o->dtype == RB_F32)
+            k_asym_tables<float><<<blocks_for(tot, 256), 256, 0, st>>>(tot, (const float *)w.Gr,
+                                                                        (const float *)w.Gi, (float *)w.Hr,
+                                                                        (float *)w.Hi, (float *)w.C);
+        else
+            k_asym_tables<double><<<blocks_for(tot, 256), 256, 0, st>>>(tot, (const double *)w.Gr,
+                                                                         (const double *)w.Gi, (double *)w.Hr,
+                                                                         (double *)w.Hi, (double *)w.C);
+        RB_LAUNCHED();
+        if (o->dtype == RB_F32)
+            RB_TRY(fill_f32((float *)w.C0, 0.0f, mN, st));
+        else
+            RB_TRY(fill_f64((double *)w.C0, 0.0, mN, st));
+        RB_TRY(fill_f64(w.gA, 0.0, N, st));
+        RB_TRY(fill_f64(w.nA, 0.0, N, st));
+        const size_t es = dtype_size(o->dtype);
+        for (int k = 0; k < nf; ++k) {
+            const size_t off = (size_t)k * mN * es;
+            RB_TRY(fill_f64(w.gk, 0.0, N, st));
+            RB_TRY(fill_f64(w.nk, 0.0, N, st));
+            RB_TRY(adjoint_impl(g, (char *)w.Hr + off, (char *)w.Hi + off, nullptr, o->dtype, freqs + k, 1,
+                                w.D + (size_t)k * mm * 2, w.W + (size_t)k * mm, w.gk, nullptr, scratch,
+                                scratch_bytes, st));
+            RB_TRY(hessian_band_impl(g, (char *)w.C + off, w.C0, nullptr, o->dtype, freqs + k, 1, dmin,
+                                     reinterpret_cast<int *>(w.zl + (size_t)k * mm), w.nz + k, m * m, w.nk, st));
+            const double om = 2.0 * M_PI * freqs[k];
+            const double c2 = om * om * g->h * g->h;
+            const double sc = 1.0 / (c2 * c2);
+            k_asym_accum<<<blocks_for(N, 256), 256, 0, st>>>(N, w.gk, w.nk, sc, sc, w.gA, w.nA);
+            RB_LAUNCHED();
+        }
+        k_asym_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.gA, w.nA, w.S, w.v);
+        RB_LAUNCHED();
+        // 5. exact step length along v
+        RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.v, w.Jv, scratch, scratch_bytes,
+                            st, dmin));
+        k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.D, w.part);
+        RB_LAUNCHED();
+        k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
+        RB_LAUNCHED();
+    } else {
     RB_TRY(fill_f64(w.grad, 0.0, N, st));
     RB_TRY(fill_f64(w.hd, 0.0, N, st));
     RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.D, w.W, w.grad, nullptr, scratch,
@@ -735,7 +830,6 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin, reinterpret_cast<int *>(w.zl),
                              w.nz, m * m, w.hd, st));
     RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
-    const double *delta_dir = w.v;  // the update is res[2] * delta_dir
     if (cg_iters == 0) {
         // 4. diagonally weighted direction on the support
         k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.v);
@@ -776,6 +870,7 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
         RB_LAUNCHED();
         delta_dir = w.x;
     }
+    }
     // 6. update of 1/c^2 and the update norm
     k_update_partial<<<kRB, 256, 0, st>>>(N, c_in, w.s, delta_dir, w.res, w.part);
     RB_LAUNCHED();
@@ -806,6 +901,13 @@ size_t rb_invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, i
     if (rb::check_trace(g, t) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
     if (dtype < RB_F64 || dtype > RB_F16) return 0;
     return rb::invert_workspace_bytes(g, t, nf, dtype, emitter_batch, false);
+}
+
+size_t rb_invert_asymptotic_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int32_t nf,
+                                            rb_dtype dtype, int32_t emitter_batch) {
+    if (rb::check_trace(g, t) != RB_OK || nf < 1 || nf > RB_MAX_NF) return 0;
+    if (dtype != RB_F64 && dtype != RB_F32) return 0;
+    return rb::invert_workspace_bytes(g, t, nf, dtype, emitter_batch, false, true);
 }
 
 size_t rb_invert_cg_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int32_t nf, rb_dtype dtype,
@@ -839,6 +941,21 @@ rb_status rb_invert_frequency_set(const rb_geometry *g, const rb_trace_opts *t, 
     RB_TRY(check_invert_args(g, t, o, c_in, freqs_hz, nf, p_meas, c_out, ws));
     return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, 0, c_out, dc_l2, nullptr, ws, ws_bytes,
                            rb::as_stream(stream));
+}
+
+rb_status rb_invert_frequency_set_asymptotic(const rb_geometry *g, const rb_trace_opts *t,
+                                             const rb_invert_opts *o, const double *c_in, const double *alpha0,
+                                             const double *freqs_hz, int32_t nf, const double *p_meas,
+                                             double *c_out, double *dc_l2, void *ws, size_t ws_bytes,
+                                             void *stream) {
+    rb::clear_error();
+    RB_TRY(check_invert_args(g, t, o, c_in, freqs_hz, nf, p_meas, c_out, ws));
+    if (o->dtype != RB_F64 && o->dtype != RB_F32) {
+        rb::set_error("the asymptotic weights need 32- or 64-bit Green's tables (1 / G is unbounded)");
+        return RB_EUNSUPPORTED;
+    }
+    return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, 0, c_out, dc_l2, nullptr, ws, ws_bytes,
+                           rb::as_stream(stream), true);
 }
 
 rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,

@@ -116,3 +116,19 @@ def test_cg_workspace_holds_the_single_step_workspace():
     a = rb.invert_workspace_bytes(g, t, 2, "bf16")
     b = rb.invert_cg_workspace_bytes(g, t, 2, "bf16")
     assert b >= a + 5 * 8 * g.nx * g.ny
+
+
+def test_asymptotic_weights_refuse_16bit_on_host():
+    g = _geom()
+    t = W.TraceOpts(n_rays=30, dtau=1e-7, tau_max=2e-5)
+    L = rb.lib()
+    from paper_2511_16633_amd._binding import _freqs, geometry_struct, invert_opts_struct, trace_opts_struct
+    fa, nf = _freqs([2e5])
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: checks fail first
+    out = ctypes.c_double(0.0)
+    rc = L.rb_invert_frequency_set_asymptotic(ctypes.byref(geometry_struct(g)), ctypes.byref(trace_opts_struct(t)),
+                                              ctypes.byref(invert_opts_struct(W.InvertOpts(), "bf16")), fake, None,
+                                              fa, nf, fake, fake, ctypes.byref(out), fake, 1 << 30, None)
+    assert rc == -4
+    assert rb.invert_asymptotic_workspace_bytes(g, t, 1, "bf16") == 0
+    assert rb.invert_asymptotic_workspace_bytes(g, t, 1, "f32") > rb.invert_workspace_bytes(g, t, 1, "f32")

@@ -215,3 +215,23 @@ def test_fullsize_tof_start(rb, prob):
     ct = prob.c_true.reshape(-1)
     assert np.linalg.norm(c - ct) < 0.6 * np.linalg.norm(c0.reshape(-1) - ct)
     assert np.all(np.isfinite(c)) and c.min() > 1300.0 and c.max() < 1700.0
+
+
+def test_fullsize_asymptotic_weights(rb, prob):
+    """Set 0 of the bench sweep with the asymptotic weights (f32) against the oracle."""
+    g = prob.geom
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    f = prob.freq_sets[0]
+    _say("full-size asymptotic weights f32, set 0")
+    ref = invert.invert_frequency_set_asymptotic(g, topts, prob.inv, prob.c_start, prob.alpha0, f, prob.p_meas[0])
+    c_in = _t(prob.c_start.reshape(-1))
+    c_out = torch.empty_like(c_in)
+    pm = _t(np.stack([prob.p_meas[0].real, prob.p_meas[0].imag], -1))
+    l2 = rb.invert_frequency_set_asymptotic(g, topts, prob.inv, "f32", c_in, _t(prob.alpha0.reshape(-1)), f, pm,
+                                            c_out)
+    dc_g = c_out.cpu().numpy() - prob.c_start.reshape(-1)
+    dc_o = ref[0].reshape(-1) - prob.c_start.reshape(-1)
+    rel = np.linalg.norm(dc_g - dc_o) / np.linalg.norm(dc_o)
+    print(f"[gpu-case] full-size asymptotic: rel-L2 {rel:.3e}, norms {l2:.4f} vs {ref[1]:.4f}", flush=True)
+    assert rel <= 1e-3
+    assert abs(l2 - ref[1]) <= 1e-3 * ref[1]
