@@ -259,18 +259,18 @@ def main():
         del cws
         # the same set with the asymptotic (amplitude-normalised) weights
         if args.dtype in ("f32", "f64"):
-            aws = torch.empty(rb.invert_asymptotic_workspace_bytes(g, topts, nf, args.dtype, batch),
-                              dtype=torch.uint8, device=dev)
+            asws = torch.empty(rb.invert_asymptotic_workspace_bytes(g, topts, nf, args.dtype, batch),
+                               dtype=torch.uint8, device=dev)
 
             def asym_set():
                 ccg.copy_(c_start)
                 return rb.invert_frequency_set_asymptotic(g, topts, prob.inv, args.dtype, ccg, alpha, fs, pms[0],
-                                                          ccg, ws=aws, stream=stream)
+                                                          ccg, ws=asws, stream=stream)
 
             t_as = timed(asym_set)
             cg["asymptotic_weights_ms_per_set"] = round(t_as, 3)
             print(f"[bench] asymptotic weights set 0: {t_as:.2f} ms", file=sys.stderr, flush=True)
-            del aws
+            del asws
         del ccg
         fws = None
 
