@@ -62,16 +62,17 @@ def adjoint_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(dtype: str):
+def measured_traffic(dtype: str, workload: str):
     """HBM bytes per backprojection launch from the committed counter summary,
-    or None when it is missing, for another dtype, or the kernel's sources
-    have changed since the counters were taken."""
+    or None when it is missing, for another dtype or workload, or the
+    kernel's sources have changed since the counters were taken."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             kv = dict(line[2:].split(": ", 1) for line in f.read().splitlines() if line.startswith("- ") and ": " in line)
     except OSError:
         return None
-    if kv.get("source_sha256", "").strip() != adjoint_source_hash() or kv.get("dtype", "").strip() != dtype:
+    if (kv.get("source_sha256", "").strip() != adjoint_source_hash() or kv.get("dtype", "").strip() != dtype
+            or kv.get("workload", "").strip() != workload):
         return None
     try:
         return int(kv["hbm_bytes_per_launch"].split()[0])
@@ -179,11 +180,19 @@ def main():
     achieved = flops / (adj_ms * 1e-3) / 1e12
     esize = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
     alg_bytes = 2 * nf * g.m * N * esize + nf * N * 8   # G (re, im) once + per-frequency gradient partials
+    # The kernel contracts over every ordered pair (unselected pairs carry
+    # weight 0): 8 flop per complex MAC over m^2 pairs is the dense-GEMM
+    # equivalent; the FP32 kernel issues 3 real products per complex MAC.
+    dense = 8.0 * N * g.m * g.m * nf
+    kname = {"f32": "k_adjoint_f32", "bf16": "k_adjoint16_lds", "f16": "k_adjoint16_lds", "f64": "k_adjoint"}[args.dtype]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[args.dtype], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK[args.dtype], 4), "traffic": measured_traffic(args.dtype),
-                "kernel": "k_adjoint_f32 (fused complex backprojection, gradient as the step runs it)",
+                "frac": round(achieved / PEAK[args.dtype], 4), "traffic": measured_traffic(args.dtype, args.workload),
+                "kernel": kname + " (fused complex backprojection, gradient as the step runs it)",
                 "launch_ms": round(adj_ms, 4), "algorithmic_flop_per_launch": flops,
-                "algorithmic_bytes_per_launch": alg_bytes}
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "dense_equivalent": {"flop_per_launch": dense,
+                                     "frac": round(dense / (adj_ms * 1e-3) / 1e12 / PEAK[args.dtype], 4),
+                                     "what": "complex GEMM over all m^2 ordered pairs at 8 flop per complex MAC"}}
 
     # ---- calibration copy for the traffic counters (outside every timed region)
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
