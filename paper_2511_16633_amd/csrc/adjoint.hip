@@ -526,9 +526,30 @@ constexpr int kA16GradWaves = A16_GRAD_WAVES;   // waves per workgroup of the gr
 constexpr int kA16Buf = 3;                         // tiles c, c + 1, c + 2
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // byte offset of (tile row rl, pixel px) within one array of a tile
 __device__ __forceinline__ int a16_off(int rl, int px) { return (rl >> 1) * kA16Pair + (rl & 1) * 128 + 2 * px; }
+
+// The emitter rows of a pass (16 EB NW of them) are receiver rows of tiles
+// that pass through LDS during the same pass, so the epilogue takes G_e from
+// a copy of those tiles instead of reading the tables again: rows of 64
+// pixels (128 bytes) at a stride of 136 bytes, which puts the rows four
+// apart (the lane groups of the epilogue's reads) on different banks.
+constexpr int kA16ERow = 136;
+
+// Copy tile rows 0..31 (both arrays) to rows el..el + 31 of the emitter
+// store sE (rows ne per array); 8 bytes per thread and instruction.
+template <int NW>
+__device__ __forceinline__ void a16_keep(const unsigned char *sT, unsigned char *sE, int ne, int el) {
+#pragma unroll
+    for (int j = 0; j < 1024 / (64 * NW); ++j) {
+        const int q = threadIdx.x + 64 * NW * j;
+        const int arr = q >> 9, rl = (q >> 4) & 31, u = q & 15;
+        const u32x2 v = *reinterpret_cast<const u32x2 *>(sT + arr * kA16Arr + a16_off(rl, 4 * u));
+        *reinterpret_cast<u32x2 *>(sE + (arr * ne + el + rl) * kA16ERow + 8 * u) = v;
+    }
+}
 
 // Aligned full tiles (m a multiple of 32, so every row exists): wave w of
 // NW fills row pairs (16 / NW) w .. of both arrays, one pair per
@@ -557,7 +578,8 @@ template <int NW>
 __device__ __forceinline__ void a16_stage_regs(const unsigned short *__restrict__ gr,
                                                const unsigned short *__restrict__ gi, int m, int64_t N, int rc,
                                                int64_t x0, unsigned char *sT) {
-#pragma unroll
+    // not unrolled: this rare path must not raise the kernel's register count
+#pragma unroll 1
     for (int q = threadIdx.x; q < 2 * kA16KC * 8; q += 64 * NW) {
         const int arr = q >> 8, rl = (q >> 3) & 31, p0 = (q & 7) * 8;
         const unsigned short *g = arr ? gi : gr;
@@ -578,8 +600,6 @@ __device__ __forceinline__ void a16_stage_regs(const unsigned short *__restrict_
 // pixels 4 j + q (j = lane % 16), so lane (j, kk) reads pixels 4 j .. 4 j + 3
 // of rows 8 kk .. 8 kk + 7 with eight 8-byte LDS reads and splits the 16-bit
 // halves among the four fragments.  `base` = a16_off(8 kk, 4 j).
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
 template <typename V>
 __device__ __forceinline__ void a16_frags(const unsigned char *sA, int base, V (&out)[4]) {
     u32x2 d[8];
@@ -633,6 +653,8 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
     __shared__ __align__(16) unsigned char sG1[2 * kA16Arr];
     __shared__ __align__(16) unsigned char sG2[2 * kA16Arr];
     __shared__ float sred[2][NW][kA16NT];
+    constexpr int NE = 16 * EB * NW;   // emitters per pass
+    __shared__ __align__(16) unsigned char sE[2 * NE * kA16ERow];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 15, kk = lane >> 4;
@@ -721,8 +743,11 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
             // adds no wait of its own
             __builtin_amdgcn_sched_barrier(0);
             if (FULL || c + 2 < nch) stage(c + 2, buf(Idx<I + 2>()), vtag);
-            if (!(((c < 64 ? cm[0] : cm[1]) >> (c & 63)) & 1)) return;
             const unsigned char *sb = buf(Idx<I>());
+            const int el = c * kA16KC - ec;   // workgroup-uniform
+            if (el >= 0 && el < NE) a16_keep<NW>(sb, sE, NE, el);
+            __builtin_amdgcn_sched_barrier(0);   // keep the copy's reads apart from the fragment reads
+            if (!(((c < 64 ? cm[0] : cm[1]) >> (c & 63)) & 1)) return;
             V brs[4], bis[4];
             a16_frags<V>(sb, fbase, brs);
             a16_frags<V>(sb + kA16Arr, fbase, bis);
@@ -776,36 +801,29 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
         else
             kloop(std::false_type());
         // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e (Y =
-        // A conj(G)); a lane's four pixels 4 row .. 4 row + 3 of a row are one
-        // 8-byte load
-        const bool wide = ((N & 3) == 0) && (x0 + 4 * row + 4 <= N);
+        // A conj(G)), with G_e from the pass's copy of its emitter rows (zero
+        // beyond m and N, like the tiles); a lane's four pixels 4 row .. 4 row
+        // + 3 of a row are one 8-byte read
+        lds_barrier();   // every wave's copies are visible
 #pragma unroll
         for (int b = 0; b < EB; ++b) {
             if (e0 + 16 * b >= P.m) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int e = e0 + 16 * b + 4 * kk + i;
-                const int64_t xb = x0 + 4 * row;
+                const unsigned char *se = sE + (e - ec) * kA16ERow + 8 * row;
+                const u32x2 vr = *reinterpret_cast<const u32x2 *>(se);
+                const u32x2 vi = *reinterpret_cast<const u32x2 *>(se + NE * kA16ERow);
+                const bool ok = e < P.m;
                 float ger[4], gei[4];
-                if (e < P.m && wide) {
-                    const u32x2 vr = *reinterpret_cast<const u32x2 *>(gr + (int64_t)e * N + xb);
-                    const u32x2 vi = *reinterpret_cast<const u32x2 *>(gi + (int64_t)e * N + xb);
-                    ger[0] = MM16<S>::bits_to_f(vr.x);
-                    ger[1] = MM16<S>::bits_to_f(vr.x >> 16);
-                    ger[2] = MM16<S>::bits_to_f(vr.y);
-                    ger[3] = MM16<S>::bits_to_f(vr.y >> 16);
-                    gei[0] = MM16<S>::bits_to_f(vi.x);
-                    gei[1] = MM16<S>::bits_to_f(vi.x >> 16);
-                    gei[2] = MM16<S>::bits_to_f(vi.y);
-                    gei[3] = MM16<S>::bits_to_f(vi.y >> 16);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool ok = (e < P.m) && (xb + q < N);
-                        ger[q] = ok ? MM16<S>::bits_to_f(gr[(int64_t)e * N + xb + q]) : 0.0f;
-                        gei[q] = ok ? MM16<S>::bits_to_f(gi[(int64_t)e * N + xb + q]) : 0.0f;
-                    }
-                }
+                ger[0] = ok ? MM16<S>::bits_to_f(vr.x) : 0.0f;
+                ger[1] = ok ? MM16<S>::bits_to_f(vr.x >> 16) : 0.0f;
+                ger[2] = ok ? MM16<S>::bits_to_f(vr.y) : 0.0f;
+                ger[3] = ok ? MM16<S>::bits_to_f(vr.y >> 16) : 0.0f;
+                gei[0] = ok ? MM16<S>::bits_to_f(vi.x) : 0.0f;
+                gei[1] = ok ? MM16<S>::bits_to_f(vi.x >> 16) : 0.0f;
+                gei[2] = ok ? MM16<S>::bits_to_f(vi.y) : 0.0f;
+                gei[3] = ok ? MM16<S>::bits_to_f(vi.y >> 16) : 0.0f;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
                     gp[cb] += ger[cb] * yr[b][cb][i] - gei[cb] * yn[b][cb][i];
