@@ -568,6 +568,162 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
     }
 }
 
+// ------------------------------------------------------------------ 16-bit, large rings
+// For large rings the 64 x 64 tiles above move 16 KB per 64 MFMAs and are
+// bound by memory traffic.  This kernel takes 128 x 128 (e, r) tiles, waves 2 x 2
+// of 64 x 64 (4 x 4 blocks of 16 x 16, 64 MFMAs per wave and step), which
+// halves the bytes per MFMA.  The accumulators leave no registers for staged
+// tiles, so both operands go from memory straight into LDS (16-byte direct
+// loads, the chunk swizzle of the 64-tile kernel) from two plain tables: G
+// for the e side and a copy of G times delta (rounded to the storage type
+// as the 64-tile kernel rounds it) for the r side, whose rows are padded
+// with zeros to a multiple of 32 pixels.  Rows at or beyond m read row m - 1
+// (their outputs are dropped); on the e side a chunk beyond N reads the last
+// whole chunk, which the zero padding on the r side multiplies by 0.
+// It pays from m = 1024 (68 -> 52 ms for four frequencies on 1100^2 pixels,
+// the table pass included); at m = 512 the table pass outweighs the gain
+// (10.1 against 8.2 ms).
+#ifndef RB_FWD16_BIG_M
+#define RB_FWD16_BIG_M 1024
+#endif
+constexpr int kF16BigM = RB_FWD16_BIG_M;
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int kFBT = 128;
+constexpr int kFBArr = kFBT * kF16KC * 2;   // one array of a tile (bytes)
+
+// Gd[k][r][x] = G[k][r][x] * df[x] (rows padded to np pixels with zeros);
+// one thread per eight pixels of a row.
+template <typename S>
+__global__ void k_scale16(int64_t N, int64_t np, int64_t rows, const S *__restrict__ Gr,
+                          const S *__restrict__ Gi, const float *__restrict__ df, S *__restrict__ Dr,
+                          S *__restrict__ Di) {
+    using V = typename MM16<S>::vec;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = np / 8;
+    if (t >= rows * per) return;
+    const int64_t row = t / per, x0 = (t - row * per) * 8;
+    V vr, vi;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t x = x0 + q;
+        const bool ok = x < N;
+        const float d = ok ? df[x] : 0.0f;
+        const float gr = ok ? MM16<S>::to_f(Gr[row * N + x]) : 0.0f;
+        const float gi = ok ? MM16<S>::to_f(Gi[row * N + x]) : 0.0f;
+        vr[q] = MM16<S>::from_f(gr * d);
+        vi[q] = MM16<S>::from_f(gi * d);
+    }
+    *reinterpret_cast<V *>(Dr + row * np + x0) = vr;
+    *reinterpret_cast<V *>(Di + row * np + x0) = vi;
+}
+
+// Stage one k-step (32 pixels from xc) of rows r0 .. r0 + 127 of a table
+// with row stride `ld` into one LDS array: wave w fills rows 32 w .. 32 w +
+// 31, sixteen rows per instruction; lane l writes chunk slot l % 4 of row
+// l / 4 and so loads the chunk the swizzle puts there.
+__device__ __forceinline__ void fb_stage(const unsigned short *__restrict__ g, int64_t ld, int m, int r0,
+                                         int64_t xc, int64_t xmax, unsigned char *dst) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int rb = 32 * wave + 16 * i;
+        const int rl = rb + (lane >> 2);
+        const int r = min(r0 + rl, m - 1);
+        const int ch = (lane & 3) ^ ((rl >> 1) & 3);
+        const int64_t x = min(xc + 8 * ch, xmax);
+        __builtin_amdgcn_global_load_lds(g + (int64_t)r * ld + x, (lds_void_t *)(dst + rb * 64), 16, 0, 0);
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256, 2) k_forward16_big(FwdParams P, const S *__restrict__ Gr,
+                                                          const S *__restrict__ Gi, const S *__restrict__ Dr,
+                                                          const S *__restrict__ Di, int64_t np,
+                                                          float *__restrict__ part) {
+    using V = typename MM16<S>::vec;
+    __shared__ __align__(16) unsigned char sA[2][2 * kFBArr];   // [buffer][re, im] G_e rows
+    __shared__ __align__(16) unsigned char sB[2][2 * kFBArr];   // [buffer][re, im] G_r delta rows
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wr = wave & 1;
+    int te, tr, split, k;
+    fwd_block(P, te, tr, split, k);
+    if (P.dmin >= 32 && max_circ_dist(P.m, te * kFBT, kFBT, tr * kFBT, kFBT) < P.dmin) return;
+    const bool idle = (te == tr && we > wr) ||
+                      (P.dmin >= 32 && max_circ_dist(P.m, te * kFBT + 64 * we, 64, tr * kFBT + 64 * wr, 64) < P.dmin);
+    const int64_t N = P.N;
+    const unsigned short *ger = reinterpret_cast<const unsigned short *>(Gr + (int64_t)k * P.m * N);
+    const unsigned short *gei = reinterpret_cast<const unsigned short *>(Gi + (int64_t)k * P.m * N);
+    const unsigned short *gdr = reinterpret_cast<const unsigned short *>(Dr + (int64_t)k * P.m * np);
+    const unsigned short *gdi = reinterpret_cast<const unsigned short *>(Di + (int64_t)k * P.m * np);
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const int nch = (int)((ke - ks + kF16KC - 1) / kF16KC);
+    auto stage = [&](int c, int buf) {
+        const int64_t xc = ks + (int64_t)c * kF16KC;
+        fb_stage(ger, N, P.m, te * kFBT, xc, N - 8, sA[buf]);
+        fb_stage(gei, N, P.m, te * kFBT, xc, N - 8, sA[buf] + kFBArr);
+        fb_stage(gdr, np, P.m, tr * kFBT, xc, np - 8, sB[buf]);
+        fb_stage(gdi, np, P.m, tr * kFBT, xc, np - 8, sB[buf] + kFBArr);
+    };
+    f4 re[4][4], im[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) re[b][c] = im[b][c] = f4{0, 0, 0, 0};
+    if (nch > 0) stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) stage(c + 1, buf ^ 1);
+        if (!idle) {
+            V b_r[4], b_i[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int rb = 64 * wr + 16 * cb + row;
+                b_r[cb] = *reinterpret_cast<const V *>(sB[buf] + f16_off(rb, kk));
+                b_i[cb] = *reinterpret_cast<const V *>(sB[buf] + kFBArr + f16_off(rb, kk));
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int ra = 64 * we + 16 * b + row;
+                const V a_r = *reinterpret_cast<const V *>(sA[buf] + f16_off(ra, kk));
+                const V a_i = *reinterpret_cast<const V *>(sA[buf] + kFBArr + f16_off(ra, kk));
+                const V a_n = neg(a_i);
+                // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    re[b][cb] = MM16<S>::mma(a_r, b_r[cb], re[b][cb]);
+                    re[b][cb] = MM16<S>::mma(a_n, b_i[cb], re[b][cb]);
+                    im[b][cb] = MM16<S>::mma(a_r, b_i[cb], im[b][cb]);
+                    im[b][cb] = MM16<S>::mma(a_i, b_r[cb], im[b][cb]);
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // tile c + 1 has landed in LDS
+        __syncthreads();
+    }
+    if (idle) return;
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int r = tr * kFBT + 64 * wr + 16 * cb + row;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ee = te * kFBT + 64 * we + 16 * b + 4 * kk + i;
+                const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+                pp[o] = re[b][cb][i];
+                pp[o + 1] = im[b][cb][i];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -585,13 +741,20 @@ static int device_cus() {
     return cached[dev];
 }
 
+// The 128 x 128-tile 16-bit kernel: large rings, rows of whole 16-byte chunks.
+static bool fwd16_big(const rb_geometry *g, rb_dtype dt) {
+    const int64_t N = (int64_t)g->nx * g->ny;
+    return (dt == RB_BF16 || dt == RB_F16) && g->m >= kF16BigM && N % 8 == 0;
+}
+
 static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, rb_dtype dt) {
     FwdParams P;
+    const int tile = fwd16_big(g, dt) ? kFBT : 64;
     P.m = g->m;
-    P.mp = (g->m + 63) / 64 * 64;
+    P.mp = (g->m + tile - 1) / tile * tile;
     P.N = (int64_t)g->nx * g->ny;
     P.nf = nf;
-    P.ntl = P.mp / 64;
+    P.ntl = P.mp / tile;
     const int ntri = P.ntl * (P.ntl + 1) / 2;
     // about four rounds of resident workgroups (two per CU), rounded down so
     // the last round is full
@@ -614,27 +777,33 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
     return P;
 }
 
-// workspace: max |delta|, the split partials, and (16-bit) delta as float
+// workspace: max |delta|, the split partials, (16-bit) delta as float, and
+// (large rings) the G delta tables with rows padded to np pixels
 struct FwdWs {
     double *dmax, *dparts;
     void *part;
     float *df;
+    void *dr, *di;
+    int64_t np;
 };
 
-static FwdWs carve_fwd(Carver &c, const FwdParams &P, rb_dtype dt) {
+static FwdWs carve_fwd(Carver &c, const FwdParams &P, rb_dtype dt, bool big) {
     const size_t es = dt == RB_F64 ? 8 : 4;
     FwdWs w;
     w.dmax = c.take<double>(1);
     w.dparts = (dt == RB_BF16 || dt == RB_F16) ? c.take<double>(kReduceBlocks) : nullptr;
     w.part = c.take<char>((size_t)P.nsplit * P.nf * P.mp * P.mp * 2 * es);
     w.df = (dt == RB_BF16 || dt == RB_F16) ? c.take<float>((size_t)P.N + 8) : nullptr;
+    w.np = (P.N + kF16KC - 1) / kF16KC * kF16KC;
+    w.dr = big ? (void *)c.take<uint16_t>((size_t)P.nf * P.m * w.np) : nullptr;
+    w.di = big ? (void *)c.take<uint16_t>((size_t)P.nf * P.m * w.np) : nullptr;
     return w;
 }
 
 size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
     FwdParams P = fwd_params(g, nullptr, nf, dt);
     Carver c(nullptr, 0);
-    carve_fwd(c, P, dt);
+    carve_fwd(c, P, dt, fwd16_big(g, dt));
     return c.used + 256;
 }
 
@@ -647,8 +816,9 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
     }
     FwdParams P = fwd_params(g, freqs, nf, dt);
     P.dmin = dmin;
+    const bool big = fwd16_big(g, dt);
     Carver c(ws, ws_bytes);
-    FwdWs w = carve_fwd(c, P, dt);
+    FwdWs w = carve_fwd(c, P, dt, big);
     const unsigned nblk = (unsigned)((int64_t)P.ntri * P.nsplit * nf);
     const int64_t tot = (int64_t)nf * P.m * P.m;
     switch (dt) {
@@ -673,7 +843,23 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             RB_TRY(reduce_absmax_f64(delta, P.N, w.dparts, w.dmax, st));
             k_delta_f32<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, delta, w.dmax, w.df);
             RB_LAUNCHED();
-            if (dt == RB_BF16)
+            if (big) {
+                const int64_t rows = (int64_t)nf * P.m;
+                auto go = [&](auto tag) {
+                    using S = decltype(tag);
+                    k_scale16<S><<<blocks_for(rows * (w.np / 8), 256), 256, 0, st>>>(
+                        P.N, w.np, rows, (const S *)G_re, (const S *)G_im, w.df, (S *)w.dr, (S *)w.di);
+                    RB_LAUNCHED();
+                    k_forward16_big<S><<<nblk, 256, 0, st>>>(P, (const S *)G_re, (const S *)G_im,
+                                                             (const S *)w.dr, (const S *)w.di, w.np,
+                                                             (float *)w.part);
+                    return RB_OK;
+                };
+                if (dt == RB_BF16)
+                    RB_TRY(go(__hip_bfloat16()));
+                else
+                    RB_TRY(go(__half()));
+            } else if (dt == RB_BF16)
                 k_forward16_lds<__hip_bfloat16><<<nblk, 256, 0, st>>>(P, (const __hip_bfloat16 *)G_re,
                                                                       (const __hip_bfloat16 *)G_im, w.df,
                                                                       (float *)w.part);

@@ -286,8 +286,11 @@ def test_hessian_banded_ignores_bad_pairs_and_is_deterministic(rb):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
-@pytest.mark.parametrize("shape", [(37, 29, 40), (50, 50, 130)])
+@pytest.mark.parametrize("shape", [(37, 29, 40), (50, 50, 130), (24, 20, 1030), (22, 20, 1100)])
 def test_forward_matches_oracle(rb, dtype, shape):
+    """The last two shapes take the 128 x 128-tile 16-bit kernel (m >= 1024,
+    N a multiple of 8): whole and partial last pixel chunks, m not a
+    multiple of the tile."""
     nx, ny, m = shape
     geom = W.centred_grid(nx, 0.5e-3, m, 12e-3, 1500.0)
     import dataclasses

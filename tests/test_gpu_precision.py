@@ -65,6 +65,23 @@ def config1_set0():
     return _Case(W.breast_ring256(), 720)
 
 
+@pytest.fixture(scope="module")
+def ring1040():
+    # a large ring on a small grid: the 16-bit step takes the 128 x 128-tile
+    # forward kernel, with its receiver-band skip (dmin = 130)
+    return _Case(W.custom(44, 0.5e-3, 1040, 20e-3, 360, [[200e3, 250e3]], seed=9), 360)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_precision_form_ring1040_grid44(rb, ring1040, dtype):
+    print(f"[gpu-case] precision ring1040_grid44 dtype={dtype}", flush=True)
+    rel, mx, l2 = ring1040.run(rb, dtype)
+    print(f"[precision] ring1040_grid44 {dtype}: rel-L2(dc) {rel:.3e}, max|dc diff| {mx:.3e} m/s, "
+          f"|dc| {l2:.4f} vs oracle {ring1040.ref_l2:.4f}", flush=True)
+    b_rel, b_max = BOUNDS[dtype]
+    assert rel <= b_rel and mx <= b_max
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
 def test_precision_form_ring64_grid128(rb, config0, dtype):
     print(f"[gpu-case] precision ring64_grid128 dtype={dtype}", flush=True)
