@@ -27,6 +27,10 @@
  *    water: slowness 1 / c_background and no absorption.
  *  - Complex data are interleaved (re, im) FP64 pairs; data cubes are
  *    [nf][m (emitter e)][m (receiver r)].
+ *  - Green's tables G_re / G_im start on a 16-byte boundary (any hipMalloc
+ *    or torch allocation does; an offset view may not): the contractions
+ *    read their rows in 16-byte pieces and refuse other pointers with
+ *    RB_EINVAL.
  *  - SI units: m, s, Hz, m/s; absorption alpha0 in Np / (m MHz^y).
  *  - Errors: invalid arguments are detected on the host before any work is
  *    enqueued and return RB_EINVAL; a HIP launch/runtime failure returns

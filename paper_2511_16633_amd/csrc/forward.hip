@@ -881,6 +881,8 @@ rb_status check_contraction(const rb_geometry *g, const void *G_re, const void *
     RB_TRY(check_freqs(freqs, nf));
     RB_CHECK_ARG(dt >= RB_F64 && dt <= RB_F16, "unknown dtype %d", (int)dt);
     RB_CHECK_ARG(G_re && G_im, "G_re/G_im are NULL");
+    RB_CHECK_ARG(((uintptr_t)G_re & 15) == 0 && ((uintptr_t)G_im & 15) == 0,
+                 "G_re/G_im must be 16-byte aligned (the kernels read rows in 16-byte pieces)");
     RB_CHECK_ARG(!(dt == RB_BF16 || dt == RB_F16) || scale, "scale is required for 16-bit storage");
     return RB_OK;
 }

@@ -132,3 +132,16 @@ def test_asymptotic_weights_refuse_16bit_on_host():
     assert rc == -4
     assert rb.invert_asymptotic_workspace_bytes(g, t, 1, "bf16") == 0
     assert rb.invert_asymptotic_workspace_bytes(g, t, 1, "f32") > rb.invert_workspace_bytes(g, t, 1, "f32")
+
+
+def test_misaligned_green_tables_are_rejected_on_host():
+    g = _geom()
+    L = rb.lib()
+    from paper_2511_16633_amd._binding import _freqs, geometry_struct
+    fa, nf = _freqs([2e5])
+    ok, bad = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1008)   # never dereferenced: checks fail first
+    rc = L.rb_born_forward(ctypes.byref(geometry_struct(g)), bad, ok, ok, 1, fa, nf, ok, ok, ok, 1 << 30, None)
+    assert rc == -1 and "16-byte" in L.rb_last_error().decode()
+    rc = L.rb_born_adjoint_weighted(ctypes.byref(geometry_struct(g)), ok, bad, ok, 1, fa, nf, ok, ok, ok, None,
+                                    ok, 1 << 30, None)
+    assert rc == -1 and "16-byte" in L.rb_last_error().decode()
