@@ -1,0 +1,128 @@
+"""GPU parity at the large instance's full size (1024 elements, 1100 x 1100
+grid at 0.2 mm, four frequencies per set) in the launch configuration
+`bench.py --workload ring1024_grid1100` times: the backprojection at sampled
+pixels (bf16 and f32 tables) and the bf16 forward at sampled pairs (the
+128 x 128-tile kernel), against the oracle computed for those outputs one by
+one.  The tables are seeded random draws made on the host in blocks of
+emitters (the oracle keeps the columns and rows it needs)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import born, invert
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"f32": 1e-5, "bf16": 1e-2}
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_16633_amd as rbm
+    rbm.lib()
+    return rbm
+
+
+@pytest.fixture(scope="module")
+def case():
+    """Geometry, frequencies, device tables and the host samples the oracle
+    needs: all emitters at 300 pixels, full rows of the sampled emitters."""
+    g = W.centred_grid(1100, 0.2e-3, 1024, 110e-3, 1500.0)
+    freqs = list(np.linspace(0.3e6, 2.0e6, 48)[:4])
+    rng = np.random.default_rng(301)
+    xs = np.sort(rng.choice(g.n_pixels, 300, replace=False))
+    pairs = [(int(a), int(b)) for a, b in zip(rng.integers(0, g.m, 24), rng.integers(0, g.m, 24))]
+    rows = sorted({e for e, _ in pairs} | {r for _, r in pairs})
+    m, n = g.m, g.n_pixels
+    t_scale = 2.0 * g.ring_radius / g.c_background
+    T = torch.empty((m, n), dtype=torch.float64, device=DEV)
+    A = torch.empty((m, n), dtype=torch.float32, device=DEV)
+    B = torch.empty((m, n), dtype=torch.float32, device=DEV)
+    cols = {"T": np.empty((m, xs.size)), "A": np.empty((m, xs.size)), "B": np.empty((m, xs.size))}
+    full = {}
+    blk = 64
+    for e0 in range(0, m, blk):
+        r = np.random.default_rng(1000 + e0)
+        t = r.uniform(0.05, 1.0, (blk, n)) * t_scale
+        a = r.uniform(5.0, 50.0, (blk, n)).astype(np.float32)
+        b = r.uniform(0.0, 0.2, (blk, n)).astype(np.float32)
+        T[e0:e0 + blk] = torch.as_tensor(t, device=DEV)
+        A[e0:e0 + blk] = torch.as_tensor(a, device=DEV)
+        B[e0:e0 + blk] = torch.as_tensor(b, device=DEV)
+        cols["T"][e0:e0 + blk] = t[:, xs]
+        cols["A"][e0:e0 + blk] = a[:, xs]
+        cols["B"][e0:e0 + blk] = b[:, xs]
+        for e in rows:
+            if e0 <= e < e0 + blk:
+                full[e] = (t[e - e0].copy(), a[e - e0].astype(np.float64), b[e - e0].astype(np.float64))
+    z64 = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    z32 = torch.zeros((m, m), dtype=torch.float32, device=DEV)
+    tabs = {"T": T, "amp": A, "att": B, "T_rx": z64, "amp_rx": z32, "att_rx": z32}
+    return g, freqs, xs, pairs, tabs, cols, full
+
+
+def _green(rb, g, tabs, freqs, dtype):
+    td = {"f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    Gr = torch.empty((len(freqs), g.m, g.n_pixels), dtype=td, device=DEV)
+    Gi = torch.empty_like(Gr)
+    sc = torch.empty(len(freqs), dtype=torch.float32, device=DEV)
+    rb.build_green(g, tabs, freqs, 1.0, dtype, Gr, Gi, sc)
+    return Gr, Gi, sc
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_large_backprojection_sampled_pixels(rb, case, dtype):
+    g, freqs, xs, _, tabs, cols, _ = case
+    nf = len(freqs)
+    D = W.random_residual(nf, g.m, 302)
+    mask = invert.receiver_mask(g.m).astype(np.float64)
+    Wd = np.repeat(mask[None], nf, axis=0)
+    _say(f"large backprojection {dtype} (1024 elements, 1100^2, random tables)")
+    Gr, Gi, sc = _green(rb, g, tabs, freqs, dtype)
+    grad = torch.zeros(g.n_pixels, dtype=torch.float64, device=DEV)
+    dres = torch.as_tensor(np.stack([D.real, D.imag], -1), device=DEV)
+    rb.born_adjoint_weighted(g, Gr, Gi, sc, dtype, freqs, dres, torch.as_tensor(Wd, device=DEV), grad, None)
+    torch.cuda.synchronize()
+    gg = grad[torch.as_tensor(xs, device=DEV)].cpu().numpy()
+    del Gr, Gi
+    torch.cuda.empty_cache()
+    go = np.zeros(xs.size)
+    for k, f in enumerate(freqs):
+        G = born.green(cols["T"], cols["A"], cols["B"], f)
+        go += born.born_adjoint(G, Wd[k] * D[k], f, g.h ** 2)
+    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    print(f"[large] backprojection {dtype}: rel-L2 {rel:.3e} at {xs.size} pixels", flush=True)
+    assert rel <= TOL[dtype]
+
+
+def test_large_forward_sampled_pairs_bf16(rb, case):
+    g, freqs, _, pairs, tabs, _, full = case
+    nf = len(freqs)
+    delta = W.random_delta(g.n_pixels, 303)
+    _say("large forward bf16 (1024 elements, 1100^2, random tables)")
+    Gr, Gi, sc = _green(rb, g, tabs, freqs, "bf16")
+    d = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=DEV)
+    rb.born_forward(g, Gr, Gi, sc, "bf16", freqs, torch.as_tensor(delta, device=DEV), d)
+    torch.cuda.synchronize()
+    dg = d.cpu().numpy()
+    del Gr, Gi
+    torch.cuda.empty_cache()
+    for k, f in enumerate(freqs):
+        G = {e: born.green(t[None], a[None], b[None], f)[0] for e, (t, a, b) in full.items()}
+        om2 = (2 * math.pi * f) ** 2 * g.h ** 2
+        ref = np.array([om2 * np.sum(G[e] * G[r] * delta) for e, r in pairs])
+        got = np.array([dg[k, e, r, 0] + 1j * dg[k, e, r, 1] for e, r in pairs])
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"[large] forward bf16 f={f:.3e}: rel-L2 {rel:.3e} at {len(pairs)} pairs", flush=True)
+        assert rel <= TOL["bf16"]
