@@ -126,3 +126,40 @@ def test_large_forward_sampled_pairs_bf16(rb, case):
         rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"[large] forward bf16 f={f:.3e}: rel-L2 {rel:.3e} at {len(pairs)} pairs", flush=True)
         assert rel <= TOL["bf16"]
+
+
+def test_large_tables_sampled_emitters(rb):
+    """Ray tables of the large instance's start model (1440 rays per element,
+    emitters traced 128 at a time as bench.py does) at two sampled emitters
+    against the oracle's tracer and rasteriser."""
+    from oracle import rays
+    prob = W.breast_ring1024(with_data=False)
+    g = prob.geom
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    _say("large trace, all 1024 emitters in batches of 128")
+    tabs = rb.alloc_tables(g, DEV)
+    ws = torch.empty(rb.trace_workspace_bytes(g, topts, 128), dtype=torch.uint8, device=DEV)
+    s = torch.as_tensor(1.0 / prob.c_start.reshape(-1), device=DEV)
+    a = torch.as_tensor(prob.alpha0.reshape(-1), device=DEV)
+    rb.trace_rays(g, topts, s, a, tabs, ws=ws)
+    torch.cuda.synchronize()
+    del ws
+    for e in (5, 700):
+        T, A, B, Tr, Ar, Br = rays.tables(g, topts, 1.0 / prob.c_start, prob.alpha0, e, e + 1)
+        Tg = tabs["T"][e].cpu().numpy()
+        cg, co = np.isfinite(Tg), np.isfinite(T[0])
+        both = cg & co
+        ndiff = int((cg != co).sum())
+        dT = float(np.max(np.abs(Tg[both] - T[0][both])))
+        ag = tabs["amp"][e].cpu().numpy().astype(np.float64)
+        da = float(np.max(np.abs(ag[both] - A[0][both]) / A[0][both]))
+        bg = tabs["att"][e].cpu().numpy().astype(np.float64)
+        dB = float(np.max(np.abs(bg[both] - B[0][both])))
+        print(f"[large] tables emitter {e}: coverage differences {ndiff}, max |dT| {dT:.2e} s, "
+              f"max rel da {da:.2e}, max |dB| {dB:.2e}", flush=True)
+        assert ndiff <= 50 and both.sum() > 0.5 * Tg.size
+        assert dT <= 1e-9 and da <= 2e-6 and dB <= 1e-6
+        Trg = tabs["T_rx"][e].cpu().numpy()
+        msk = invert.receiver_mask(g.m)[e]
+        assert np.all(np.isfinite(Trg[msk])) and np.all(np.isfinite(Tr[0][msk]))
+        assert np.max(np.abs(Trg[msk] - Tr[0][msk])) <= 1e-9
