@@ -159,7 +159,10 @@ rb_status rb_build_green(const rb_geometry *g, const rb_tables *tab,
  *     d_er(omega) = omega^2 h^2 sum_x G_e(x, omega) G_r(x, omega) delta(x).
  * delta: [N] FP64 perturbation of q.  d_out: [nf][m][m] complex (written,
  * symmetric in e, r).  G as produced by rb_build_green; scale as there
- * (NULL = 1).  ws: rb_forward_workspace_bytes().
+ * (NULL = 1).  ws: rb_forward_workspace_bytes(); with 16-bit tables and
+ * m >= 1024 (N a multiple of 8) it includes a copy of G times delta
+ * (2 nf m N 16-bit values, rows padded to a multiple of 32 pixels) that
+ * the 128 x 128-tile kernel reads.
  */
 size_t rb_forward_workspace_bytes(const rb_geometry *g, int32_t nf, rb_dtype dtype);
 rb_status rb_born_forward(const rb_geometry *g, const void *G_re, const void *G_im,
