@@ -580,9 +580,9 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
 // with zeros to a multiple of 32 pixels.  Rows at or beyond m read row m - 1
 // (their outputs are dropped); on the e side a chunk beyond N reads the last
 // whole chunk, which the zero padding on the r side multiplies by 0.
-// It pays from m = 1024 (68 -> 52 ms for four frequencies on 1100^2 pixels,
-// the table pass included); at m = 512 the table pass outweighs the gain
-// (10.1 against 8.2 ms).
+// It pays from m = 1024 (68 -> 36 ms for four frequencies on 1100^2 pixels,
+// the table pass included); at m = 512 the table pass outweighed the gain
+// (10.1 against 8.2 ms, measured before the table pass used 16-byte loads).
 #ifndef RB_FWD16_BIG_M
 #define RB_FWD16_BIG_M 1024
 #endif
@@ -603,15 +603,29 @@ __global__ void k_scale16(int64_t N, int64_t np, int64_t rows, const S *__restri
     if (t >= rows * per) return;
     const int64_t row = t / per, x0 = (t - row * per) * 8;
     V vr, vi;
+    if (x0 + 8 <= N) {
+        // whole run: 16-byte loads (N is a multiple of 8 here, so rows and
+        // runs are 16-byte aligned)
+        const V gr = *reinterpret_cast<const V *>(Gr + row * N + x0);
+        const V gi = *reinterpret_cast<const V *>(Gi + row * N + x0);
+        const f4 d0 = *reinterpret_cast<const f4 *>(df + x0), d1 = *reinterpret_cast<const f4 *>(df + x0 + 4);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int64_t x = x0 + q;
-        const bool ok = x < N;
-        const float d = ok ? df[x] : 0.0f;
-        const float gr = ok ? MM16<S>::to_f(Gr[row * N + x]) : 0.0f;
-        const float gi = ok ? MM16<S>::to_f(Gi[row * N + x]) : 0.0f;
-        vr[q] = MM16<S>::from_f(gr * d);
-        vi[q] = MM16<S>::from_f(gi * d);
+        for (int q = 0; q < 8; ++q) {
+            const float d = q < 4 ? d0[q] : d1[q - 4];
+            vr[q] = MM16<S>::from_f((float)gr[q] * d);
+            vi[q] = MM16<S>::from_f((float)gi[q] * d);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t x = x0 + q;
+            const bool ok = x < N;
+            const float d = ok ? df[x] : 0.0f;
+            const float gr = ok ? MM16<S>::to_f(Gr[row * N + x]) : 0.0f;
+            const float gi = ok ? MM16<S>::to_f(Gi[row * N + x]) : 0.0f;
+            vr[q] = MM16<S>::from_f(gr * d);
+            vi[q] = MM16<S>::from_f(gi * d);
+        }
     }
     *reinterpret_cast<V *>(Dr + row * np + x0) = vr;
     *reinterpret_cast<V *>(Di + row * np + x0) = vi;
