@@ -27,6 +27,19 @@ __device__ __forceinline__ void green_value(const GreenParams &P, int k, double 
     im = mag * sn;
 }
 
+// The same with the magnitude a exp(-b f^y) in FP32, for tables stored in
+// 16 bits: the phase is reduced and evaluated in FP64 as above.
+__device__ __forceinline__ void green_value_mag32(const GreenParams &P, int k, double t, float amag, float b,
+                                                  double &re, double &im) {
+    const double cycles = P.f[k] * t + 0.125;
+    const double frac = cycles - floor(cycles);
+    double sn, cs;
+    sincospi(2.0 * frac, &sn, &cs);
+    const double mag = (double)(amag * expf(-b * (float)P.fy[k]));
+    re = mag * cs;
+    im = mag * sn;
+}
+
 // Green's tables written by the rasteriser's write pass in place of the
 // T/amp/att tables (32/64-bit storage): G [nf][m][N].
 struct GreenOut {
