@@ -6,7 +6,8 @@
 // entry (16 bytes) once and writes the nf frequencies of the set, so the
 // tables are read once per frequency set rather than once per frequency.
 // The phase is reduced to [0, 1) cycles in FP64 before sincospi, and every
-// value is computed in FP64 and rounded once to the storage type.
+// value is computed in FP64 and rounded once to the storage type, except
+// that 16-bit tables take the magnitude a exp(-B f^y) in FP32.
 #include <algorithm>
 #include <cmath>
 
