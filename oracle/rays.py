@@ -35,16 +35,8 @@ def lib():
         _lib = ctypes.CDLL(LIB)
         _lib.orc_tables.restype = ctypes.c_int
         _lib.orc_trace_fan.restype = ctypes.c_int
-        _lib.orc_order_bits.restype = ctypes.c_int
         _lib.orc_rx_links.restype = ctypes.c_int
     return _lib
-
-
-def order_bits(geom, topts) -> int:
-    """Fraction bits F of the fixed-point arrival order u_q = floor(u 2^F),
-    u = T / dtau, used to pick the first arrival among covering triangles."""
-    P = make_params(geom, topts)
-    return int(lib().orc_order_bits(ctypes.byref(P)))
 
 
 def _p(a):

@@ -27,11 +27,9 @@
  * n, n+1 and is split into the triangles (P[n][j], P[n][j+1], P[n+1][j+1])
  * and (P[n][j], P[n+1][j+1], P[n+1][j]); a point inside a triangle takes
  * the barycentric interpolation of T, a and B; over all covering triangles
- * the first arrival wins.  Arrivals are ordered by the interpolated step
- * index u = T / dtau = la n_a + lb n_b + lc n_c held in fixed point,
- * u_q = floor(max(u, 0) 2^F) with F = 64 - bits(2 nmax n_rays - 1) -
- * bits(nmax) (u_q and the triangle index then fill one 64-bit word), and
- * equal u_q go to the first triangle in (n, j, triangle) order.
+ * the first arrival wins: the candidate with the smallest interpolated
+ * travel time T = la T_a + lb T_b + lc T_c, computed in FP64 and compared
+ * exactly; equal values go to the first triangle in (n, j, triangle) order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -180,27 +178,12 @@ int orc_trace_fan(const orc_params *P, const double *s, const double *alpha, int
 }
 
 /* One triangle: evaluate at the candidate points inside its closed bounding
- * box; keep the smallest u_q per point (strict <, so earlier triangles keep
- * ties). */
-typedef struct { double x, y, t, a, b, u; } vtx;   /* u: step index of the node */
+ * box; keep the smallest interpolated T per point in Q (strict <, so the
+ * triangles visited earlier keep exact ties). */
+typedef struct { double x, y, t, a, b; } vtx;
 
-static int bit_length(uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; }
-
-/* Fraction bits of the fixed-point arrival order (see the file header). */
-int orc_order_bits(const orc_params *P)
-{
-    const uint64_t nidx = 2ull * (uint64_t)P->nmax * (uint64_t)P->n_rays;
-    return 64 - bit_length(nidx > 0 ? nidx - 1 : 0) - bit_length((uint64_t)P->nmax);
-}
-
-static uint64_t order_u(double u, double scale)
-{
-    if (!(u > 0.0)) return 0;
-    return (uint64_t)floor(u * scale);
-}
-
-static void raster_grid(const orc_params *P, double scale, const vtx *A, const vtx *B, const vtx *C,
-                        uint64_t *Q, double *T, double *Am, double *Bt)
+static void raster_grid(const orc_params *P, const vtx *A, const vtx *B, const vtx *C,
+                        double *Q, double *T, double *Am, double *Bt)
 {
     double e1x = B->x - A->x, e1y = B->y - A->y;
     double e2x = C->x - A->x, e2y = C->y - A->y;
@@ -224,11 +207,11 @@ static void raster_grid(const orc_params *P, double scale, const vtx *A, const v
             double lc = (e1x * qy - e1y * qx) / det;
             double la = (1.0 - lb) - lc;
             if (la < tol || lb < tol || lc < tol) continue;
-            uint64_t q = order_u(la * A->u + lb * B->u + lc * C->u, scale);
+            double t = la * A->t + lb * B->t + lc * C->t;
             size_t p = (size_t)jj * (size_t)P->nx + (size_t)ii;
-            if (q < Q[p]) {
-                Q[p] = q;
-                T[p] = la * A->t + lb * B->t + lc * C->t;
+            if (t < Q[p]) {
+                Q[p] = t;
+                T[p] = t;
                 Am[p] = la * A->a + lb * B->a + lc * C->a;
                 Bt[p] = la * A->b + lb * B->b + lc * C->b;
             }
@@ -236,9 +219,9 @@ static void raster_grid(const orc_params *P, double scale, const vtx *A, const v
     }
 }
 
-static void raster_points(const orc_params *P, double scale, const vtx *A, const vtx *B, const vtx *C,
+static void raster_points(const orc_params *P, const vtx *A, const vtx *B, const vtx *C,
                           int npts, const double *px, const double *py,
-                          uint64_t *Q, double *T, double *Am, double *Bt,
+                          double *Q, double *T, double *Am, double *Bt,
                           int64_t tri_index, int64_t *Wi, double *Wl)
 {
     double e1x = B->x - A->x, e1y = B->y - A->y;
@@ -261,10 +244,10 @@ static void raster_points(const orc_params *P, double scale, const vtx *A, const
         double lc = (e1x * qy - e1y * qx) / det;
         double la = (1.0 - lb) - lc;
         if (la < tol || lb < tol || lc < tol) continue;
-        uint64_t q = order_u(la * A->u + lb * B->u + lc * C->u, scale);
-        if (q < Q[r]) {
-            Q[r] = q;
-            T[r] = la * A->t + lb * B->t + lc * C->t;
+        double t = la * A->t + lb * B->t + lc * C->t;
+        if (t < Q[r]) {
+            Q[r] = t;
+            T[r] = t;
             Am[r] = la * A->a + lb * B->a + lc * C->a;
             Bt[r] = la * A->b + lb * B->b + lc * C->b;
             if (Wi) {   /* the winning triangle and the point's barycentrics */
@@ -292,39 +275,37 @@ int orc_tables(const orc_params *P, const double *s, const double *alpha, int e0
         double th = 2.0 * M_PI * (double)r / (double)m;
         px[r] = P->R * cos(th); py[r] = P->R * sin(th);
     }
-    const double scale = ldexp(1.0, orc_order_bits(P));
     int status = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int e = e0; e < e1; ++e) {
         size_t nn = (size_t)(P->nmax + 1) * nr;
         double *X = (double *)malloc(sizeof(double) * nn * 6);
         int32_t *L = (int32_t *)malloc(sizeof(int32_t) * nr);
-        uint64_t *Q = (uint64_t *)malloc(sizeof(uint64_t) * (N + (size_t)m));
+        double *Q = (double *)malloc(sizeof(double) * (N + (size_t)m));
         if (!X || !L || !Q) { status = -2; free(X); free(L); free(Q); continue; }
-        uint64_t *Qr = Q + N;
+        double *Qr = Q + N;
         double *Y = X + nn, *PX = Y + nn, *PY = PX + nn, *Bn = PY + nn, *AMP = Bn + nn;
         orc_trace_fan(P, s, alpha, e, X, Y, PX, PY, Bn, AMP, L);
         double *Te = T + (size_t)(e - e0) * N, *Ae = Am + (size_t)(e - e0) * N;
         double *Be = Bt + (size_t)(e - e0) * N;
         double *Tr = Trx + (size_t)(e - e0) * m, *Ar = Arx + (size_t)(e - e0) * m;
         double *Br = Brx + (size_t)(e - e0) * m;
-        for (size_t p = 0; p < N; ++p) { Q[p] = UINT64_MAX; Te[p] = NAN; Ae[p] = 0.0; Be[p] = 0.0; }
-        for (int r = 0; r < m; ++r) { Qr[r] = UINT64_MAX; Tr[r] = NAN; Ar[r] = 0.0; Br[r] = 0.0; }
+        for (size_t p = 0; p < N; ++p) { Q[p] = INFINITY; Te[p] = NAN; Ae[p] = 0.0; Be[p] = 0.0; }
+        for (int r = 0; r < m; ++r) { Qr[r] = INFINITY; Tr[r] = NAN; Ar[r] = 0.0; Br[r] = 0.0; }
         for (int n = 0; n < P->nmax; ++n) {
             for (int j = 0; j + 1 < nr; ++j) {
                 if (n + 1 > L[j] || n + 1 > L[j + 1]) continue;
                 size_t k00 = (size_t)n * nr + j, k10 = k00 + 1;
                 size_t k01 = k00 + nr, k11 = k01 + 1;
                 double t0 = (double)n * P->dtau, t1 = (double)(n + 1) * P->dtau;
-                const double u0 = (double)n, u1 = (double)(n + 1);
-                vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00], u0};
-                vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10], u0};
-                vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11], u1};
-                vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01], u1};
-                raster_grid(P, scale, &p00, &p10, &p11, Q, Te, Ae, Be);
-                raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
-                raster_grid(P, scale, &p00, &p11, &p01, Q, Te, Ae, Be);
-                raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
+                vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00]};
+                vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10]};
+                vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11]};
+                vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01]};
+                raster_grid(P, &p00, &p10, &p11, Q, Te, Ae, Be);
+                raster_points(P, &p00, &p10, &p11, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
+                raster_grid(P, &p00, &p11, &p01, Q, Te, Ae, Be);
+                raster_points(P, &p00, &p11, &p01, m, px, py, Qr, Tr, Ar, Br, 0, NULL, NULL);
             }
         }
         free(X); free(L); free(Q);
@@ -348,32 +329,30 @@ int orc_rx_links(const orc_params *P, const double *s, const double *alpha, int 
     const int nr = P->n_rays, m = P->m;
     size_t nn = (size_t)(P->nmax + 1) * nr;
     double *buf = (double *)malloc(sizeof(double) * nn * 4 + sizeof(double) * 4 * m);
-    uint64_t *Qr = (uint64_t *)malloc(sizeof(uint64_t) * m);
+    double *Qr = (double *)malloc(sizeof(double) * m);
     if (!buf || !Qr) { free(buf); free(Qr); return -2; }
     double *PX = buf, *PY = PX + nn, *Bn = PY + nn, *AMP = Bn + nn;
     double *px = AMP + nn, *py = px + m, *Ar = py + m, *Br = Ar + m;
     for (int r = 0; r < m; ++r) {
         double th = 2.0 * M_PI * (double)r / (double)m;
         px[r] = P->R * cos(th); py[r] = P->R * sin(th);
-        Qr[r] = UINT64_MAX; T[r] = NAN; W[r] = -1;
+        Qr[r] = INFINITY; T[r] = NAN; W[r] = -1;
         Wl[3 * r] = Wl[3 * r + 1] = Wl[3 * r + 2] = 0.0;
     }
     orc_trace_fan(P, s, alpha, e, X, Y, PX, PY, Bn, AMP, L);
-    const double scale = ldexp(1.0, orc_order_bits(P));
     for (int n = 0; n < P->nmax; ++n) {
         for (int j = 0; j + 1 < nr; ++j) {
             if (n + 1 > L[j] || n + 1 > L[j + 1]) continue;
             size_t k00 = (size_t)n * nr + j, k10 = k00 + 1;
             size_t k01 = k00 + nr, k11 = k01 + 1;
             double t0 = (double)n * P->dtau, t1 = (double)(n + 1) * P->dtau;
-            const double u0 = (double)n, u1 = (double)(n + 1);
-            vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00], u0};
-            vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10], u0};
-            vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11], u1};
-            vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01], u1};
+            vtx p00 = {X[k00], Y[k00], t0, AMP[k00], Bn[k00]};
+            vtx p10 = {X[k10], Y[k10], t0, AMP[k10], Bn[k10]};
+            vtx p11 = {X[k11], Y[k11], t1, AMP[k11], Bn[k11]};
+            vtx p01 = {X[k01], Y[k01], t1, AMP[k01], Bn[k01]};
             const int64_t cell = (int64_t)n * nr + j;
-            raster_points(P, scale, &p00, &p10, &p11, m, px, py, Qr, T, Ar, Br, 2 * cell, W, Wl);
-            raster_points(P, scale, &p00, &p11, &p01, m, px, py, Qr, T, Ar, Br, 2 * cell + 1, W, Wl);
+            raster_points(P, &p00, &p10, &p11, m, px, py, Qr, T, Ar, Br, 2 * cell, W, Wl);
+            raster_points(P, &p00, &p11, &p01, m, px, py, Qr, T, Ar, Br, 2 * cell + 1, W, Wl);
         }
     }
     free(buf); free(Qr);

@@ -225,7 +225,9 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
 // Arrival key of a candidate: the interpolated step index u = T / dtau in
 // fixed point, floor(max(u, 0) 2^F), above the triangle index
 // idx = 2 (n nr + j) + tri.  The minimum key is the first arrival, equal
-// fixed-point values going to the first triangle in (n, j, tri) order.
+// fixed-point values going to the first triangle in (n, j, tri) order: the
+// smallest interpolated travel time, except that two times within one
+// quantum dtau 2^-F of each other count as equal.
 // ~0 marks an uncovered point (no key reaches it: the fixed-point part
 // stays below 2^(64 - idx_bits) - 2^F).
 __device__ __forceinline__ uint64_t arrival_key(const TP &P, double u, uint32_t idx) {

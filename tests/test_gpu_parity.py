@@ -75,9 +75,16 @@ def _oracle_tables(geom, topts, c, alpha, e0=0, e1=None):
 
 # ----------------------------------------------------------------------------- tracing
 
-@pytest.mark.parametrize("case", ["ring64_grid128", "ragged_45x45_m12", "ring_outside_grid"])
+@pytest.mark.parametrize("case", ["ring64_grid128", "ragged_45x45_m12", "ring_outside_grid", "ring64_caustic_lens"])
 def test_trace_tables_match_oracle(rb, case):
-    if case == "ring64_grid128":
+    if case == "ring64_caustic_lens":
+        # a strong slow lens in front of element 0 folds the wavefronts of the
+        # nearby elements: where two branches overlap, both sides must keep the
+        # earlier one (their amplitudes differ severalfold)
+        geom = W.centred_grid(128, 0.5e-3, 64, 30e-3, 1500.0)
+        c, al = W.lens_medium(geom, (25e-3, 0.0), 1.5e-3, -400.0)
+        topts = W.resolve_trace_opts(geom, c, 360)
+    elif case == "ring64_grid128":
         p = W.small_ring(with_data=False)
         geom, c, al = p.geom, p.c_true, p.alpha0
         topts = W.resolve_trace_opts(geom, c, 360)

@@ -162,6 +162,18 @@ def ellipse_phantom(geom: Geometry, seed: int, n_ellipses: int = 3,
     return c, alpha
 
 
+def lens_medium(geom: Geometry, centre: Tuple[float, float], sigma: float, dc: float,
+                c0: float = 1500.0, alpha0: float = 3.0):
+    """Water with one Gaussian speed anomaly c0 + dc exp(-|x - centre|^2 /
+    (2 sigma^2)) and a uniform absorption map.  A strong slow anomaly (dc of
+    a few hundred m/s below c0, sigma a few pixels) a few millimetres in
+    front of an element focuses that element's rays: its wavefront folds
+    behind the lens (a caustic) and some points see several arrivals."""
+    X, Y = geom.pixel_centres()
+    c = c0 + dc * np.exp(-((X - centre[0]) ** 2 + (Y - centre[1]) ** 2) / (2.0 * sigma ** 2))
+    return c, np.full_like(c, alpha0)
+
+
 def breast_phantom(geom: Geometry, seed: int, calcifications: bool = False,
                    support_radius: float | None = None):
     """Breast-like phantom: fat disc, fibroglandular blobs, inclusions, texture.
