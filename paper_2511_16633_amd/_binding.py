@@ -81,6 +81,8 @@ def lib():
         "rb_adjoint_workspace_bytes": (_sz, [_P(RbGeometry), _i32, ctypes.c_int]),
         "rb_born_adjoint_weighted": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32,
                                                     _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "rb_born_hessian_banded": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32, _i32,
+                                                  _vp, _vp, _i32, _vp, _vp]),
         "rb_invert_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int, _i32]),
         "rb_invert_frequency_set": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts), _vp, _vp,
                                                    _P(_d), _i32, _vp, _vp, _P(_d), _vp, _sz, _vp]),
@@ -104,6 +106,7 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    L.rb_signatures = sig
     _lib = L
     return L
 

@@ -741,18 +741,14 @@ __global__ void __launch_bounds__(256, 2) k_forward16_big(FwdParams P, const S *
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-// Compute units of the current device (cached per device; 256 on MI355X).
+// Compute units of the current device (256 on MI355X), queried on every
+// call: the library keeps no mutable state between calls.
 static int device_cus() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        cached[dev] = cus;
-    }
-    return cached[dev];
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
 }
 
 // The 128 x 128-tile 16-bit kernel: large rings, rows of whole 16-byte chunks.

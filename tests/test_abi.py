@@ -29,6 +29,30 @@ def test_library_exports_every_declared_symbol():
     assert rb.version().startswith("rayborn")
 
 
+def _declared_arity():
+    """Parameter count of every entry point declared in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(rb_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", text):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_declares_every_symbol_with_its_arity():
+    """The binding gives every declared entry point a restype and argtypes
+    with as many arguments as the header declares (ctypes would otherwise
+    pass untyped integers and pointers)."""
+    L = rb.lib()
+    arity = _declared_arity()
+    assert set(arity) == set(_declared())
+    sig = L.rb_signatures
+    for name, n in arity.items():
+        assert name in sig, f"{name} has no signature in the binding"
+        assert len(sig[name][1]) == n, (name, len(sig[name][1]), n)
+        assert getattr(L, name).argtypes is not None
+
+
 def test_status_strings():
     L = rb.lib()
     assert L.rb_status_string(0) == b"ok"
