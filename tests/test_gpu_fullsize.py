@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workload as W
+from _parity import close
 from oracle import born, invert, rays
 
 torch = pytest.importorskip("torch")
@@ -93,8 +94,8 @@ def test_fullsize_backprojection_sampled_pixels(rb, prob):
         G = born.green(T[:, xs], A[:, xs].astype(np.float64), B[:, xs].astype(np.float64), f)
         go += born.born_adjoint(G, Wd[k] * D[k], f, g.h ** 2)
         ho += born.hessian_diag(G, Wd[k], f, g.h ** 2)
-    assert np.linalg.norm(gg[xs] - go) / np.linalg.norm(go) <= 1e-5
-    assert np.linalg.norm(hg[xs] - ho) / np.linalg.norm(ho) <= 1e-5
+    close(gg[xs], go, 1e-5, "full-size grad, sampled pixels")
+    close(hg[xs], ho, 1e-5, "full-size hdiag, sampled pixels")
     # the banded Hessian diagonal for the same weights (band + zeroed pairs)
     zl, nz = [], []
     for k in range(nf):
@@ -111,8 +112,8 @@ def test_fullsize_backprojection_sampled_pixels(rb, prob):
                            torch.as_tensor(np.array(nz, np.int32), device=DEV), hb)
     torch.cuda.synchronize()
     hbg = hb.cpu().numpy()
-    assert np.linalg.norm(hbg[xs] - ho) / np.linalg.norm(ho) <= 1e-5
-    assert np.linalg.norm(hbg - hg) / np.linalg.norm(hg) <= 2e-5
+    close(hbg[xs], ho, 1e-5, "full-size banded hdiag, sampled pixels")
+    close(hbg, hg, 2e-5, "full-size banded vs MFMA hdiag")
 
 
 def test_fullsize_forward_sampled_pairs(rb, prob):
@@ -140,7 +141,7 @@ def test_fullsize_forward_sampled_pairs(rb, prob):
         om2 = (2 * math.pi * f) ** 2 * g.h ** 2
         ref = np.array([om2 * np.sum(G[e] * G[r] * delta) for e, r in pairs])
         got = np.array([dg[k, e, r, 0] + 1j * dg[k, e, r, 1] for e, r in pairs])
-        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+        close(got, ref, 1e-5, f"full-size forward f{k}, sampled pairs")
 
 
 def test_fullsize_one_frequency_set_end_to_end(rb, prob):
@@ -160,9 +161,9 @@ def test_fullsize_one_frequency_set_end_to_end(rb, prob):
     rel = np.linalg.norm(dc_g - dc_o) / np.linalg.norm(dc_o)
     print(f"[gpu-case] full-size set 0: rel-L2 {rel:.3e}, max|dc diff| {np.abs(dc_g - dc_o).max():.3e} m/s, "
           f"norms {l2:.4f} vs {ref['dc_l2']:.4f}", flush=True)
-    assert rel <= 1e-3
-    assert np.abs(dc_g - dc_o).max() <= 0.1
-    assert abs(l2 - ref["dc_l2"]) <= 1e-3 * ref["dc_l2"]
+    assert rel <= 1e-4
+    assert np.abs(dc_g - dc_o).max() <= 0.01
+    assert abs(l2 - ref["dc_l2"]) <= 1e-4 * ref["dc_l2"]
 
 
 def test_fullsize_cg_three_iterations(rb, prob):
@@ -232,6 +233,8 @@ def test_fullsize_asymptotic_weights(rb, prob):
     dc_g = c_out.cpu().numpy() - prob.c_start.reshape(-1)
     dc_o = ref[0].reshape(-1) - prob.c_start.reshape(-1)
     rel = np.linalg.norm(dc_g - dc_o) / np.linalg.norm(dc_o)
-    print(f"[gpu-case] full-size asymptotic: rel-L2 {rel:.3e}, norms {l2:.4f} vs {ref[1]:.4f}", flush=True)
-    assert rel <= 1e-3
-    assert abs(l2 - ref[1]) <= 1e-3 * ref[1]
+    print(f"[gpu-case] full-size asymptotic: rel-L2 {rel:.3e}, max|dc diff| {np.abs(dc_g - dc_o).max():.3e} m/s, "
+          f"norms {l2:.4f} vs {ref[1]:.4f}", flush=True)
+    assert rel <= 1e-4
+    assert np.abs(dc_g - dc_o).max() <= 0.01
+    assert abs(l2 - ref[1]) <= 1e-4 * ref[1]

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workload as W
+from _parity import close
 from oracle import born, invert
 
 torch = pytest.importorskip("torch")
@@ -101,9 +102,7 @@ def test_large_backprojection_sampled_pixels(rb, case, dtype):
     for k, f in enumerate(freqs):
         G = born.green(cols["T"], cols["A"], cols["B"], f)
         go += born.born_adjoint(G, Wd[k] * D[k], f, g.h ** 2)
-    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
-    print(f"[large] backprojection {dtype}: rel-L2 {rel:.3e} at {xs.size} pixels", flush=True)
-    assert rel <= TOL[dtype]
+    close(gg, go, TOL[dtype], f"large backprojection {dtype} at {xs.size} pixels")
 
 
 def test_large_forward_sampled_pairs_bf16(rb, case):
@@ -123,9 +122,7 @@ def test_large_forward_sampled_pairs_bf16(rb, case):
         om2 = (2 * math.pi * f) ** 2 * g.h ** 2
         ref = np.array([om2 * np.sum(G[e] * G[r] * delta) for e, r in pairs])
         got = np.array([dg[k, e, r, 0] + 1j * dg[k, e, r, 1] for e, r in pairs])
-        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        print(f"[large] forward bf16 f={f:.3e}: rel-L2 {rel:.3e} at {len(pairs)} pairs", flush=True)
-        assert rel <= TOL["bf16"]
+        close(got, ref, TOL["bf16"], f"large forward bf16 f={f:.3e} at {len(pairs)} pairs")
 
 
 def test_large_tables_sampled_emitters(rb):

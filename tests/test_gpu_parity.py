@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import workload as W
+from _parity import close
 from oracle import born, invert, rays
 
 torch = pytest.importorskip("torch")
@@ -204,9 +205,9 @@ def test_adjoint_and_hessian_match_oracle(rb, dtype, shape):
         g_o += born.born_adjoint(G, Wd[k] * D[k], f, geom.h ** 2)
         h_o += born.hessian_diag(G, Wd[k], f, geom.h ** 2)
     tol = CONTRACTION_TOL[dtype]
-    assert _rel(grad.cpu().numpy(), g_o) <= tol
-    assert _rel(hd.cpu().numpy(), h_o) <= tol
-    assert _rel(grad_only.cpu().numpy(), g_o) <= tol   # the gradient-only kernel
+    close(grad.cpu().numpy(), g_o, tol, f"grad {dtype} {shape}")
+    close(hd.cpu().numpy(), h_o, tol, f"hdiag {dtype} {shape}")
+    close(grad_only.cpu().numpy(), g_o, tol, f"grad-only {dtype} {shape}")   # the gradient-only kernel
 
 
 def _banded_weights(m, nf, dmin, nzero_each, seed):
@@ -266,8 +267,8 @@ def test_hessian_banded_matches_oracle(rb, dtype, shape):
         assert np.all(hg == 0.0) and np.all(h_o == 0.0)
         return
     tol = CONTRACTION_TOL[dtype]
-    assert _rel(hg, h_o) <= tol
-    assert _rel(hg, hd_mfma.cpu().numpy()) <= 2 * tol
+    close(hg, h_o, tol, f"banded hdiag {dtype} {shape}")
+    close(hg, hd_mfma.cpu().numpy(), 2 * tol, f"banded vs MFMA hdiag {dtype} {shape}")
 
 
 def test_hessian_banded_ignores_bad_pairs_and_is_deterministic(rb):
@@ -289,7 +290,7 @@ def test_hessian_banded_ignores_bad_pairs_and_is_deterministic(rb):
     G = born.green(T, A.astype(np.float64), B.astype(np.float64), freqs[0])
     h_o = born.hessian_diag(G, Wd[0], freqs[0], geom.h ** 2)
     assert np.array_equal(outs[0], outs[1])
-    assert _rel(outs[0], h_o) <= 1e-5
+    close(outs[0], h_o, 1e-5, "banded hdiag, out-of-range pairs")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
@@ -315,7 +316,7 @@ def test_forward_matches_oracle(rb, dtype, shape):
     for k, f in enumerate(freqs):
         G = born.green(T, A.astype(np.float64), B.astype(np.float64), f)
         do = born.born_forward(G, delta, f, geom.h ** 2)
-        assert _rel(dg[k], do) <= tol
+        close(dg[k], do, tol, f"forward {dtype} {shape} f{k}")
         assert np.array_equal(dg[k], dg[k].T)
 
 

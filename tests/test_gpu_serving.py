@@ -1,6 +1,9 @@
-"""Serving loop on the GPU: jobs of different ring sizes run concurrently on
-their own streams, and every result is bit-for-bit the one the job gives
-alone."""
+"""Serving loop on the GPU: jobs of different ring sizes and contraction
+types run concurrently on their own streams, and every result is
+bit-for-bit the one the job gives alone.  The mix holds a 16-bit job of the
+large-ring class (1040 elements around a small grid, BF16 contractions with
+the 128 x 128-tile forward), whose served image is also checked against the
+FP64 oracle at equal accuracy (rel-L2 <= 1e-2, max |dc| <= 1 m/s)."""
 import copy
 
 import numpy as np
@@ -23,13 +26,26 @@ def serving():
     return S
 
 
+_RING1040 = None
+
+
+def _ring1040():
+    """A large ring on a small grid (the 1024+-element class, cheap to check)."""
+    global _RING1040
+    if _RING1040 is None:
+        _RING1040 = W.custom(44, 0.5e-3, 1040, 20e-3, 360, [[200e3, 250e3]], seed=9)
+    return _RING1040
+
+
 def _jobs(S):
-    specs = [(0, 2101, 0.085), (0, 2102, 0.11), (1, 2103, 0.1), (0, 2104, 0.095), (0, 2105, 0.12), (0, 2106, 0.03)]
+    specs = [(0, 2101, 0.085), (0, 2102, 0.11), (1, 2103, 0.1), (0, 2104, 0.095), (0, 2105, 0.12), (0, 2106, 0.03),
+             (2, None, None)]
     jobs = []
     for i, (cls, seed, radius) in enumerate(specs):
-        p = W.serving_job(cls, seed, radius)
+        p = W.serving_job(cls, seed, radius) if seed is not None else _ring1040()
+        dtype = "f32" if seed is not None else "bf16"
         topts = W.resolve_trace_opts(p.geom, p.c_start, p.trace.n_rays)
-        jobs.append(S.Job(jid=i, arrival=0.05 * i, geom=p.geom, topts=topts, inv=p.inv, dtype="f32",
+        jobs.append(S.Job(jid=i, arrival=0.05 * i, geom=p.geom, topts=topts, inv=p.inv, dtype=dtype,
                           c_start=p.c_start, alpha0=p.alpha0, freq_sets=p.freq_sets, p_meas=p.p_meas,
                           size_class=cls))
     return jobs
@@ -37,7 +53,7 @@ def _jobs(S):
 
 def test_mixed_results_equal_alone(serving):
     S = serving
-    print("[gpu-case] serving: 6 jobs alone, then mixed", flush=True)
+    print("[gpu-case] serving: 7 jobs alone, then mixed", flush=True)
     alone = _jobs(S)
     srv = S.Server(DEV, max_running=4)
     for j in alone:
@@ -54,6 +70,17 @@ def test_mixed_results_equal_alone(serving):
     # several jobs were on the device at once
     spans = sorted((j.t_admit, j.t_done) for j in mixed)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    # the served bf16 job against the FP64 oracle, at equal accuracy
+    from oracle import invert
+    j = mixed[-1]
+    assert j.dtype == "bf16" and j.geom.m == 1040
+    ref_c, _ = invert.invert_frequency_set(j.geom, j.topts, j.inv, j.c_start, j.alpha0, j.freq_sets[0], j.p_meas[0])
+    dc_g = j.result - j.c_start.reshape(-1)
+    dc_o = ref_c.reshape(-1) - j.c_start.reshape(-1)
+    rel = float(np.linalg.norm(dc_g - dc_o) / np.linalg.norm(dc_o))
+    mx = float(np.abs(dc_g - dc_o).max())
+    print(f"[gpu-case] served bf16 ring1040 vs oracle: rel-L2 {rel:.3e}, max|dc diff| {mx:.3e} m/s", flush=True)
+    assert rel <= 1e-2 and mx <= 1.0
 
 
 def test_admission_respects_the_budget(serving):
