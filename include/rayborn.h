@@ -187,6 +187,25 @@ rb_status rb_born_adjoint_weighted(const rb_geometry *g, const void *G_re, const
                                    void *stream);
 
 /*
+ * For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and arguments as rb_born_adjoint_weighted, with no workspace
+ * argument.  Its scratch is one fixed array of RB_NOALLOC_SCRATCH_BYTES per
+ * GPU, inside the library, allocated when the library is loaded on that GPU
+ * and held until the process ends; the call itself allocates nothing.
+ * Problems whose rb_adjoint_workspace_bytes() exceeds that size are refused
+ * with RB_ENOMEM before any work is enqueued.  Every call on one GPU shares
+ * the array: calls that overlap on one GPU (different streams or threads)
+ * race and give undefined results; calls ordered on one stream are safe.
+ * Results are bitwise those of rb_born_adjoint_weighted.
+ */
+#define RB_NOALLOC_SCRATCH_BYTES (64u << 20)
+rb_status rb_born_adjoint_weighted_noalloc(const rb_geometry *g, const void *G_re, const void *G_im,
+                                           const float *scale, rb_dtype dtype, const double *freqs_hz,
+                                           int32_t nf, const double *d_res, const double *w_data,
+                                           double *grad, double *hdiag, void *stream);
+
+/*
  * Hessian diagonal of Eq. 10 for the data weights the single step uses
  * (Results: receivers on the opposite part of the ring, the largest values
  * of a frequency set zeroed):

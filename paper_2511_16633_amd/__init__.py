@@ -27,6 +27,7 @@ from ._binding import (  # noqa: F401
     build_green,
     born_forward,
     born_adjoint_weighted,
+    born_adjoint_weighted_noalloc,
     born_hessian_banded,
     invert_frequency_set,
     invert_frequency_set_cg,

@@ -81,6 +81,8 @@ def lib():
         "rb_adjoint_workspace_bytes": (_sz, [_P(RbGeometry), _i32, ctypes.c_int]),
         "rb_born_adjoint_weighted": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32,
                                                     _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "rb_born_adjoint_weighted_noalloc": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d),
+                                                            _i32, _vp, _vp, _vp, _vp, _vp]),
         "rb_born_hessian_banded": (ctypes.c_int, [_P(RbGeometry), _vp, _vp, _vp, ctypes.c_int, _P(_d), _i32, _i32,
                                                   _vp, _vp, _i32, _vp, _vp]),
         "rb_invert_workspace_bytes": (_sz, [_P(RbGeometry), _P(RbTraceOpts), _i32, ctypes.c_int, _i32]),
@@ -242,6 +244,20 @@ def born_adjoint_weighted(g, G_re, G_im, scale, dtype, freqs, d_res: torch.Tenso
     _check(lib().rb_born_adjoint_weighted(ctypes.byref(geometry_struct(g)), _ptr(G_re), _ptr(G_im), _ptr(scale),
                                           _dt(dtype), fa, nf, _ptr(d_res), _ptr(w_data), _ptr(grad),
                                           _ptr(hdiag), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def born_adjoint_weighted_noalloc(g, G_re, G_im, scale, dtype, freqs, d_res: torch.Tensor, w_data: torch.Tensor,
+                                  grad: torch.Tensor, hdiag: Optional[torch.Tensor], stream=None):
+    """born_adjoint_weighted without a workspace: the library's fixed
+    per-GPU scratch (NOALLOC_SCRATCH_BYTES) serves instead.  Calls that
+    overlap on one GPU race."""
+    fa, nf = _freqs(freqs)
+    _check(lib().rb_born_adjoint_weighted_noalloc(ctypes.byref(geometry_struct(g)), _ptr(G_re), _ptr(G_im),
+                                                  _ptr(scale), _dt(dtype), fa, nf, _ptr(d_res), _ptr(w_data),
+                                                  _ptr(grad), _ptr(hdiag), _stream(stream)))
 
 
 def born_hessian_banded(g, G_re, G_im, scale, dtype, freqs, dmin: int, zeroed: Optional[torch.Tensor],

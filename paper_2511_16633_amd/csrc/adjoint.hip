@@ -16,6 +16,7 @@
 // around the diagonal) are skipped per 16x16 block.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "born.h"
@@ -1014,6 +1015,36 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
     return RB_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+// Scratch of rb_born_adjoint_weighted_noalloc: the same workspace the
+// ordinary entry point carves from its caller's buffer, held in one device
+// array per GPU (allocated when the library is loaded on that GPU and kept
+// until the process ends).  Host code never passes `scratch` itself to a
+// kernel: its name there is a host-side stand-in; the device address comes
+// from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[RB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device.
+static rb_status scratch_address(void **out) {
+    int dev = 0;
+    RB_HIP(hipGetDevice(&dev));
+    RB_CHECK_ARG(dev >= 0 && dev < kMaxDevices, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        RB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RB_OK;
+}
+
 }  // namespace rb
 
 extern "C" {
@@ -1033,6 +1064,26 @@ rb_status rb_born_adjoint_weighted(const rb_geometry *g, const void *G_re, const
     RB_CHECK_ARG(ws, "workspace is NULL");
     return rb::adjoint_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, d_res, w_data, grad, hdiag, ws, ws_bytes,
                             rb::as_stream(stream));
+}
+
+rb_status rb_born_adjoint_weighted_noalloc(const rb_geometry *g, const void *G_re, const void *G_im,
+                                           const float *scale, rb_dtype dtype, const double *freqs_hz,
+                                           int32_t nf, const double *d_res, const double *w_data, double *grad,
+                                           double *hdiag, void *stream) {
+    rb::clear_error();
+    RB_TRY(rb::check_contraction(g, G_re, G_im, scale, dtype, freqs_hz, nf));
+    RB_CHECK_ARG(d_res && w_data && grad, "d_res/w_data/grad are NULL");
+    const size_t need = rb::adjoint_workspace_bytes(g, nf, dtype);
+    if (need > (size_t)RB_NOALLOC_SCRATCH_BYTES) {
+        rb::set_error("rb_born_adjoint_weighted_noalloc: this problem needs %zu bytes of scratch, the fixed "
+                      "scratch holds %zu (use rb_born_adjoint_weighted with a workspace)",
+                      need, (size_t)RB_NOALLOC_SCRATCH_BYTES);
+        return RB_ENOMEM;
+    }
+    void *ws = nullptr;
+    RB_TRY(rb::scratch_address(&ws));
+    return rb::adjoint_impl(g, G_re, G_im, scale, dtype, freqs_hz, nf, d_res, w_data, grad, hdiag, ws,
+                            (size_t)RB_NOALLOC_SCRATCH_BYTES, rb::as_stream(stream));
 }
 
 }  // extern "C"
