@@ -286,6 +286,41 @@ rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *
                                      void *stream);
 
 /*
+ * One frequency set of several independent problems (jobs of different ring
+ * sizes, grids and contraction types), batched: every job's single step as
+ * rb_invert_frequency_set computes it, all on one stream, with the
+ * backprojection contractions of the jobs grouped into shared launches - a
+ * flat grid of (job, frequency, pixel tile) work items, one launch per
+ * contraction type for up to 8 jobs - so that small problems fill the GPU
+ * together (the serving loop's batched form of the Inverse Problem
+ * section's single step).  Each job's result is bitwise the one
+ * rb_invert_frequency_set gives it alone: its work items compute exactly
+ * what the single-job launch computes, and every reduction keeps its order.
+ * Each rb_set_job holds that call's arguments (ws: the job's own workspace
+ * of rb_invert_workspace_bytes; jobs may not share workspaces or outputs);
+ * status [host], if not NULL, receives the job's own status (RB_ENUMERIC
+ * leaves that job's c_out = c_in).  The call synchronises the stream and
+ * returns the first failure, RB_OK if none.  1 <= njobs <= RB_MAX_GROUP.
+ */
+#define RB_MAX_GROUP 256
+typedef struct {
+    const rb_geometry *g;
+    const rb_trace_opts *t;
+    const rb_invert_opts *o;
+    const double *c_in;
+    const double *alpha0;
+    const double *freqs_hz;   /* [host][nf] */
+    int32_t nf;
+    const double *p_meas;
+    double *c_out;
+    double *dc_l2;            /* [host] out */
+    rb_status *status;        /* [host] out, or NULL */
+    void *ws;
+    size_t ws_bytes;
+} rb_set_job;
+rb_status rb_invert_frequency_sets_grouped(const rb_set_job *jobs, int32_t njobs, void *stream);
+
+/*
  * The frequency set with asymptotic (amplitude-normalised) weights in place
  * of the Hessian-diagonal weight (single-step paragraph: weights that
  * diagonalise the Hessian, here in their ray-Born asymptotic form; the

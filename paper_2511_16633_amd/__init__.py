@@ -30,6 +30,7 @@ from ._binding import (  # noqa: F401
     born_adjoint_weighted_noalloc,
     born_hessian_banded,
     invert_frequency_set,
+    invert_frequency_sets_grouped,
     invert_frequency_set_cg,
     invert_frequency_set_asymptotic,
     tof_invert,

@@ -52,6 +52,14 @@ class RbInvertOpts(ctypes.Structure):
                 ("eps", ctypes.c_double), ("y_pow", ctypes.c_double), ("dtype", ctypes.c_int)]
 
 
+class RbSetJob(ctypes.Structure):
+    _fields_ = [("g", ctypes.POINTER(RbGeometry)), ("t", ctypes.POINTER(RbTraceOpts)),
+                ("o", ctypes.POINTER(RbInvertOpts)), ("c_in", ctypes.c_void_p), ("alpha0", ctypes.c_void_p),
+                ("freqs_hz", ctypes.POINTER(ctypes.c_double)), ("nf", ctypes.c_int32),
+                ("p_meas", ctypes.c_void_p), ("c_out", ctypes.c_void_p), ("dc_l2", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.POINTER(ctypes.c_int)), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
@@ -100,6 +108,7 @@ def lib():
         "rb_invert_frequency_set_asymptotic": (ctypes.c_int, [_P(RbGeometry), _P(RbTraceOpts), _P(RbInvertOpts),
                                                               _vp, _vp, _P(_d), _i32, _vp, _vp, _P(_d), _vp, _sz,
                                                               _vp]),
+        "rb_invert_frequency_sets_grouped": (ctypes.c_int, [_P(RbSetJob), _i32, _vp]),
         "rb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "rb_last_error": (ctypes.c_char_p, []),
         "rb_version": (ctypes.c_char_p, []),
@@ -284,6 +293,35 @@ def invert_frequency_set(g, t, o, dtype, c_in: torch.Tensor, alpha0: Optional[to
                                          fa, nf, _ptr(p_meas), _ptr(c_out), ctypes.byref(out), _ptr(ws),
                                          ws.numel(), _stream(stream)))
     return out.value
+
+
+def invert_frequency_sets_grouped(jobs, stream=None):
+    """One frequency set of each job, batched (rb_invert_frequency_sets_grouped).
+
+    jobs: sequence of dicts with the arguments of invert_frequency_set -
+    g, t, o, dtype, c_in, alpha0, freqs, p_meas, c_out, ws (each job its own
+    workspace).  Returns the update norms, one per job; raises on the first
+    job that failed (NumericError for RB_ENUMERIC, whose model is left
+    unchanged).  Synchronises the stream."""
+    n = len(jobs)
+    keep = []
+    arr = (RbSetJob * n)()
+    norms = (ctypes.c_double * n)()
+    status = (ctypes.c_int * n)()
+    for i, j in enumerate(jobs):
+        gs, ts = geometry_struct(j["g"]), trace_opts_struct(j["t"])
+        os_ = invert_opts_struct(j["o"], j["dtype"])
+        fa, nf = _freqs(j["freqs"])
+        keep += [gs, ts, os_, fa]
+        arr[i] = RbSetJob(ctypes.pointer(gs), ctypes.pointer(ts), ctypes.pointer(os_), _ptr(j["c_in"]),
+                          _ptr(j.get("alpha0")), ctypes.cast(fa, ctypes.POINTER(ctypes.c_double)), nf, _ptr(j["p_meas"]), _ptr(j["c_out"]),
+                          ctypes.cast(ctypes.byref(norms, i * ctypes.sizeof(ctypes.c_double)),
+                                      ctypes.POINTER(ctypes.c_double)),
+                          ctypes.cast(ctypes.byref(status, i * ctypes.sizeof(ctypes.c_int)),
+                                      ctypes.POINTER(ctypes.c_int)),
+                          _ptr(j["ws"]), j["ws"].numel())
+    _check(lib().rb_invert_frequency_sets_grouped(arr, n, _stream(stream)))
+    return [norms[i] for i in range(n)]
 
 
 def invert_cg_workspace_bytes(g, t, nf: int, dtype, emitter_batch: int = 0) -> int:

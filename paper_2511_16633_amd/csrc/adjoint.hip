@@ -339,14 +339,62 @@ __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&v
     }
 }
 
+// Where a workgroup's work lies: pixel tile loc.tile(), frequency loc.k().
+// A launch over one problem reads them from the grid (blockIdx), a grouped
+// launch from the problem table.
+struct GridLoc {
+    __device__ __forceinline__ int64_t tile() const { return blockIdx.x; }
+    __device__ __forceinline__ int k() const { return blockIdx.y; }
+};
+struct ItemLoc {
+    int64_t t;
+    int kf;
+    __device__ __forceinline__ int64_t tile() const { return t; }
+    __device__ __forceinline__ int k() const { return kf; }
+};
+
+// Kernel argument of a launch over one problem: grid (pixel tiles, frequencies).
+struct AdjOne {
+    using Loc = GridLoc;
+    AdjItem item;
+    __device__ __forceinline__ const AdjItem &locate(Loc &) const { return item; }
+};
+
+// Kernel argument of a launch over several problems: which problem a flat
+// workgroup id belongs to, and its (pixel tile, frequency) there.
+// Workgroup-uniform.
+struct AdjGroupArg {
+    using Loc = ItemLoc;
+    AdjGroup G;
+    __device__ __forceinline__ const AdjItem &locate(Loc &loc) const {
+        const int b = blockIdx.x;
+        int j = 0;
+        while (j + 1 < G.n && b >= G.item[j + 1].begin) ++j;
+        const AdjItem &it = G.item[j];
+        const int local = b - it.begin;
+        loc.kf = local / it.ntiles;
+        loc.t = local - loc.kf * it.ntiles;
+        return it;
+    }
+};
+
 // HESS = false computes the gradient only (three MFMAs per block and step);
-// its registers allow three workgroups per CU (34 KB of LDS each).
-template <bool HESS>
-__global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, const float *__restrict__ Gr,
-                                                        const float *__restrict__ Gi, const float *__restrict__ Ar,
-                                                        const float *__restrict__ Ai, const float *__restrict__ Wt,
-                                                        const uint8_t *__restrict__ flags, double *__restrict__ pg,
-                                                        double *__restrict__ ph) {
+// its registers allow three workgroups per CU (34 KB of LDS each).  The
+// argument is one problem (AdjOne: grid = pixel tiles x frequencies) or a
+// group of problems (AdjGroup: flat grid over every problem's work items).
+template <bool HESS, typename A>
+__global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(const A args) {
+    typename A::Loc loc;
+    const AdjItem &it = args.locate(loc);
+    const AdjParams &P = it.P;
+    const float *__restrict__ Gr = (const float *)it.Gr;
+    const float *__restrict__ Gi = (const float *)it.Gi;
+    const float *__restrict__ Ar = (const float *)it.Ar;
+    const float *__restrict__ Ai = (const float *)it.Ai;
+    const float *__restrict__ Wt = (const float *)it.Wt;
+    const uint8_t *__restrict__ flags = it.flags;
+    double *__restrict__ pg = it.pg;
+    double *__restrict__ ph = it.ph;
     __shared__ __align__(16) float sB[2][2 * kAdjTile];   // [buffer][re tile, im tile]
     __shared__ double sred[2][2][kAdjNT];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -354,7 +402,7 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
     const int row = lane & 15, kk = lane >> 4;
     const int we = wave >> 1, wp = wave & 1;
     const int64_t N = P.N;
-    const int64_t x0 = (int64_t)blockIdx.x * kAdjNT;
+    const int64_t x0 = (int64_t)loc.tile() * kAdjNT;
     const bool vec = ((N & 3) == 0) && (x0 + kAdjNT <= N);   // workgroup-uniform
     // this lane's column offsets in the swizzled tile (rows 4 s + kk)
     int coff[2];
@@ -364,7 +412,7 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
     double gacc[2] = {0.0, 0.0}, hacc[2] = {0.0, 0.0};
 
     {
-        const int k = blockIdx.y;   // one frequency per workgroup (finer work units)
+        const int k = loc.k();   // one frequency per workgroup (finer work units)
         const float *gr = Gr + (int64_t)k * P.m * N;
         const float *gi = Gi + (int64_t)k * P.m * N;
         const float *ar = Ar + (int64_t)k * P.mp * P.mp;
@@ -497,11 +545,12 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(AdjParams P, 
     if (tid < kAdjNT) {
         const int64_t x = x0 + tid;
         if (x < N) {
-            pg[(int64_t)blockIdx.y * N + x] = sred[0][0][tid] + sred[1][0][tid];
-            if (HESS) ph[(int64_t)blockIdx.y * N + x] = sred[0][1][tid] + sred[1][1][tid];
+            pg[(int64_t)loc.k() * N + x] = sred[0][0][tid] + sred[1][0][tid];
+            if (HESS) ph[(int64_t)loc.k() * N + x] = sred[0][1][tid] + sred[1][1][tid];
         }
     }
 }
+
 
 // ------------------------------------------------------------------ 16-bit, LDS-staged
 // Backprojection with 16-bit tables on the 16x16x32 matrix cores (FP32
@@ -637,14 +686,21 @@ __device__ __forceinline__ V a16_abs2(V br, V bi) {
 template <int I>
 using Idx = std::integral_constant<int, I>;
 
-template <typename S, bool HESS, int EB, int NW>
-__global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(AdjParams P, const S *__restrict__ Gr,
-                                                          const S *__restrict__ Gi, const S *__restrict__ Ar,
-                                                          const S *__restrict__ Ai, const S *__restrict__ Wt,
-                                                          const uint8_t *__restrict__ flags,
-                                                          const float *__restrict__ gscale,
-                                                          const float *__restrict__ ascale,
-                                                          double *__restrict__ pg, double *__restrict__ ph) {
+template <typename S, bool HESS, int EB, int NW, typename A>
+__global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(const A args) {
+    typename A::Loc loc;
+    const AdjItem &it = args.locate(loc);
+    const AdjParams &P = it.P;
+    const S *__restrict__ Gr = (const S *)it.Gr;
+    const S *__restrict__ Gi = (const S *)it.Gi;
+    const S *__restrict__ Ar = (const S *)it.Ar;
+    const S *__restrict__ Ai = (const S *)it.Ai;
+    const S *__restrict__ Wt = (const S *)it.Wt;
+    const uint8_t *__restrict__ flags = it.flags;
+    const float *__restrict__ gscale = it.gscale;
+    const float *__restrict__ ascale = it.ascale;
+    double *__restrict__ pg = it.pg;
+    double *__restrict__ ph = it.ph;
     using V = typename MM16<S>::vec;
     // Three tile buffers as separate LDS objects, always addressed by a
     // compile-time index: the compiler can then tell that a direct load into
@@ -660,8 +716,8 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row = lane & 15, kk = lane >> 4;
     const int64_t N = P.N;
-    const int k = blockIdx.y;
-    const int64_t x0 = (int64_t)blockIdx.x * kA16NT;
+    const int k = loc.k();
+    const int64_t x0 = (int64_t)loc.tile() * kA16NT;
     const bool vec = ((N & 1) == 0) && (x0 + kA16NT <= N) && (P.m % kA16KC == 0);   // workgroup-uniform
     const S *gre = Gr + (int64_t)k * P.m * N;
     const S *gim = Gi + (int64_t)k * P.m * N;
@@ -864,6 +920,7 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
     }
 }
 
+
 // grad += sum_k pg[k], hd += sum_k ph[k] in frequency order.
 __global__ void k_adj_sum(int64_t N, int nf, const double *__restrict__ pg, const double *__restrict__ ph,
                           double *__restrict__ grad, double *__restrict__ hd) {
@@ -929,9 +986,9 @@ size_t adjoint_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt) {
     return c.used + 256;
 }
 
-rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
-                       rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
-                       double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st) {
+rb_status adjoint_prepare(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                          rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
+                          double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st, AdjTask *task) {
     if (ws_bytes < adjoint_workspace_bytes(g, nf, dt)) {
         set_error("adjoint workspace too small: need %zu bytes", adjoint_workspace_bytes(g, nf, dt));
         return RB_ENOMEM;
@@ -966,53 +1023,146 @@ rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
     }
     RB_LAUNCHED();
-    switch (dt) {
+    AdjItem &it = task->item;
+    it.P = P;
+    it.Gr = G_re;
+    it.Gi = G_im;
+    it.Ar = w.Ar;
+    it.Ai = w.Ai;
+    it.Wt = w.Wt;
+    it.flags = w.flags;
+    it.gscale = gscale;
+    it.ascale = w.ascale;
+    it.pg = w.pg;
+    it.ph = w.ph;
+    it.ntiles = (int)blocks_for(P.N, dt == RB_F32 ? kAdjNT : kA16NT);
+    it.begin = 0;
+    task->dt = dt;
+    task->grad = grad;
+    task->hdiag = hdiag;
+    return RB_OK;
+}
+
+rb_status adjoint_run(const AdjTask &task, hipStream_t st) {
+    const AdjItem &it = task.item;
+    const AdjParams &P = it.P;
+    const int nf = P.nf;
+    double *grad = task.grad, *hdiag = task.hdiag;
+    switch (task.dt) {
         case RB_F64: {
             const unsigned nb = blocks_for(P.N, 64 * 2);
-            k_adjoint<double, 2, 2><<<nb, 256, 0, st>>>(P, (const double *)G_re, (const double *)G_im,
-                                                        (const double *)w.Ar, (const double *)w.Ai,
-                                                        (const double *)w.Wt, w.flags, grad, hdiag);
+            k_adjoint<double, 2, 2><<<nb, 256, 0, st>>>(P, (const double *)it.Gr, (const double *)it.Gi,
+                                                        (const double *)it.Ar, (const double *)it.Ai,
+                                                        (const double *)it.Wt, it.flags, grad, hdiag);
             break;
         }
         case RB_F32: {
             dim3 ga(blocks_for(P.N, kAdjNT), nf);
+            const AdjOne one{it};
             if (hdiag)
-                k_adjoint_f32<true><<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
-                                                        (const float *)w.Ar, (const float *)w.Ai,
-                                                        (const float *)w.Wt, w.flags, w.pg, w.ph);
+                k_adjoint_f32<true><<<ga, 256, 0, st>>>(one);
             else
-                k_adjoint_f32<false><<<ga, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
-                                                         (const float *)w.Ar, (const float *)w.Ai,
-                                                         (const float *)w.Wt, w.flags, w.pg, w.ph);
+                k_adjoint_f32<false><<<ga, 256, 0, st>>>(one);
             RB_LAUNCHED();
-            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.pg, it.ph, grad, hdiag);
             break;
         }
         case RB_BF16:
         case RB_F16: {
             dim3 ga(blocks_for(P.N, kA16NT), nf);
+            const AdjOne one{it};
             auto go = [&](auto tag) {
                 using S = decltype(tag);
-                const S *gr = (const S *)G_re, *gi = (const S *)G_im;
-                const S *ar = (const S *)w.Ar, *ai = (const S *)w.Ai, *wt = (const S *)w.Wt;
                 if (hdiag)
-                    k_adjoint16_lds<S, true, 2, 4><<<ga, 256, 0, st>>>(P, gr, gi, ar, ai, wt, w.flags, gscale,
-                                                                       w.ascale, w.pg, w.ph);
+                    k_adjoint16_lds<S, true, 2, 4><<<ga, 256, 0, st>>>(one);
                 else
-                    k_adjoint16_lds<S, false, 2, kA16GradWaves><<<ga, 64 * kA16GradWaves, 0, st>>>(
-                        P, gr, gi, ar, ai, wt, w.flags, gscale, w.ascale, w.pg, w.ph);
+                    k_adjoint16_lds<S, false, 2, kA16GradWaves><<<ga, 64 * kA16GradWaves, 0, st>>>(one);
             };
-            if (dt == RB_BF16)
+            if (task.dt == RB_BF16)
                 go(__hip_bfloat16());
             else
                 go(__half());
             RB_LAUNCHED();
-            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, w.pg, w.ph, grad, hdiag);
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.pg, it.ph, grad, hdiag);
             break;
         }
     }
     RB_LAUNCHED();
     return RB_OK;
+}
+
+rb_status adjoint_run_grouped(AdjTask *const *tasks, int n, hipStream_t st) {
+    // contraction type and variant of a task: f32 / bf16 / f16, with or
+    // without the Hessian diagonal; f64 runs alone
+    auto kind = [](const AdjTask &t) { return 2 * (int)t.dt + (t.hdiag ? 1 : 0); };
+    bool done[256] = {};
+    RB_CHECK_ARG(n >= 0 && n <= 256, "grouped backprojection: %d problems (at most 256)", n);
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        if (tasks[i]->dt == RB_F64) {
+            RB_TRY(adjoint_run(*tasks[i], st));
+            done[i] = true;
+            continue;
+        }
+        // up to kAdjGroupMax not-yet-run tasks of this kind, in order
+        AdjGroupArg arg;
+        AdjGroup &G = arg.G;
+        G.n = 0;
+        int idx[kAdjGroupMax];
+        int64_t blocks = 0;
+        for (int j = i; j < n && G.n < kAdjGroupMax; ++j) {
+            if (done[j] || kind(*tasks[j]) != kind(*tasks[i])) continue;
+            AdjItem it = tasks[j]->item;
+            it.begin = (int)blocks;
+            blocks += (int64_t)it.ntiles * it.P.nf;
+            G.item[G.n] = it;
+            idx[G.n++] = j;
+            done[j] = true;
+        }
+        RB_CHECK_ARG(blocks < (int64_t)1 << 31, "grouped backprojection: too many workgroups");
+        const bool hess = tasks[i]->hdiag != nullptr;
+        switch (tasks[i]->dt) {
+            case RB_F32:
+                if (hess)
+                    k_adjoint_f32<true><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                else
+                    k_adjoint_f32<false><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                break;
+            case RB_BF16:
+                if (hess)
+                    k_adjoint16_lds<__hip_bfloat16, true, 2, 4><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                else
+                    k_adjoint16_lds<__hip_bfloat16, false, 2, kA16GradWaves>
+                        <<<(unsigned)blocks, 64 * kA16GradWaves, 0, st>>>(arg);
+                break;
+            case RB_F16:
+                if (hess)
+                    k_adjoint16_lds<__half, true, 2, 4><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                else
+                    k_adjoint16_lds<__half, false, 2, kA16GradWaves>
+                        <<<(unsigned)blocks, 64 * kA16GradWaves, 0, st>>>(arg);
+                break;
+            default:
+                break;
+        }
+        RB_LAUNCHED();
+        for (int q = 0; q < G.n; ++q) {
+            const AdjTask &t = *tasks[idx[q]];
+            k_adj_sum<<<blocks_for(t.item.P.N, 256), 256, 0, st>>>(t.item.P.N, t.item.P.nf, t.item.pg, t.item.ph,
+                                                                   t.grad, t.hdiag);
+            RB_LAUNCHED();
+        }
+    }
+    return RB_OK;
+}
+
+rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                       rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
+                       double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st) {
+    AdjTask task;
+    RB_TRY(adjoint_prepare(g, G_re, G_im, gscale, dt, freqs, nf, d_res, w_data, grad, hdiag, ws, ws_bytes, st,
+                           &task));
+    return adjoint_run(task, st);
 }
 
 // ---------------------------------------------------------------- no-allocation variant

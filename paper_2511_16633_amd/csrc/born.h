@@ -12,6 +12,32 @@ struct AdjParams {
     double ch[RB_MAX_NF];  // omega^4 h^4
 };
 
+// One problem's backprojection as the contraction kernel sees it, for
+// launches that group several problems: its parameters, its tables and
+// prepared operands, its per-frequency partial sums, its pixel tiles per
+// frequency and its first flat workgroup in the launch.
+struct AdjItem {
+    AdjParams P;
+    const void *Gr, *Gi, *Ar, *Ai, *Wt;
+    const uint8_t *flags;
+    const float *gscale, *ascale;
+    double *pg, *ph;
+    int ntiles, begin;
+};
+constexpr int kAdjGroupMax = 8;   // problems per grouped launch (kernel-argument size)
+struct AdjGroup {
+    int n;
+    AdjItem item[kAdjGroupMax];
+};
+
+// A prepared backprojection (operands and block flags written on the
+// stream), ready for its contraction kernel alone or grouped with others.
+struct AdjTask {
+    AdjItem item;
+    rb_dtype dt;
+    double *grad, *hdiag;
+};
+
 struct FwdParams {
     int m, mp, nf, ntl, ntri, nsplit;
     int dmin;              // >= 32: diagonal 32 x 32 blocks need not be computed
@@ -26,6 +52,16 @@ size_t forward_workspace_bytes(const rb_geometry *g, int nf, rb_dtype dt);
 rb_status adjoint_impl(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
                        rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
                        double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st);
+// The same as adjoint_impl in two parts: the operand preparation, then the
+// contraction and the frequency sum.  adjoint_run_grouped runs the second
+// part of several prepared problems, with one contraction launch per
+// contraction type (up to kAdjGroupMax problems each); every problem's result
+// is bitwise that of adjoint_impl.  The f64 type is prepared and run alone.
+rb_status adjoint_prepare(const rb_geometry *g, const void *G_re, const void *G_im, const float *gscale,
+                          rb_dtype dt, const double *freqs, int nf, const double *d_res, const double *w_data,
+                          double *grad, double *hdiag, void *ws, size_t ws_bytes, hipStream_t st, AdjTask *task);
+rb_status adjoint_run(const AdjTask &task, hipStream_t st);
+rb_status adjoint_run_grouped(AdjTask *const *tasks, int n, hipStream_t st);
 // d_out = J delta, [nf][m][m] complex.  With dmin >= 32 (a caller that
 // weights every pair of circular index distance below dmin by zero) the
 // 32/16-bit kernels may return 0 for the pairs of a diagonal 32 x 32 block,

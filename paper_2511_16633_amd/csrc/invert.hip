@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "born.h"
 #include "common.h"
@@ -721,28 +722,59 @@ size_t invert_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t, int 
     return c.used + 256 + scratch_need(g, t, nf, dt, batch);
 }
 
-// cg_iters = 0: the single step; cg_iters >= 1: CG (cg_hist [host] may be
-// null); asym: the single step with the asymptotic weights (32/64-bit).
-rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o, const double *c_in,
-                      const double *alpha0, const double *freqs, int nf, const double *p_meas, int cg_iters,
-                      double *c_out, double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes, hipStream_t st,
-                      bool asym = false) {
+// Everything one call on one frequency set carries between its phases.
+struct SetCtx {
+    const rb_geometry *g;
+    const rb_trace_opts *t;
+    const rb_invert_opts *o;
+    const double *c_in, *alpha0, *freqs, *p_meas;
+    int nf;
+    double *c_out;
+    InvWs w;
+    void *scratch;
+    size_t scratch_bytes;
+    int dmin;
+    AdjTask adj;      // the single step's backprojection, prepared
+    double res[8];    // host copy of the set's scalars
+};
+
+// Workspace carve and size check.
+static rb_status set_open(SetCtx &S, const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,
+                          const double *c_in, const double *alpha0, const double *freqs, int nf,
+                          const double *p_meas, double *c_out, void *ws, size_t ws_bytes, bool cg, bool asym) {
+    S.g = g;
+    S.t = t;
+    S.o = o;
+    S.c_in = c_in;
+    S.alpha0 = alpha0;
+    S.freqs = freqs;
+    S.nf = nf;
+    S.p_meas = p_meas;
+    S.c_out = c_out;
     Carver c(ws, ws_bytes);
-    InvWs w = carve_inv(c, g, nf, o->dtype, cg_iters > 0, asym);
+    S.w = carve_inv(c, g, nf, o->dtype, cg, asym);
     if (c.used + 256 + trace_workspace_bytes(g, t, 1) > ws_bytes ||
         c.used + 256 + std::max(adjoint_workspace_bytes(g, nf, o->dtype),
                                 forward_workspace_bytes(g, nf, o->dtype)) > ws_bytes) {
         set_error("invert workspace too small (%zu bytes)", ws_bytes);
         return RB_ENOMEM;
     }
-    const size_t scratch_bytes = ws_bytes - c.used - 256;
-    void *scratch = reinterpret_cast<void *>(((uintptr_t)w.scratch + 255) & ~(uintptr_t)255);
-    const int64_t N = (int64_t)g->nx * g->ny;
-    const int m = g->m;
-    const int64_t mm = (int64_t)m * m;
+    S.scratch_bytes = ws_bytes - c.used - 256;
+    S.scratch = reinterpret_cast<void *>(((uintptr_t)S.w.scratch + 255) & ~(uintptr_t)255);
+    S.dmin = (int)std::ceil((1.0 - o->recv_fraction) * 0.5 * g->m - 1e-9);
+    return RB_OK;
+}
 
-    // 1. rays, tables and Green's functions in the current model
-    k_slowness<<<blocks_for(N, 256), 256, 0, st>>>(c_in, N, w.s);
+// 1-2. rays, tables and Green's functions in the current model; residual,
+// data weights and the list of zeroed pairs
+static rb_status set_linearise(SetCtx &S, hipStream_t st) {
+    const rb_geometry *g = S.g;
+    const rb_invert_opts *o = S.o;
+    InvWs &w = S.w;
+    const int64_t N = (int64_t)g->nx * g->ny;
+    const int m = g->m, nf = S.nf;
+    const int64_t mm = (int64_t)m * m;
+    k_slowness<<<blocks_for(N, 256), 256, 0, st>>>(S.c_in, N, w.s);
     RB_LAUNCHED();
     // support (step 4): inside the ring margin and covered by every emitter
     const double rs = g->ring_radius - g->support_margin;
@@ -751,31 +783,116 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
     rb_tables tab{w.T, w.amp, w.att, w.Trx, w.amp_rx, w.att_rx};
     if (o->dtype == RB_F32 || o->dtype == RB_F64) {
         // 32/64-bit G needs no global scale: the rasteriser writes it directly
-        GreenOut gout{green_params(freqs, nf, o->y_pow), o->dtype, w.Gr, w.Gi};
-        RB_TRY(trace_rays_impl(g, t, w.s, alpha0, &tab, scratch, scratch_bytes, st, w.S, &gout));
+        GreenOut gout{green_params(S.freqs, nf, o->y_pow), o->dtype, w.Gr, w.Gi};
+        RB_TRY(trace_rays_impl(g, S.t, w.s, S.alpha0, &tab, S.scratch, S.scratch_bytes, st, w.S, &gout));
         RB_TRY(fill_f32(w.gscale, 1.0f, nf, st));
     } else {
-        RB_TRY(trace_rays_impl(g, t, w.s, alpha0, &tab, scratch, scratch_bytes, st, w.S, nullptr));
-        Carver gc(scratch, scratch_bytes);
+        RB_TRY(trace_rays_impl(g, S.t, w.s, S.alpha0, &tab, S.scratch, S.scratch_bytes, st, w.S, nullptr));
+        Carver gc(S.scratch, S.scratch_bytes);
         float *amax = gc.take<float>(1);
         float *parts = gc.take<float>(kReduceBlocks);
-        RB_TRY(build_green_impl(w.T, w.amp, w.att, (int64_t)m * N, freqs, nf, o->y_pow, o->dtype, w.Gr, w.Gi,
+        RB_TRY(build_green_impl(w.T, w.amp, w.att, (int64_t)m * N, S.freqs, nf, o->y_pow, o->dtype, w.Gr, w.Gi,
                                 w.gscale, amax, parts, st));
     }
-    // 2. residual and data weights
-    GreenParams GP = green_params(freqs, nf, o->y_pow);
-    k_residual<<<blocks_for(mm * nf, 256), 256, 0, st>>>(GP, m, w.Trx, w.amp_rx, w.att_rx, p_meas, w.D);
+    GreenParams GP = green_params(S.freqs, nf, o->y_pow);
+    k_residual<<<blocks_for(mm * nf, 256), 256, 0, st>>>(GP, m, w.Trx, w.amp_rx, w.att_rx, S.p_meas, w.D);
     RB_LAUNCHED();
-    const int dmin = (int)std::ceil((1.0 - o->recv_fraction) * 0.5 * m - 1e-9);
-    const int64_t n_valid = (int64_t)m * selected_count(m, dmin);
+    const int64_t n_valid = (int64_t)m * selected_count(m, S.dmin);
     const int64_t kzero = (int64_t)std::floor(o->outlier_fraction * (double)n_valid);
-    k_weights<<<nf, kWThreads, 0, st>>>(m, dmin, kzero, p_meas, w.W);
+    k_weights<<<nf, kWThreads, 0, st>>>(m, S.dmin, kzero, S.p_meas, w.W);
     RB_LAUNCHED();
-    // 3. gradient and Hessian diagonal
     // the Hessian diagonal comes from the band structure of W: the
     // backprojection computes the gradient only
-    k_zero_list<<<nf, kWThreads, 0, st>>>(m, dmin, w.W, m * m, w.zl, w.nz);
+    k_zero_list<<<nf, kWThreads, 0, st>>>(m, S.dmin, w.W, m * m, w.zl, w.nz);
     RB_LAUNCHED();
+    return RB_OK;
+}
+
+// 6. update of 1/c^2 along res[2] * dir and the update norm; the set's
+// scalars are copied to S.res (the caller synchronises the stream)
+static rb_status set_update(SetCtx &S, const double *dir, hipStream_t st) {
+    const int64_t N = (int64_t)S.g->nx * S.g->ny;
+    InvWs &w = S.w;
+    k_update_partial<<<kRB, 256, 0, st>>>(N, S.c_in, w.s, dir, w.res, w.part);
+    RB_LAUNCHED();
+    k_update_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
+    RB_LAUNCHED();
+    k_update_write<<<blocks_for(N, 256), 256, 0, st>>>(N, S.c_in, w.s, dir, w.res, S.c_out);
+    RB_LAUNCHED();
+    RB_HIP(hipMemcpyAsync(S.res, w.res, sizeof(S.res), hipMemcpyDeviceToHost, st));
+    return RB_OK;
+}
+
+// After the stream has been synchronised: the update norm, or RB_ENUMERIC.
+static rb_status set_result(const SetCtx &S, double *dc_l2) {
+    if (S.res[4] != 0.0) {
+        if (dc_l2) *dc_l2 = 0.0;
+        set_error("1/c^2 + delta <= 0 at %.0f pixels; model left unchanged", S.res[4]);
+        return RB_ENUMERIC;
+    }
+    if (dc_l2) *dc_l2 = std::sqrt(S.res[3]);
+    return RB_OK;
+}
+
+// The single step before the backprojection's contraction: linearisation,
+// cleared gradient and Hessian diagonal, the backprojection's operands.
+static rb_status step_begin(SetCtx &S, hipStream_t st) {
+    RB_TRY(set_linearise(S, st));
+    const int64_t N = (int64_t)S.g->nx * S.g->ny;
+    InvWs &w = S.w;
+    RB_TRY(fill_f64(w.grad, 0.0, N, st));
+    RB_TRY(fill_f64(w.hd, 0.0, N, st));
+    return adjoint_prepare(S.g, w.Gr, w.Gi, w.gscale, S.o->dtype, S.freqs, S.nf, w.D, w.W, w.grad, nullptr,
+                           S.scratch, S.scratch_bytes, st, &S.adj);
+}
+
+// The single step after the backprojection: Hessian diagonal, direction,
+// exact step length, update.
+static rb_status step_end(SetCtx &S, hipStream_t st) {
+    const rb_geometry *g = S.g;
+    InvWs &w = S.w;
+    const int64_t N = (int64_t)g->nx * g->ny;
+    const int m = g->m;
+    const int64_t mm = (int64_t)m * m;
+    RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, S.o->dtype, S.freqs, S.nf, S.dmin,
+                             reinterpret_cast<int *>(w.zl), w.nz, m * m, w.hd, st));
+    RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
+    // 4. diagonally weighted direction on the support
+    k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, S.o->eps, w.v);
+    RB_LAUNCHED();
+    // 5. exact step length along v
+    RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, S.o->dtype, S.freqs, S.nf, w.v, w.Jv, S.scratch,
+                        S.scratch_bytes, st, S.dmin));
+    k_beta_partial<<<kRB, 256, 0, st>>>(mm * S.nf, w.W, w.Jv, w.D, w.part);
+    RB_LAUNCHED();
+    k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
+    RB_LAUNCHED();
+    return set_update(S, w.v, st);
+}
+
+// cg_iters = 0: the single step; cg_iters >= 1: CG (cg_hist [host] may be
+// null); asym: the single step with the asymptotic weights (32/64-bit).
+rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o, const double *c_in,
+                      const double *alpha0, const double *freqs, int nf, const double *p_meas, int cg_iters,
+                      double *c_out, double *dc_l2, double *cg_hist, void *ws, size_t ws_bytes, hipStream_t st,
+                      bool asym = false) {
+    SetCtx S;
+    RB_TRY(set_open(S, g, t, o, c_in, alpha0, freqs, nf, p_meas, c_out, ws, ws_bytes, cg_iters > 0, asym));
+    if (cg_iters == 0 && !asym) {
+        RB_TRY(step_begin(S, st));
+        RB_TRY(adjoint_run(S.adj, st));
+        RB_TRY(step_end(S, st));
+        RB_HIP(hipStreamSynchronize(st));
+        return set_result(S, dc_l2);
+    }
+    InvWs &w = S.w;
+    void *scratch = S.scratch;
+    const size_t scratch_bytes = S.scratch_bytes;
+    const int64_t N = (int64_t)g->nx * g->ny;
+    const int m = g->m;
+    const int64_t mm = (int64_t)m * m;
+    const int dmin = S.dmin;
+    RB_TRY(set_linearise(S, st));
     const double *delta_dir = w.v;  // the update is res[2] * delta_dir
     if (asym) {
         // 3-4. amplitude-normalised backprojection g_A and pair count n_A,
@@ -823,25 +940,14 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
         k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
         RB_LAUNCHED();
     } else {
-    RB_TRY(fill_f64(w.grad, 0.0, N, st));
-    RB_TRY(fill_f64(w.hd, 0.0, N, st));
-    RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.D, w.W, w.grad, nullptr, scratch,
-                        scratch_bytes, st));
-    RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin, reinterpret_cast<int *>(w.zl),
-                             w.nz, m * m, w.hd, st));
-    RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
-    if (cg_iters == 0) {
-        // 4. diagonally weighted direction on the support
-        k_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.v);
-        RB_LAUNCHED();
-        // 5. exact step length along v
-        RB_TRY(forward_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.v, w.Jv, scratch, scratch_bytes,
-                            st, dmin));
-        k_beta_partial<<<kRB, 256, 0, st>>>(mm * nf, w.W, w.Jv, w.D, w.part);
-        RB_LAUNCHED();
-        k_beta_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
-        RB_LAUNCHED();
-    } else {
+        // 3. gradient and Hessian diagonal
+        RB_TRY(fill_f64(w.grad, 0.0, N, st));
+        RB_TRY(fill_f64(w.hd, 0.0, N, st));
+        RB_TRY(adjoint_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, w.D, w.W, w.grad, nullptr, scratch,
+                            scratch_bytes, st));
+        RB_TRY(hessian_band_impl(g, w.Gr, w.Gi, w.gscale, o->dtype, freqs, nf, dmin,
+                                 reinterpret_cast<int *>(w.zl), w.nz, m * m, w.hd, st));
+        RB_TRY(reduce_max_f64(w.hd, w.S, N, w.part, w.hmax, st));
         // 4-5. preconditioned CG from delta = 0
         k_cg_start<<<kRB, 256, 0, st>>>(N, w.grad, w.hd, w.S, w.hmax, o->eps, w.x, w.r, w.z, w.p, w.part);
         RB_LAUNCHED();
@@ -870,26 +976,38 @@ rb_status invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb_inv
         RB_LAUNCHED();
         delta_dir = w.x;
     }
-    }
-    // 6. update of 1/c^2 and the update norm
-    k_update_partial<<<kRB, 256, 0, st>>>(N, c_in, w.s, delta_dir, w.res, w.part);
-    RB_LAUNCHED();
-    k_update_final<<<1, 256, 0, st>>>(w.part, kRB, w.res);
-    RB_LAUNCHED();
-    k_update_write<<<blocks_for(N, 256), 256, 0, st>>>(N, c_in, w.s, delta_dir, w.res, c_out);
-    RB_LAUNCHED();
-    double res[8];
-    RB_HIP(hipMemcpyAsync(res, w.res, sizeof(res), hipMemcpyDeviceToHost, st));
+    RB_TRY(set_update(S, delta_dir, st));
     if (cg_iters > 0 && cg_hist)
         RB_HIP(hipMemcpyAsync(cg_hist, w.hist, sizeof(double) * 2 * cg_iters, hipMemcpyDeviceToHost, st));
     RB_HIP(hipStreamSynchronize(st));
-    if (res[4] != 0.0) {
-        if (dc_l2) *dc_l2 = 0.0;
-        set_error("1/c^2 + delta <= 0 at %.0f pixels; model left unchanged", res[4]);
-        return RB_ENUMERIC;
+    return set_result(S, dc_l2);
+}
+
+// Single steps of several problems on one stream, their backprojections'
+// contractions in grouped launches.  status[j] receives each problem's
+// status; the call returns the first failure.
+rb_status invert_grouped(const rb_set_job *jobs, int n, hipStream_t st) {
+    std::vector<SetCtx> ctx(n);
+    std::vector<AdjTask *> tasks(n);
+    for (int j = 0; j < n; ++j) {
+        const rb_set_job &J = jobs[j];
+        RB_TRY(set_open(ctx[j], J.g, J.t, J.o, J.c_in, J.alpha0, J.freqs_hz, J.nf, J.p_meas, J.c_out, J.ws,
+                        J.ws_bytes, false, false));
     }
-    if (dc_l2) *dc_l2 = std::sqrt(res[3]);
-    return RB_OK;
+    for (int j = 0; j < n; ++j) {
+        RB_TRY(step_begin(ctx[j], st));
+        tasks[j] = &ctx[j].adj;
+    }
+    RB_TRY(adjoint_run_grouped(tasks.data(), n, st));
+    for (int j = 0; j < n; ++j) RB_TRY(step_end(ctx[j], st));
+    RB_HIP(hipStreamSynchronize(st));
+    rb_status first = RB_OK;
+    for (int j = 0; j < n; ++j) {
+        const rb_status sj = set_result(ctx[j], jobs[j].dc_l2);
+        if (jobs[j].status) *jobs[j].status = sj;
+        if (sj != RB_OK && first == RB_OK) first = sj;
+    }
+    return first;
 }
 
 }  // namespace rb
@@ -967,6 +1085,21 @@ rb_status rb_invert_frequency_set_cg(const rb_geometry *g, const rb_trace_opts *
     RB_CHECK_ARG(n_iter >= 1 && n_iter <= RB_MAX_CG_ITERS, "n_iter must be in [1, %d]", RB_MAX_CG_ITERS);
     return rb::invert_impl(g, t, o, c_in, alpha0, freqs_hz, nf, p_meas, n_iter, c_out, dc_l2, cg_hist, ws,
                            ws_bytes, rb::as_stream(stream));
+}
+
+rb_status rb_invert_frequency_sets_grouped(const rb_set_job *jobs, int32_t njobs, void *stream) {
+    rb::clear_error();
+    RB_CHECK_ARG(jobs != nullptr && njobs >= 1 && njobs <= RB_MAX_GROUP, "njobs must be in [1, %d]", RB_MAX_GROUP);
+    for (int j = 0; j < njobs; ++j) {
+        const rb_set_job &J = jobs[j];
+        if (J.status) *J.status = RB_OK;
+        const rb_status sj = check_invert_args(J.g, J.t, J.o, J.c_in, J.freqs_hz, J.nf, J.p_meas, J.c_out, J.ws);
+        if (sj != RB_OK) {
+            if (J.status) *J.status = sj;
+            return sj;
+        }
+    }
+    return rb::invert_grouped(jobs, njobs, rb::as_stream(stream));
 }
 
 }  // extern "C"

@@ -169,3 +169,16 @@ def test_misaligned_green_tables_are_rejected_on_host():
     rc = L.rb_born_adjoint_weighted(ctypes.byref(geometry_struct(g)), ok, bad, ok, 1, fa, nf, ok, ok, ok, None,
                                     ok, 1 << 30, None)
     assert rc == -1 and "16-byte" in L.rb_last_error().decode()
+
+
+def test_grouped_step_refuses_bad_counts():
+    """rb_invert_frequency_sets_grouped: no jobs, or too many, is RB_EINVAL
+    before any work (no GPU needed)."""
+    from paper_2511_16633_amd import _binding as Bd
+    L = rb.lib()
+    arr = (Bd.RbSetJob * 1)()
+    assert L.rb_invert_frequency_sets_grouped(arr, 0, None) == -1
+    assert L.rb_invert_frequency_sets_grouped(None, 1, None) == -1
+    assert L.rb_invert_frequency_sets_grouped(arr, 100000, None) == -1
+    # a job with NULL geometry is refused by the per-job checks
+    assert L.rb_invert_frequency_sets_grouped(arr, 1, None) == -1

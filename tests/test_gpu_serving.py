@@ -1,6 +1,7 @@
 """Serving loop on the GPU: jobs of different ring sizes and contraction
-types run concurrently on their own streams, and every result is
-bit-for-bit the one the job gives alone.  The mix holds a 16-bit job of the
+types are served together - the small rings in grouped rounds of the batch
+lane (their backprojections in shared launches), the large ring on its own
+stream - and every result is bit-for-bit the one the job gives alone.  The mix holds a 16-bit job of the
 large-ring class (1040 elements around a small grid, BF16 contractions with
 the 128 x 128-tile forward), whose served image is also checked against the
 FP64 oracle at equal accuracy (rel-L2 <= 1e-2, max |dc| <= 1 m/s)."""
@@ -62,6 +63,10 @@ def test_mixed_results_equal_alone(serving):
     mixed = _jobs(S)
     stats = srv.run(mixed, realtime=False)
     assert stats["errors"] == 0, [j.error for j in mixed]
+    print(f"[gpu-case] serving: {stats['grouped_rounds']} grouped rounds, up to {stats['max_jobs_per_round']} "
+          f"jobs per round", flush=True)
+    assert stats["grouped_rounds"] >= 8 and stats["max_jobs_per_round"] >= 2
+    assert stats["max_ring_sizes_per_round"] >= 2   # 64- and 256-element rings in one grouped launch
     for a, b in zip(alone, mixed):
         assert a.result is not None and b.result is not None
         assert np.array_equal(a.result, b.result), f"job {a.jid} differs alone and mixed"
