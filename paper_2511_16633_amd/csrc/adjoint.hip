@@ -345,12 +345,14 @@ __device__ __forceinline__ void adj_mma_steps(const f4 (&va)[2][2], const f4 (&v
 struct GridLoc {
     __device__ __forceinline__ int64_t tile() const { return blockIdx.x; }
     __device__ __forceinline__ int k() const { return blockIdx.y; }
+    __device__ __forceinline__ int group() const { return 0; }
 };
 struct ItemLoc {
     int64_t t;
-    int kf;
+    int kf, q;
     __device__ __forceinline__ int64_t tile() const { return t; }
     __device__ __forceinline__ int k() const { return kf; }
+    __device__ __forceinline__ int group() const { return q; }   // emitter-pass group
 };
 
 // Kernel argument of a launch over one problem: grid (pixel tiles, frequencies).
@@ -360,8 +362,24 @@ struct AdjOne {
     __device__ __forceinline__ const AdjItem &locate(Loc &) const { return item; }
 };
 
+// Kernel argument of a launch over one problem whose emitter passes are
+// split into item.npg groups: grid (pixel tiles x groups, frequencies), the
+// groups of a tile adjacent in logical order and, through the XCD remap, on
+// one XCD at about the same time, so that they share its G tiles in L2.
+struct AdjOneSplit {
+    using Loc = ItemLoc;
+    AdjItem item;
+    __device__ __forceinline__ const AdjItem &locate(Loc &loc) const {
+        const int64_t l = xcd_remap(blockIdx.x, gridDim.x);
+        loc.t = l / item.npg;
+        loc.q = (int)(l - loc.t * item.npg);
+        loc.kf = blockIdx.y;
+        return item;
+    }
+};
+
 // Kernel argument of a launch over several problems: which problem a flat
-// workgroup id belongs to, and its (pixel tile, frequency) there.
+// workgroup id belongs to, and its (frequency, pixel tile, group) there.
 // Workgroup-uniform.
 struct AdjGroupArg {
     using Loc = ItemLoc;
@@ -372,8 +390,11 @@ struct AdjGroupArg {
         while (j + 1 < G.n && b >= G.item[j + 1].begin) ++j;
         const AdjItem &it = G.item[j];
         const int local = b - it.begin;
-        loc.kf = local / it.ntiles;
-        loc.t = local - loc.kf * it.ntiles;
+        const int per = it.ntiles * it.npg;
+        loc.kf = local / per;
+        const int rem = local - loc.kf * per;
+        loc.t = rem / it.npg;
+        loc.q = rem - (int)loc.t * it.npg;
         return it;
     }
 };
@@ -737,7 +758,10 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
         return I == 0 ? sG0 : (I == 1 ? sG1 : sG2);
     };
 
-    for (int ec = 0; ec < P.mp; ec += 16 * EB * NW) {
+    // this workgroup's emitter passes: group loc.group() of it.npg
+    const int npass = (P.mp + NE - 1) / NE, npg = it.npg, qg = loc.group();
+    const int pass0 = qg * npass / npg, pass1 = (qg + 1) * npass / npg;
+    for (int ec = pass0 * NE; ec < pass1 * NE; ec += NE) {
         const int e0 = ec + 16 * EB * wave;
         f4 yr[EB][4], yn[EB][4], z[EB][4];
 #pragma unroll
@@ -914,20 +938,21 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
                 g += (double)sred[0][w][tid];
                 h += (double)sred[1][w][tid];
             }
-            pg[(int64_t)k * N + x] = g * (P.cg[k] * g2 * as);
-            if (HESS) ph[(int64_t)k * N + x] = h * (P.ch[k] * g2 * g2);
+            pg[((int64_t)k * npg + qg) * N + x] = g * (P.cg[k] * g2 * as);
+            if (HESS) ph[((int64_t)k * npg + qg) * N + x] = h * (P.ch[k] * g2 * g2);
         }
     }
 }
 
 
-// grad += sum_k pg[k], hd += sum_k ph[k] in frequency order.
-__global__ void k_adj_sum(int64_t N, int nf, const double *__restrict__ pg, const double *__restrict__ ph,
+// grad += sum_k sum_q pg[k][q], hd += sum_k sum_q ph[k][q] in frequency
+// order, then emitter-pass group order.
+__global__ void k_adj_sum(int64_t N, int nf, int npg, const double *__restrict__ pg, const double *__restrict__ ph,
                           double *__restrict__ grad, double *__restrict__ hd) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= N) return;
     double g = 0.0, h = 0.0;
-    for (int k = 0; k < nf; ++k) {
+    for (int k = 0; k < nf * npg; ++k) {
         g += pg[(int64_t)k * N + x];
         if (hd) h += ph[(int64_t)k * N + x];
     }
@@ -965,8 +990,21 @@ struct AdjWs {
     double *pg, *ph;  // per-frequency partials of the f32 backprojection
 };
 
+// Workgroups that split the emitter passes of one pixel tile: the 16-bit
+// kernel's passes of 128 emitters each go to a workgroup of their own once
+// there are four or more (large rings), so that a tile's G rows come from
+// HBM once and from L2 for the other passes; one workgroup per tile
+// otherwise.
+static int adj_groups(const rb_geometry *g, rb_dtype dt) {
+    if (dt != RB_BF16 && dt != RB_F16) return 1;
+    const int ne = 16 * 2 * 4;   // emitters per pass of k_adjoint16_lds
+    const int npass = (pad_m(g->m) + ne - 1) / ne;
+    return npass >= 4 ? npass : 1;
+}
+
 static AdjWs carve_adj(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
     const int mp = pad_m(g->m);
+    const size_t npg = (size_t)adj_groups(g, dt);
     const size_t per = (size_t)nf * mp * mp;
     const size_t es = dt == RB_F64 ? 8 : (dt == RB_F32 ? 4 : 2);
     AdjWs w;
@@ -975,8 +1013,8 @@ static AdjWs carve_adj(Carver &c, const rb_geometry *g, int nf, rb_dtype dt) {
     w.Wt = c.take<char>(per * es);
     w.flags = c.take<uint8_t>((size_t)nf * (mp / 16) * (mp / 16));
     w.ascale = c.take<float>(RB_MAX_NF);
-    w.pg = c.take<double>((size_t)nf * g->nx * g->ny);
-    w.ph = c.take<double>((size_t)nf * g->nx * g->ny);
+    w.pg = c.take<double>((size_t)nf * npg * g->nx * g->ny);
+    w.ph = c.take<double>((size_t)nf * npg * g->nx * g->ny);
     return w;
 }
 
@@ -1037,6 +1075,7 @@ rb_status adjoint_prepare(const rb_geometry *g, const void *G_re, const void *G_
     it.ph = w.ph;
     it.ntiles = (int)blocks_for(P.N, dt == RB_F32 ? kAdjNT : kA16NT);
     it.begin = 0;
+    it.npg = adj_groups(g, dt);
     task->dt = dt;
     task->grad = grad;
     task->hdiag = hdiag;
@@ -1064,13 +1103,13 @@ rb_status adjoint_run(const AdjTask &task, hipStream_t st) {
             else
                 k_adjoint_f32<false><<<ga, 256, 0, st>>>(one);
             RB_LAUNCHED();
-            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.pg, it.ph, grad, hdiag);
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, 1, it.pg, it.ph, grad, hdiag);
             break;
         }
         case RB_BF16:
         case RB_F16: {
-            dim3 ga(blocks_for(P.N, kA16NT), nf);
-            const AdjOne one{it};
+            dim3 ga((unsigned)it.ntiles * it.npg, nf);
+            const AdjOneSplit one{it};
             auto go = [&](auto tag) {
                 using S = decltype(tag);
                 if (hdiag)
@@ -1083,7 +1122,7 @@ rb_status adjoint_run(const AdjTask &task, hipStream_t st) {
             else
                 go(__half());
             RB_LAUNCHED();
-            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.pg, it.ph, grad, hdiag);
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.npg, it.pg, it.ph, grad, hdiag);
             break;
         }
     }
@@ -1114,7 +1153,7 @@ rb_status adjoint_run_grouped(AdjTask *const *tasks, int n, hipStream_t st) {
             if (done[j] || kind(*tasks[j]) != kind(*tasks[i])) continue;
             AdjItem it = tasks[j]->item;
             it.begin = (int)blocks;
-            blocks += (int64_t)it.ntiles * it.P.nf;
+            blocks += (int64_t)it.ntiles * it.npg * it.P.nf;
             G.item[G.n] = it;
             idx[G.n++] = j;
             done[j] = true;
@@ -1148,8 +1187,8 @@ rb_status adjoint_run_grouped(AdjTask *const *tasks, int n, hipStream_t st) {
         RB_LAUNCHED();
         for (int q = 0; q < G.n; ++q) {
             const AdjTask &t = *tasks[idx[q]];
-            k_adj_sum<<<blocks_for(t.item.P.N, 256), 256, 0, st>>>(t.item.P.N, t.item.P.nf, t.item.pg, t.item.ph,
-                                                                   t.grad, t.hdiag);
+            k_adj_sum<<<blocks_for(t.item.P.N, 256), 256, 0, st>>>(t.item.P.N, t.item.P.nf, t.item.npg, t.item.pg,
+                                                                   t.item.ph, t.grad, t.hdiag);
             RB_LAUNCHED();
         }
     }

@@ -15,7 +15,8 @@ struct AdjParams {
 // One problem's backprojection as the contraction kernel sees it, for
 // launches that group several problems: its parameters, its tables and
 // prepared operands, its per-frequency partial sums, its pixel tiles per
-// frequency and its first flat workgroup in the launch.
+// frequency, its first flat workgroup in the launch and how many workgroups
+// split the emitter passes of one pixel tile.
 struct AdjItem {
     AdjParams P;
     const void *Gr, *Gi, *Ar, *Ai, *Wt;
@@ -23,6 +24,7 @@ struct AdjItem {
     const float *gscale, *ascale;
     double *pg, *ph;
     int ntiles, begin;
+    int npg;   // emitter-pass groups per pixel tile, each a workgroup of its own (partials [nf][npg][N])
 };
 constexpr int kAdjGroupMax = 8;   // problems per grouped launch (kernel-argument size)
 struct AdjGroup {

@@ -39,6 +39,10 @@ struct HbParams {
 // precision of the matrix-core path).  Group q loads receivers
 // r = q (mod groups) and takes emitters [m q / groups, m (q + 1) / groups);
 // partial sums are combined in group order, so the result is deterministic.
+// The zeroed pairs pass through LDS in chunks of 2 NT, packed as
+// e << 16 | r (0xffffffff for an entry out of range), double-buffered: each
+// thread loads its two entries of the next chunk into registers while the
+// block works on the current one, one barrier per chunk.
 template <typename T, typename L, int PB, int NT = kHbThreads>
 __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restrict__ Gr,
                                                           const T *__restrict__ Gi, const float *__restrict__ gscale,
@@ -48,7 +52,8 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
     extern __shared__ __align__(16) unsigned char lds_raw[];
     L *sg = reinterpret_cast<L *>(lds_raw);   // [m][PB]
     __shared__ L spart[NT];
-    __shared__ int2 sz[NT];                   // a chunk of the zeroed-pair list
+    constexpr int ZC = 2 * NT;                // zeroed pairs per chunk
+    __shared__ unsigned sz[2][ZC];            // two chunks of the zeroed-pair list, packed
     const int m = P.m;
     const int t = threadIdx.x;
     const int px = t % PB, grp = t / PB;
@@ -114,13 +119,29 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
                 }
             }
         }
-        // zeroed pairs, staged through LDS a chunk at a time
+        // zeroed pairs, staged through LDS two chunks at a time
         const int nz = nzero ? min(nzero[k], P.zcap) : 0;   // block-uniform
-        for (int c0 = 0; c0 < nz; c0 += NT) {
-            __syncthreads();   // the previous chunk has been read
-            if (c0 + t < nz) sz[t] = zeroed[(int64_t)k * P.zcap + c0 + t];
-            __syncthreads();
-            const int cn = min(NT, nz - c0);
+        const int2 *zk = zeroed + (int64_t)k * P.zcap;
+        auto fetch = [&](int c0, unsigned (&reg)[2]) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = c0 + h * NT + t;
+                reg[h] = 0xffffffffu;
+                if (i < nz) {
+                    const int2 q = zk[i];
+                    if ((unsigned)q.x < (unsigned)m && (unsigned)q.y < (unsigned)m)
+                        reg[h] = ((unsigned)q.x << 16) | (unsigned)q.y;
+                }
+            }
+        };
+        unsigned zr[2];
+        if (nz > 0) fetch(0, zr);
+        for (int c0 = 0, b = 0; c0 < nz; c0 += ZC, b ^= 1) {
+            sz[b][t] = zr[0];
+            sz[b][NT + t] = zr[1];
+            __syncthreads();   // chunk b is in LDS; the chunk read two rounds ago is done
+            if (c0 + ZC < nz) fetch(c0 + ZC, zr);   // in flight while chunk b is summed
+            const int cn = min(ZC, nz - c0);
             for (int i0 = grp; i0 < cn; i0 += 8 * NG) {
                 L pr[8];
 #pragma unroll
@@ -128,9 +149,8 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
                     const int i = i0 + u * NG;
                     pr[u] = 0;
                     if (i < cn) {
-                        const int2 q = sz[i];
-                        if ((unsigned)q.x < (unsigned)m && (unsigned)q.y < (unsigned)m)
-                            pr[u] = col[q.x * PB] * col[q.y * PB];
+                        const unsigned q = sz[b][i];
+                        if (q != 0xffffffffu) pr[u] = col[(int)(q >> 16) * PB] * col[(int)(q & 0xffffu) * PB];
                     }
                 }
 #pragma unroll
