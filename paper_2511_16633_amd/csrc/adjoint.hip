@@ -358,6 +358,7 @@ struct ItemLoc {
 // Kernel argument of a launch over one problem: grid (pixel tiles, frequencies).
 struct AdjOne {
     using Loc = GridLoc;
+    static constexpr bool kSplit = false;   // one workgroup per (pixel tile, frequency)
     AdjItem item;
     __device__ __forceinline__ const AdjItem &locate(Loc &) const { return item; }
 };
@@ -368,6 +369,7 @@ struct AdjOne {
 // one XCD at about the same time, so that they share its G tiles in L2.
 struct AdjOneSplit {
     using Loc = ItemLoc;
+    static constexpr bool kSplit = true;
     AdjItem item;
     __device__ __forceinline__ const AdjItem &locate(Loc &loc) const {
         const int64_t l = xcd_remap(blockIdx.x, gridDim.x);
@@ -383,6 +385,7 @@ struct AdjOneSplit {
 // Workgroup-uniform.
 struct AdjGroupArg {
     using Loc = ItemLoc;
+    static constexpr bool kSplit = true;
     AdjGroup G;
     __device__ __forceinline__ const AdjItem &locate(Loc &loc) const {
         const int b = blockIdx.x;
@@ -431,6 +434,10 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(const A args)
     for (int cb = 0; cb < 2; ++cb) coff[cb] = adj_off(kk, 32 * wp + 16 * cb + row) - kk * 64;
     const int nch = P.mp / kAdjKC;
     double gacc[2] = {0.0, 0.0}, hacc[2] = {0.0, 0.0};
+    // this workgroup's emitter passes (64 emitters each): group qg of npg
+    const int npg = A::kSplit ? it.npg : 1, qg = A::kSplit ? loc.group() : 0;
+    const int npass = P.mp / 64 + ((P.mp & 63) ? 1 : 0);
+    const int pass0 = A::kSplit ? qg * npass / npg : 0, pass1 = A::kSplit ? (qg + 1) * npass / npg : npass;
 
     {
         const int k = loc.k();   // one frequency per workgroup (finer work units)
@@ -441,7 +448,7 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(const A args)
         const float *wt = Wt + (int64_t)k * P.mp * P.mp;
         const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
         float gp[2] = {0.0f, 0.0f}, hp[2] = {0.0f, 0.0f};
-        for (int ec = 0; ec < P.mp; ec += 64) {
+        for (int ec = 64 * pass0; ec < 64 * pass1; ec += 64) {
             f4 p1[2][2], p2[2][2], p3[2][2], z[2][2];
 #pragma unroll
             for (int b = 0; b < 2; ++b)
@@ -566,8 +573,8 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(const A args)
     if (tid < kAdjNT) {
         const int64_t x = x0 + tid;
         if (x < N) {
-            pg[(int64_t)loc.k() * N + x] = sred[0][0][tid] + sred[1][0][tid];
-            if (HESS) ph[(int64_t)loc.k() * N + x] = sred[0][1][tid] + sred[1][1][tid];
+            pg[((int64_t)loc.k() * npg + qg) * N + x] = sred[0][0][tid] + sred[1][0][tid];
+            if (HESS) ph[((int64_t)loc.k() * npg + qg) * N + x] = sred[0][1][tid] + sred[1][1][tid];
         }
     }
 }
@@ -990,12 +997,20 @@ struct AdjWs {
     double *pg, *ph;  // per-frequency partials of the f32 backprojection
 };
 
-// Workgroups that split the emitter passes of one pixel tile: the 16-bit
-// kernel's passes of 128 emitters each go to a workgroup of their own once
-// there are four or more (large rings), so that a tile's G rows come from
-// HBM once and from L2 for the other passes; one workgroup per tile
-// otherwise.
+// Workgroups that split the emitter passes of one pixel tile: every pass
+// (64 emitters in the FP32 kernel, 128 in the 16-bit one) goes to a
+// workgroup of its own once there are four or more, the passes of a tile
+// adjacent in logical order and on one XCD (AdjOneSplit), so that the
+// tile's G rows come from HBM once and from L2 for the other passes (FP32,
+// 1024 elements / 1100^2: 221.6 -> 209.6 ms per 4-frequency launch; 16-bit:
+// 51.9 -> 47.6 ms).  Ordering the split workgroups pass-major instead (all
+// workgroups in flight on one pass, sharing its W.D rows) was slower: 224.7
+// and 60.0 ms.  One workgroup per tile otherwise.
 static int adj_groups(const rb_geometry *g, rb_dtype dt) {
+    if (dt == RB_F32) {
+        const int npass = (pad_m(g->m) + 63) / 64;   // 64 emitters per pass of k_adjoint_f32
+        return npass >= 4 ? npass : 1;
+    }
     if (dt != RB_BF16 && dt != RB_F16) return 1;
     const int ne = 16 * 2 * 4;   // emitters per pass of k_adjoint16_lds
     const int npass = (pad_m(g->m) + ne - 1) / ne;
@@ -1096,14 +1111,23 @@ rb_status adjoint_run(const AdjTask &task, hipStream_t st) {
             break;
         }
         case RB_F32: {
-            dim3 ga(blocks_for(P.N, kAdjNT), nf);
-            const AdjOne one{it};
-            if (hdiag)
-                k_adjoint_f32<true><<<ga, 256, 0, st>>>(one);
-            else
-                k_adjoint_f32<false><<<ga, 256, 0, st>>>(one);
+            if (it.npg == 1) {
+                dim3 ga(blocks_for(P.N, kAdjNT), nf);
+                const AdjOne one{it};
+                if (hdiag)
+                    k_adjoint_f32<true><<<ga, 256, 0, st>>>(one);
+                else
+                    k_adjoint_f32<false><<<ga, 256, 0, st>>>(one);
+            } else {
+                dim3 ga((unsigned)it.ntiles * it.npg, nf);
+                const AdjOneSplit one{it};
+                if (hdiag)
+                    k_adjoint_f32<true><<<ga, 256, 0, st>>>(one);
+                else
+                    k_adjoint_f32<false><<<ga, 256, 0, st>>>(one);
+            }
             RB_LAUNCHED();
-            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, 1, it.pg, it.ph, grad, hdiag);
+            k_adj_sum<<<blocks_for(P.N, 256), 256, 0, st>>>(P.N, nf, it.npg, it.pg, it.ph, grad, hdiag);
             break;
         }
         case RB_BF16:
