@@ -106,8 +106,8 @@ typedef struct {
 
 /*
  * Ray tracing and ray-to-grid tables (Forward Problem: Eqs. 4-7; Discussion:
- * "ray tracing", "amplitude computation", "back-propagation of ray
- * parameters").
+ * the three stages of tracing the rays, computing their amplitudes and
+ * carrying the ray parameters back onto the grid).
  *
  * For every emitter e, a fan of n_rays rays is launched into the inward
  * half-plane (angles theta_e + pi + (j + 1/2 - n_rays/2) pi / n_rays) with

@@ -22,8 +22,8 @@
  *         A_geom = sqrt(c(x) / (8 pi omega J)),  J = |dx/dpsi| at fixed tau;
  *     the omega^(-1/2) factor is applied when G is formed, this file
  *     stores a = sqrt(c / (8 pi max(J, j_min))).
- * The ray-to-grid step ("back-propagation of ray parameters", Discussion)
- * is done on the wavefront mesh: cell (j, n) spans rays j, j+1 and nodes
+ * The ray-to-grid step (the Discussion's carrying of the ray parameters back
+ * onto the grid) is done on the wavefront mesh: cell (j, n) spans rays j, j+1 and nodes
  * n, n+1 and is split into the triangles (P[n][j], P[n][j+1], P[n+1][j+1])
  * and (P[n][j], P[n+1][j+1], P[n+1][j]); a point inside a triangle takes
  * the barycentric interpolation of T, a and B; over all covering triangles

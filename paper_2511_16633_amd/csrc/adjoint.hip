@@ -952,6 +952,376 @@ __global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(
 }
 
 
+// ------------------------------------------------------------------------
+// 16-bit backprojection with transposing LDS reads.
+//
+// Workgroup tile: 128 emitters (a pass; 32 per wave) x 128 pixels, the
+// receivers streamed in k-steps of 32.  The G tile of a step (32 receiver
+// rows x 128 pixels, both arrays, 16 KB) is copied into LDS by 16-byte direct
+// global->LDS loads (one instruction fills four rows), two steps ahead, into
+// four buffers.  MFMA B fragments need eight consecutive receivers of one
+// pixel per lane; ds_read_b64_tr_b16 delivers four of them from a
+// pixel-major tile (within each 16-lane group, lane i receives the i-th
+// 16-bit element of the 4 x 8-byte rows its group addressed), so two
+// transposing reads give a fragment with no register permutes.  The
+// 16-byte chunks of each tile row are XOR-swizzled so that the eight rows
+// one half-wave reads together lie on distinct banks; the direct loads
+// realise the swizzle by choosing which global chunk each lane fetches.
+// A fragments (eight receivers of one emitter) come from L2 as 16-byte
+// loads, one step ahead.
+//
+// The k-steps of a pass run in rotated order, the pass's own emitter rows
+// last: those tiles are then still in the four buffers when the loop ends,
+// and the epilogue takes G_e from them with the same transposing read (four
+// emitters of one pixel per lane), without reading G again.
+constexpr int kT16NT = 128;                   // pixels per tile
+constexpr int kT16KC = 32;                    // receivers per k-step
+constexpr int kT16Row = 2 * kT16NT;           // bytes per tile row
+constexpr int kT16Arr = kT16KC * kT16Row;     // bytes of one array of a tile
+constexpr int kT16NE = 128;                   // emitters per pass (4 waves x 32)
+
+typedef short t16v4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) t16v4 t16lds_v4;
+
+// chunk position of 16-byte chunk c in tile row r: c XOR 2 g(r), where g
+// numbers the rows {0..3, 8..11} (and their shifts by 4 and 16) 0..7
+__device__ __forceinline__ int t16_pos(int r, int c) { return c ^ (2 * ((r & 3) | (((r >> 3) & 1) << 2))); }
+// byte offset of (tile row r, pixel px) in one array
+__device__ __forceinline__ int t16_off(int r, int px) {
+    return r * kT16Row + (t16_pos(r, px >> 3) << 4) + ((px & 7) << 1);
+}
+
+// Transposing read: lane (group kk, index i) of the wave addresses row
+// r0 + (i >> 2), pixels 4 (i & 3) .. + 3 of a 16-pixel column block; it gets
+// rows r0 .. r0 + 3 of pixel (i) of the block.
+__device__ __forceinline__ t16v4 t16_tr(const unsigned char *p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((t16lds_v4 *)(p));
+}
+
+template <typename V>
+__device__ __forceinline__ V t16_join(t16v4 lo, t16v4 hi) {
+    typedef short s8v __attribute__((ext_vector_type(8)));
+    const s8v v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(V, v);
+}
+
+// Aligned full tiles (N a multiple of 8, m a multiple of 32): wave w issues
+// instructions q = 4 w .. 4 w + 3 of the tile's 16 (array q >> 3, rows
+// 4 (q & 7) .. + 3); `goff[j]` is lane l's element offset from the step's
+// first row and pixel for its j-th instruction.
+__device__ __forceinline__ void t16_stage_async(const unsigned short *__restrict__ gr,
+                                                const unsigned short *__restrict__ gi, const int64_t (&goff)[4],
+                                                unsigned char *sT) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned short *g = (wave >> 1) ? gi : gr;
+    unsigned char *d = sT + (wave >> 1) * kT16Arr + (wave & 1) * 4 * 4 * kT16Row;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        __builtin_amdgcn_global_load_lds(g + goff[j], (lds_void_t *)(d + j * 4 * kT16Row), 16, 0, 0);
+}
+
+// Ragged or unaligned tiles: through registers, zero beyond m and N; each
+// thread writes four 16-byte chunks.
+__device__ __forceinline__ void t16_stage_regs(const unsigned short *__restrict__ gr,
+                                               const unsigned short *__restrict__ gi, int m, int64_t N, int rc,
+                                               int64_t x0, unsigned char *sT) {
+#pragma unroll 1
+    for (int q = threadIdx.x; q < 2 * kT16KC * 16; q += 256) {
+        const int arr = q >> 9, rl = (q >> 4) & 31, pos = q & 15;
+        const int c = pos ^ (t16_pos(rl, 0));   // the global chunk stored at `pos`
+        const unsigned short *g = arr ? gi : gr;
+        const int r = rc + rl;
+        unsigned short v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t x = x0 + 8 * c + u;
+            v[u] = (r < m && x < N) ? g[(int64_t)r * N + x] : (unsigned short)0;
+        }
+        unsigned short *d = reinterpret_cast<unsigned short *>(sT + arr * kT16Arr + rl * kT16Row + pos * 16);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = v[u];
+    }
+}
+
+template <typename S, bool HESS, typename A>
+__global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args) {
+    typename A::Loc loc;
+    const AdjItem &it = args.locate(loc);
+    const AdjParams &P = it.P;
+    const S *__restrict__ Ar = (const S *)it.Ar;
+    const S *__restrict__ Ai = (const S *)it.Ai;
+    const S *__restrict__ Wt = (const S *)it.Wt;
+    const uint8_t *__restrict__ flags = it.flags;
+    const float *__restrict__ gscale = it.gscale;
+    const float *__restrict__ ascale = it.ascale;
+    double *__restrict__ pg = it.pg;
+    double *__restrict__ ph = it.ph;
+    using V = typename MM16<S>::vec;
+    constexpr int EB = 2;   // 16-row emitter blocks per wave
+    // four tile buffers as separate LDS objects, addressed by compile-time
+    // index inside the k-loop: a direct load into one is then known not to
+    // write the one being read
+    __shared__ __align__(16) unsigned char sG0[2 * kT16Arr];
+    __shared__ __align__(16) unsigned char sG1[2 * kT16Arr];
+    __shared__ __align__(16) unsigned char sG2[2 * kT16Arr];
+    __shared__ __align__(16) unsigned char sG3[2 * kT16Arr];
+    __shared__ float sred[2][4][kT16NT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int64_t N = P.N;
+    const int k = loc.k();
+    const int64_t x0 = (int64_t)loc.tile() * kT16NT;
+    const unsigned short *gr = reinterpret_cast<const unsigned short *>((const S *)it.Gr + (int64_t)k * P.m * N);
+    const unsigned short *gi = reinterpret_cast<const unsigned short *>((const S *)it.Gi + (int64_t)k * P.m * N);
+    const bool vec = ((N & 7) == 0) && (x0 + kT16NT <= N) && (P.m % kT16KC == 0) &&
+                     ((((uintptr_t)gr) | ((uintptr_t)gi)) & 15) == 0;   // workgroup-uniform
+    const S *ar = Ar + (int64_t)k * P.mp * P.mp;
+    const S *ai = Ai + (int64_t)k * P.mp * P.mp;
+    const S *wt = Wt + (int64_t)k * P.mp * P.mp;
+    const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
+    const int nch = P.mp / kT16KC;
+    // lane's element offsets of its four direct-load chunks within a step
+    int64_t goff[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int rl = 4 * (4 * (wave & 1) + j) + (lane >> 4);
+        goff[j] = (int64_t)rl * N + x0 + 8 * ((lane & 15) ^ (t16_pos(rl, 0)));
+    }
+    // transposing-read offsets: rows 8 kk + 4 h + (row >> 2), pixels
+    // 16 cb + 4 (row & 3) (h = 0, 1; cb = 0 .. 7)
+    int toff[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int cb = 0; cb < 8; ++cb) toff[h][cb] = t16_off(8 * kk + 4 * h + (row >> 2), 16 * cb + 4 * (row & 3));
+    float gp[8], hp[8];
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) gp[cb] = hp[cb] = 0.0f;
+    auto buf = [&](auto itag) -> unsigned char * {
+        constexpr int I = decltype(itag)::value & 3;
+        return I == 0 ? sG0 : (I == 1 ? sG1 : (I == 2 ? sG2 : sG3));
+    };
+
+    const int npass = (P.mp + kT16NE - 1) / kT16NE, npg = it.npg, qg = loc.group();
+    const int pass0 = qg * npass / npg, pass1 = (qg + 1) * npass / npg;
+    for (int ec = pass0 * kT16NE; ec < pass1 * kT16NE; ec += kT16NE) {
+        const int e0 = ec + 32 * wave;
+        // the pass's emitter chunks [ce0, ce1) come last
+        const int ce0 = ec / kT16KC, ce1 = min(ce0 + kT16NE / kT16KC, nch);
+        const int nlead = nch - (ce1 - ce0);
+        auto chunk = [&](int s) { return s < nlead ? (s < nch - ce1 ? ce1 + s : s - (nch - ce1)) : ce0 + (s - nlead); };
+        f4 yr[EB][8], yn[EB][8], z[EB][8];
+#pragma unroll
+        for (int b = 0; b < EB; ++b)
+#pragma unroll
+            for (int cb = 0; cb < 8; ++cb) yr[b][cb] = yn[b][cb] = z[b][cb] = f4{0, 0, 0, 0};
+        unsigned aoff[EB];
+#pragma unroll
+        for (int b = 0; b < EB; ++b) aoff[b] = (unsigned)(min(e0 + 16 * b + row, P.mp - 1) * P.mp + 8 * kk);
+        auto load_a = [&](int c, V (&va)[EB], V (&vi)[EB], V (&vw)[EB]) {
+            const int co = c * kT16KC;   // uniform
+#pragma unroll
+            for (int b = 0; b < EB; ++b) {
+                va[b] = *reinterpret_cast<const V *>(ar + co + aoff[b]);
+                vi[b] = *reinterpret_cast<const V *>(ai + co + aoff[b]);
+                if (HESS) vw[b] = *reinterpret_cast<const V *>(wt + co + aoff[b]);
+            }
+        };
+        // chunks in which a 16-row block of this wave has a nonzero weight
+        uint64_t cm[2] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < EB; ++b)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int eb = (e0 >> 4) + b, c = 64 * hh + lane;
+                const bool on =
+                    eb < P.nb && c < nch && (fl[eb * P.nb + 2 * c] | fl[eb * P.nb + 2 * c + 1]) != 0;
+                cm[hh] |= __ballot(on);
+            }
+        auto stage = [&](int c, unsigned char *dst, auto vtag) {
+            if (decltype(vtag)::value)
+                t16_stage_async(gr + (int64_t)c * kT16KC * N, gi + (int64_t)c * kT16KC * N, goff, dst);
+            else
+                t16_stage_regs(gr, gi, P.m, N, c * kT16KC, x0, dst);
+        };
+        // One k-step s (chunk c = chunk(s)) on the tile in buffer s mod 4:
+        // wait for its tile and A(c), issue A(next) and the tile of step
+        // s + 2, then the MFMAs.  Per step a wave issues A(s + 1) (2 EB or
+        // 3 EB loads) and then the tile of s + 2 (4 direct loads), so at the
+        // wait only the tile of s + 1 may still be in flight.  `mode` says
+        // what the step issues when that is known at compile time (3: A and
+        // a tile, 2: A only, 1: nothing; 0: decided from s at run time), so
+        // that the compiler's own load-counter waits stay exact.
+        auto kstep = [&](int s, auto itag, V (&va)[EB], V (&vi)[EB], V (&vw)[EB], V (&na)[EB], V (&ni)[EB],
+                         V (&nw)[EB], auto vtag, auto mode) {
+            constexpr int I = decltype(itag)::value;
+            constexpr int M = decltype(mode)::value;
+            const bool has_a = M == 3 || M == 2 || (M == 0 && s + 1 < nch);
+            const bool has_t = M == 3 || (M == 0 && s + 2 < nch);
+            if (has_a)
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(4));   // tile s + 1
+            else
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            lds_barrier();
+            const int c = chunk(s);
+            if (has_a) load_a(chunk(s + 1), na, ni, nw);
+            __builtin_amdgcn_sched_barrier(0);
+            if (has_t) stage(chunk(s + 2), buf(Idx<I + 2>()), vtag);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!(((c < 64 ? cm[0] : cm[1]) >> (c & 63)) & 1)) return;
+            const unsigned char *sb = buf(Idx<I>());
+            V nva[EB];
+#pragma unroll
+            for (int b = 0; b < EB; ++b) nva[b] = neg(vi[b]);
+            // B fragments one column block ahead of the MFMAs that use them
+            t16v4 f[2][4];
+            auto frag = [&](int cb, t16v4 (&d)[4]) {
+                d[0] = t16_tr(sb + toff[0][cb]);
+                d[1] = t16_tr(sb + toff[1][cb]);
+                d[2] = t16_tr(sb + kT16Arr + toff[0][cb]);
+                d[3] = t16_tr(sb + kT16Arr + toff[1][cb]);
+            };
+            frag(0, f[0]);
+#pragma unroll
+            for (int cb = 0; cb < 8; ++cb) {
+                if (cb + 1 < 8) frag(cb + 1, f[(cb + 1) & 1]);
+                const V br = t16_join<V>(f[cb & 1][0], f[cb & 1][1]);
+                const V bi = t16_join<V>(f[cb & 1][2], f[cb & 1][3]);
+                V b2;
+                if (HESS) b2 = a16_abs2<S, V>(br, bi);
+#pragma unroll
+                for (int b = 0; b < EB; ++b) {
+                    yr[b][cb] = MM16<S>::mma(va[b], br, yr[b][cb]);
+                    yr[b][cb] = MM16<S>::mma(vi[b], bi, yr[b][cb]);
+                    yn[b][cb] = MM16<S>::mma(va[b], bi, yn[b][cb]);
+                    yn[b][cb] = MM16<S>::mma(nva[b], br, yn[b][cb]);
+                    if (HESS) z[b][cb] = MM16<S>::mma(vw[b], b2, z[b][cb]);
+                }
+            }
+        };
+        // the k-loop, specialised on the staging path and unrolled by eight
+        // (buffer index period 4, A registers period 2); when four steps
+        // remain (nch a multiple of 4) the last ones are compile-time too,
+        // otherwise the last one to five steps decide at run time
+        auto kloop = [&](auto vtag) {
+            using M3 = std::integral_constant<int, 3>;
+            using M2 = std::integral_constant<int, 2>;
+            using M1 = std::integral_constant<int, 1>;
+            using M0 = std::integral_constant<int, 0>;
+            V va[EB], vi[EB], vw[EB], na[EB], ni[EB], nw[EB];
+            lds_barrier();   // the previous pass is done with the tile buffers
+            stage(chunk(0), sG0, vtag);
+            load_a(chunk(0), va, vi, vw);
+            if (nch > 1) stage(chunk(1), sG1, vtag);
+            int s = 0;
+            for (; s + 12 <= nch; s += 8) {
+                kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 7, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
+            }
+            if (s + 8 == nch) {
+                kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M2());
+                kstep(s + 7, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M1());
+            } else if (s + 4 == nch) {
+                kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M2());
+                kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M1());
+            } else {
+                if (s + 8 <= nch) {
+                    kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
+                    kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
+                    kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
+                    kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
+                    s += 4;
+                }
+                if (s < nch) kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
+                if (s + 1 < nch) kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M0());
+                if (s + 2 < nch) kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M0());
+                if (s + 3 < nch) kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M0());
+                if (s + 4 < nch) kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
+                if (s + 5 < nch) kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M0());
+                if (s + 6 < nch) kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M0());
+            }
+        };
+        if (vec)
+            kloop(std::true_type());
+        else
+            kloop(std::false_type());
+        // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e, G_e
+        // from the pass's own tiles (the last steps; zero beyond m and N).
+        // A transposing read at rows 16 b + 4 kk of the wave's chunk gives
+        // lane (kk, row) emitters 16 b + 4 kk + i (i = 0..3) of pixel
+        // 16 cb + row, the layout of the accumulators.
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        lds_barrier();   // every wave's last tiles are in place
+        if (e0 < P.mp) {
+            const int sidx = nlead + (e0 / kT16KC - ce0);   // step that held this wave's chunk
+            const int bi = sidx & 3;
+            const unsigned char *se = bi == 0 ? sG0 : (bi == 1 ? sG1 : (bi == 2 ? sG2 : sG3));
+#pragma unroll
+            for (int b = 0; b < EB; ++b) {
+#pragma unroll
+                for (int cb = 0; cb < 8; ++cb) {
+                    const int off = t16_off(16 * b + 4 * kk + (row >> 2), 16 * cb + 4 * (row & 3));
+                    const t16v4 vr = t16_tr(se + off), vi = t16_tr(se + kT16Arr + off);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const bool ok = e0 + 16 * b + 4 * kk + i < P.m;
+                        const float ger = ok ? MM16<S>::bits_to_f((unsigned short)vr[i]) : 0.0f;
+                        const float gei = ok ? MM16<S>::bits_to_f((unsigned short)vi[i]) : 0.0f;
+                        gp[cb] += ger * yr[b][cb][i] - gei * yn[b][cb][i];
+                        if (HESS) hp[cb] += (ger * ger + gei * gei) * z[b][cb][i];
+                    }
+                }
+            }
+        }
+    }
+    // the four lane groups of a column, then the waves, in a fixed order
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) {
+        float g = gp[cb], h = hp[cb];
+        g += __shfl_xor(g, 16);
+        h += __shfl_xor(h, 16);
+        g += __shfl_xor(g, 32);
+        h += __shfl_xor(h, 32);
+        if (kk == 0) {
+            sred[0][wave][16 * cb + row] = g;
+            sred[1][wave][16 * cb + row] = h;
+        }
+    }
+    __syncthreads();
+    if (tid < kT16NT) {
+        const int64_t x = x0 + tid;
+        if (x < N) {
+            const double gs = (double)gscale[k], as = ascale[k] > 0.0f ? (double)ascale[k] : 1.0;
+            const double g2 = gs * gs;
+            double g = 0.0, h = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                g += (double)sred[0][w][tid];
+                h += (double)sred[1][w][tid];
+            }
+            const int npgl = it.npg;
+            pg[((int64_t)k * npgl + qg) * N + x] = g * (P.cg[k] * g2 * as);
+            if (HESS) ph[((int64_t)k * npgl + qg) * N + x] = h * (P.ch[k] * g2 * g2);
+        }
+    }
+}
+
+
 // grad += sum_k sum_q pg[k][q], hd += sum_k sum_q ph[k][q] in frequency
 // order, then emitter-pass group order.
 __global__ void k_adj_sum(int64_t N, int nf, int npg, const double *__restrict__ pg, const double *__restrict__ ph,
@@ -1088,7 +1458,7 @@ rb_status adjoint_prepare(const rb_geometry *g, const void *G_re, const void *G_
     it.ascale = w.ascale;
     it.pg = w.pg;
     it.ph = w.ph;
-    it.ntiles = (int)blocks_for(P.N, dt == RB_F32 ? kAdjNT : kA16NT);
+    it.ntiles = (int)blocks_for(P.N, dt == RB_F32 ? kAdjNT : kT16NT);
     it.begin = 0;
     it.npg = adj_groups(g, dt);
     task->dt = dt;
@@ -1137,9 +1507,9 @@ rb_status adjoint_run(const AdjTask &task, hipStream_t st) {
             auto go = [&](auto tag) {
                 using S = decltype(tag);
                 if (hdiag)
-                    k_adjoint16_lds<S, true, 2, 4><<<ga, 256, 0, st>>>(one);
+                    k_adjoint16_tr<S, true><<<ga, 256, 0, st>>>(one);
                 else
-                    k_adjoint16_lds<S, false, 2, kA16GradWaves><<<ga, 64 * kA16GradWaves, 0, st>>>(one);
+                    k_adjoint16_tr<S, false><<<ga, 256, 0, st>>>(one);
             };
             if (task.dt == RB_BF16)
                 go(__hip_bfloat16());
@@ -1193,17 +1563,15 @@ rb_status adjoint_run_grouped(AdjTask *const *tasks, int n, hipStream_t st) {
                 break;
             case RB_BF16:
                 if (hess)
-                    k_adjoint16_lds<__hip_bfloat16, true, 2, 4><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                    k_adjoint16_tr<__hip_bfloat16, true><<<(unsigned)blocks, 256, 0, st>>>(arg);
                 else
-                    k_adjoint16_lds<__hip_bfloat16, false, 2, kA16GradWaves>
-                        <<<(unsigned)blocks, 64 * kA16GradWaves, 0, st>>>(arg);
+                    k_adjoint16_tr<__hip_bfloat16, false><<<(unsigned)blocks, 256, 0, st>>>(arg);
                 break;
             case RB_F16:
                 if (hess)
-                    k_adjoint16_lds<__half, true, 2, 4><<<(unsigned)blocks, 256, 0, st>>>(arg);
+                    k_adjoint16_tr<__half, true><<<(unsigned)blocks, 256, 0, st>>>(arg);
                 else
-                    k_adjoint16_lds<__half, false, 2, kA16GradWaves>
-                        <<<(unsigned)blocks, 64 * kA16GradWaves, 0, st>>>(arg);
+                    k_adjoint16_tr<__half, false><<<(unsigned)blocks, 256, 0, st>>>(arg);
                 break;
             default:
                 break;

@@ -4,8 +4,8 @@
 // Eikonal equation (Eq. 6), integrated along rays with T itself as the ray
 // parameter; the amplitude follows from the Transport equation (Eq. 7) via
 // the ray-tube width J from neighbouring rays; absorption accumulates along
-// each ray (Eq. 5).  The tables are formed on the wavefront mesh
-// (Discussion: "back-propagation of ray parameters") by first-arrival
+// each ray (Eq. 5).  The tables are formed on the wavefront mesh (the
+// Discussion carries the ray parameters back onto the grid) by first-arrival
 // barycentric interpolation.
 //
 // GPU design:
@@ -13,10 +13,10 @@
 //    are packed into one 16-byte (s, alpha0) record per pixel so a bilinear
 //    corner is one load, served from L2/MALL (a 480x480 map is 3.7 MB);
 //  * wavefront nodes are stored [emitter][step][ray] so the lanes of a wave
-//    write consecutive addresses at every step;
-//  * first arrival without floating-point atomics: a classification pass
-//    lists the mesh cells whose bounding box holds a pixel centre or
-//    straddles the ring; the raster passes take one 64-bit atomicMin per
+//    write consecutive addresses at every step (24 bytes a node);
+//  * first arrival without floating-point atomics: the tracing waves list
+//    the mesh cells whose bounding box holds a pixel centre or straddles the
+//    ring as the cells close; the raster passes take one 64-bit atomicMin per
 //    candidate on the arrival key (fixed-point step index above the
 //    triangle index), and the write pass decodes each point's winner and
 //    recomputes its barycentrics.  The result is independent of scheduling;
@@ -119,24 +119,49 @@ __global__ void k_pack(int nx, int ny, double s_bg, const double *__restrict__ s
     }
 }
 
+// Cell ids: (batch emitter << 31) | (step << 13) | ray.
+__device__ __forceinline__ uint64_t cell_id(int eb, int n, int j) {
+    return ((uint64_t)eb << 31) | ((uint64_t)n << 13) | (uint64_t)j;
+}
+__device__ __forceinline__ void cell_decode(uint64_t id, int &eb, int &n, int &j) {
+    j = (int)(id & 8191u);
+    n = (int)((id >> 13) & 262143u);
+    eb = (int)(id >> 31);
+}
+
 // Rays of one emitter are traced a wave at a time in lockstep: lanes 1..62
 // own rays j0 .. j0+61 and lanes 0 and 63 trace the neighbouring rays as a
 // halo, so the ray-tube width J at every node of an owned ray comes from
 // lane shuffles at equal travel time.  The slowness at a node is the first
 // RK4 stage of the step that leaves it, so the amplitude factor
 // a = sqrt(c / (8 pi max(J, j_min))) costs no extra field evaluation.
-// Nodes are stored [eb][n][j] (positions and (a, B) as double2 pairs).
+// Nodes are stored [eb][n][j]: positions as double pairs, (a, B) as float
+// pairs (a is formed in FP32 and the tables store B in FP32).
+//
+// The same lockstep classifies the wavefront-mesh cells as they close: once
+// node n of rays j and j + 1 exists, cell (n - 1, j) has its four corners in
+// the registers of lanes j and j + 1 (two steps apart), so its bounding box
+// is tested here and not in a pass that reads the nodes back.  A cell whose
+// box holds a pixel centre goes to the pixel list, one whose box straddles
+// the ring to the ring list (both tests conservative: each triangle's box
+// lies inside its cell's).  Each wave appends to a private segment of each
+// list (segment = (batch emitter, wave), capacity 62 nmax) with ballot
+// prefixes, so there is no contended counter.
 constexpr int kOwn = 62;
 typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
 
 __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__ sa, double2 *__restrict__ XY,
-                                               double2 *__restrict__ AB, int *__restrict__ L) {
+                                               float2 *__restrict__ AB, int *__restrict__ L, int64_t cap,
+                                               uint64_t *__restrict__ list_px, uint64_t *__restrict__ list_rx,
+                                               int *__restrict__ seg_px, int *__restrict__ seg_rx) {
     // the integration may fuse multiply-adds (one rounding instead of two)
 #pragma clang fp contract(fast)
     const int lane = threadIdx.x & 63;
+    const int nw = (P.nr + kOwn - 1) / kOwn;   // waves per emitter
     const int wv = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int eb = blockIdx.y;
-    if (wv * kOwn >= P.nr || eb >= P.ne) return;  // wave-uniform
+    if (wv >= nw || eb >= P.ne) return;  // wave-uniform
     const int j = wv * kOwn + lane - 1;
     const bool valid = j >= 0 && j < P.nr;
     const bool own = valid && lane >= 1 && lane <= kOwn;
@@ -151,6 +176,13 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
     const size_t base = (size_t)eb * (size_t)(P.nmax + 1) * P.nr + (valid ? j : 0);
     const double dt = P.dtau, hdt = 0.5 * dt, sixth = dt / 6.0;
     const double eight_pi = 8.0 * M_PI;
+    const int64_t seg = (int64_t)eb * nw + wv;
+    uint64_t *lp = list_px + seg * cap;
+    uint64_t *lr = list_rx + seg * cap;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool has_right = own && j + 1 < P.nr;   // cells (., j) exist
+    int cp = 0, cr = 0;                          // wave-uniform list counts
+    double xp = 0.0, yp = 0.0;                   // node n - 1 of this ray
     bool alive = valid;   // alive at the current node n
     bool last = false;    // the current node is the ray's last
     for (int n = 0; n <= P.nmax; ++n) {
@@ -162,6 +194,31 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
         const double xl = __shfl_up(st[0], 1), yl = __shfl_up(st[1], 1);
         const double xr = __shfl_down(st[0], 1), yr = __shfl_down(st[1], 1);
         const int al = __shfl_up((int)alive, 1), ar = __shfl_down((int)alive, 1);
+        // cell (n - 1, j): nodes n - 1 and n of rays j and j + 1
+        const double xrp = __shfl_down(xp, 1), yrp = __shfl_down(yp, 1);
+        bool pix = false, ring = false;
+        if (n >= 1 && has_right && alive && ar) {
+            const double cxmin = fmin(fmin(xp, xrp), fmin(st[0], xr));
+            const double cxmax = fmax(fmax(xp, xrp), fmax(st[0], xr));
+            const double cymin = fmin(fmin(yp, yrp), fmin(st[1], yr));
+            const double cymax = fmax(fmax(yp, yrp), fmax(st[1], yr));
+            pix = ceil((cxmin - P.x0) * P.inv_h) <= fmin(floor((cxmax - P.x0) * P.inv_h), (double)(P.nx - 1)) &&
+                  ceil((cymin - P.y0) * P.inv_h) <= fmin(floor((cymax - P.y0) * P.inv_h), (double)(P.ny - 1)) &&
+                  cxmax >= P.x0 && cymax >= P.y0;
+            const double dxm = cxmin > 0.0 ? cxmin : (cxmax < 0.0 ? -cxmax : 0.0);
+            const double dym = cymin > 0.0 ? cymin : (cymax < 0.0 ? -cymax : 0.0);
+            const double dmin2 = dxm * dxm + dym * dym;
+            const double dmax2 = fmax(cxmin * cxmin, cxmax * cxmax) + fmax(cymin * cymin, cymax * cymax);
+            ring = dmin2 <= P.ring2_hi && dmax2 >= P.ring2_lo;
+        }
+        {
+            const uint64_t mp = __ballot(pix), mr = __ballot(ring);
+            const uint64_t id = cell_id(eb, n - 1, j);
+            if (pix) lp[cp + __popcll(mp & below)] = id;
+            if (ring) lr[cr + __popcll(mr & below)] = id;
+            cp += __popcll(mp);
+            cr += __popcll(mr);
+        }
         if (own && alive) {
             const bool lo = j > 0 && al;
             const bool hi = j + 1 < P.nr && ar;
@@ -190,8 +247,10 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
             // nodes are written once and read by later passes: keep them
             // from displacing the field grid in L2
             __builtin_nontemporal_store(nd2{st[0], st[1]}, reinterpret_cast<nd2 *>(&XY[k]));
-            __builtin_nontemporal_store(nd2{(double)amp, st[4]}, reinterpret_cast<nd2 *>(&AB[k]));
+            __builtin_nontemporal_store(nf2{amp, (float)st[4]}, reinterpret_cast<nf2 *>(&AB[k]));
         }
+        xp = st[0];
+        yp = st[1];
         if (alive && (last || n == P.nmax)) {
             if (own) L[(size_t)eb * P.nr + j] = n;
             alive = false;
@@ -219,6 +278,10 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
             for (int q = 0; q < 5; ++q) st[q] = st[q] + sixth * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
             last = st[0] * st[0] + st[1] * st[1] > P.rdie2;
         }
+    }
+    if (lane == 0) {
+        seg_px[seg] = cp;
+        seg_rx[seg] = cr;
     }
 }
 
@@ -334,94 +397,26 @@ __global__ void k_rx_pos(TP P, double2 *__restrict__ rxy) {
     rxy[r] = make_double2(P.R * cos(th), P.R * sin(th));
 }
 
-// Cell ids: (batch emitter << 31) | (step << 13) | ray.
-__device__ __forceinline__ uint64_t cell_id(int eb, int n, int j) {
-    return ((uint64_t)eb << 31) | ((uint64_t)n << 13) | (uint64_t)j;
-}
-__device__ __forceinline__ void cell_decode(uint64_t id, int &eb, int &n, int &j) {
-    j = (int)(id & 8191u);
-    n = (int)((id >> 13) & 262143u);
-    eb = (int)(id >> 31);
-}
-
-// Launch shape of the cell passes: logical workgroups are (64-ray column
-// block, step group of 4 waves, emitter); each wave owns a list segment of
-// 64 entries per loop iteration.
-constexpr int kCellGroupsY = 8;
-
-// Pass 0: classify every live cell of the wavefront mesh.  A cell whose
-// bounding box holds a pixel centre goes to the pixel list, one whose box
-// straddles the ring to the ring list (tests conservative: each triangle's
-// box lies inside its cell's).  Every wave owns a private segment of each
-// list (64 entries per iteration of its loop) and appends with ballot
-// prefixes, so there is no contended counter; the loop runs until the
-// wave's last live cell, with the finished lanes idle.
-__global__ void __launch_bounds__(256) k_cells(TP P, const double2 *__restrict__ XY, const int *__restrict__ L,
-                                               int cap, uint64_t *__restrict__ list_px, uint64_t *__restrict__ list_rx,
-                                               int *__restrict__ seg_px, int *__restrict__ seg_rx) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // logical workgroup (column block, step group, emitter), x fastest
-    const int gx = (P.nr - 1 + 63) / 64;
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = (int)(lb % gx), by = (int)((lb / gx) % kCellGroupsY);
-    const int j = bx * 64 + lane;
-    const int eb = (int)(lb / ((int64_t)gx * kCellGroupsY));
-    const int64_t seg = lb * 4 + wave;
-    uint64_t *lp = list_px + seg * cap;
-    uint64_t *lr = list_rx + seg * cap;
-    const int *Le = L + (size_t)eb * P.nr;
-    const int nlast = j < P.nr - 1 ? min(min(Le[j], Le[j + 1]) - 1, P.nmax - 1) : -1;
-    const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
-    const uint64_t below = (1ull << lane) - 1ull;
-    int cp = 0, cr = 0;   // wave-uniform counts
-    for (int n = by * 4 + wave;; n += kCellGroupsY * 4) {
-        const bool act = n <= nlast;
-        if (!__any(act)) break;
-        bool pix = false, ring = false;
-        if (act) {
-            const int64_t k00 = base + (int64_t)n * P.nr + j;
-            const double2 q00 = XY[k00], q10 = XY[k00 + 1], q01 = XY[k00 + P.nr], q11 = XY[k00 + P.nr + 1];
-            const double cxmin = fmin(fmin(q00.x, q10.x), fmin(q01.x, q11.x));
-            const double cxmax = fmax(fmax(q00.x, q10.x), fmax(q01.x, q11.x));
-            const double cymin = fmin(fmin(q00.y, q10.y), fmin(q01.y, q11.y));
-            const double cymax = fmax(fmax(q00.y, q10.y), fmax(q01.y, q11.y));
-            pix = ceil((cxmin - P.x0) * P.inv_h) <= fmin(floor((cxmax - P.x0) * P.inv_h), (double)(P.nx - 1)) &&
-                  ceil((cymin - P.y0) * P.inv_h) <= fmin(floor((cymax - P.y0) * P.inv_h), (double)(P.ny - 1)) &&
-                  cxmax >= P.x0 && cymax >= P.y0;
-            const double dxm = cxmin > 0.0 ? cxmin : (cxmax < 0.0 ? -cxmax : 0.0);
-            const double dym = cymin > 0.0 ? cymin : (cymax < 0.0 ? -cymax : 0.0);
-            const double dmin2 = dxm * dxm + dym * dym;
-            const double dmax2 = fmax(cxmin * cxmin, cxmax * cxmax) + fmax(cymin * cymin, cymax * cymax);
-            ring = dmin2 <= P.ring2_hi && dmax2 >= P.ring2_lo;
-        }
-        const uint64_t mp = __ballot(pix), mr = __ballot(ring);
-        const uint64_t id = cell_id(eb, n, j);
-        if (pix) lp[cp + __popcll(mp & below)] = id;
-        if (ring) lr[cr + __popcll(mr & below)] = id;
-        cp += __popcll(mp);
-        cr += __popcll(mr);
-    }
-    if (lane == 0) {
-        seg_px[seg] = cp;
-        seg_rx[seg] = cr;
-    }
-}
-
 // Pixel pass: every candidate (triangle, pixel) pair takes the atomic
-// minimum of its arrival key.  Each wave walks one list segment.  Per
-// triangle, the candidate pixel range comes first and the determinant only
-// when the range is not empty.
-__global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restrict__ XY, int nseg, int cap,
+// minimum of its arrival key.  A wave takes one chunk of kRasterChunk
+// entries of one list segment (work item = segment x chunk; chunks past the
+// segment's end return at once).  Per triangle, the candidate pixel range
+// comes first and the determinant only when the range is not empty.
+constexpr int kRasterChunk = 512;
+
+__global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restrict__ XY, int64_t nseg, int64_t cap,
                                                    const uint64_t *__restrict__ list, const int *__restrict__ segn,
                                                    uint64_t *__restrict__ akey) {
     const int64_t N = (int64_t)P.nx * P.ny;
     const double tol = -P.bary_tol;
     const int lane = threadIdx.x & 63;
-    const int64_t seg = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nch = (cap + kRasterChunk - 1) / kRasterChunk;
+    const int64_t item = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t seg = item / nch;
     if (seg >= nseg) return;
-    const int cnt = segn[seg];
-    for (int i = lane; i < cnt; i += 64) {
+    const int i0 = (int)(item - seg * nch) * kRasterChunk;
+    const int i1 = min(segn[seg], i0 + kRasterChunk);
+    for (int i = i0 + lane; i < i1; i += 64) {
         int eb, n, j;
         cell_decode(list[seg * cap + i], eb, n, j);
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
@@ -450,15 +445,18 @@ __global__ void __launch_bounds__(256) k_raster_px(TP P, const double2 *__restri
 }
 
 // The same pass over the ring list, for the ring elements.
-__global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restrict__ XY, int nseg, int cap,
+__global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restrict__ XY, int64_t nseg, int64_t cap,
                                                    const uint64_t *__restrict__ list, const int *__restrict__ segn,
                                                    const double2 *__restrict__ rxy, uint64_t *__restrict__ akey_rx) {
     const double tol = -P.bary_tol;
     const int lane = threadIdx.x & 63;
-    const int64_t seg = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nch = (cap + kRasterChunk - 1) / kRasterChunk;
+    const int64_t item = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t seg = item / nch;
     if (seg >= nseg) return;
-    const int cnt = segn[seg];
-    for (int i = lane; i < cnt; i += 64) {
+    const int i0 = (int)(item - seg * nch) * kRasterChunk;
+    const int i1 = min(segn[seg], i0 + kRasterChunk);
+    for (int i = i0 + lane; i < i1; i += 64) {
         int eb, n, j;
         cell_decode(list[seg * cap + i], eb, n, j);
         const int64_t base = (int64_t)eb * (P.nmax + 1) * P.nr;
@@ -495,7 +493,7 @@ __global__ void __launch_bounds__(256) k_raster_rx(TP P, const double2 *__restri
 // of T, a and B, from the same values (a and B rounded to float as the
 // tables store them).
 template <bool RX, typename GS = void>
-__global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const double2 *__restrict__ AB,
+__global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const float2 *__restrict__ AB,
                                const double2 *__restrict__ rxy, uint64_t *__restrict__ akey,
                                float *__restrict__ amp_out, float *__restrict__ att_out,
                                uint8_t *__restrict__ cover, GreenParams GP = GreenParams(),
@@ -575,9 +573,9 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
         bary(t, px, py, -P.bary_tol, la, lb, lc);
         const double ta = (double)na * P.dtau, tb = (double)nb * P.dtau, tc = (double)nc * P.dtau;
         const double tv = la * ta + lb * tb + lc * tc;
-        const double2 qa = AB[ka], qb = AB[kb], qc = AB[kc];
-        const float av = (float)(la * qa.x + lb * qb.x + lc * qc.x);
-        const float bv = (float)(la * qa.y + lb * qb.y + lc * qc.y);
+        const float2 qa = AB[ka], qb = AB[kb], qc = AB[kc];
+        const float av = (float)(la * (double)qa.x + lb * (double)qb.x + lc * (double)qc.x);
+        const float bv = (float)(la * (double)qa.y + lb * (double)qb.y + lc * (double)qc.y);
         if constexpr (GREEN) {
             for (int k = 0; k < GP.nf; ++k) {
                 double re, im;
@@ -593,43 +591,44 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const doubl
     }
 }
 
-inline int cell_iters(const rb_trace_opts *t) {
-    const int stride = kCellGroupsY * 4;
-    return (int)((trace_nmax(t) + stride - 1) / stride);
-}
-inline int cell_seg_cap(const rb_trace_opts *t) { return 64 * cell_iters(t); }
-inline size_t cell_segments(const rb_geometry *g, const rb_trace_opts *t, int batch) {
-    (void)g;
-    return (size_t)((t->n_rays - 1 + 63) / 64) * kCellGroupsY * 4 * batch;
+// Cell lists: one segment per tracing wave (batch emitter x wave), each
+// with room for every cell of the wave's 62 owned rays.
+inline int trace_waves(const rb_trace_opts *t) { return (t->n_rays + kOwn - 1) / kOwn; }
+inline int64_t cell_seg_cap(const rb_trace_opts *t) { return (int64_t)kOwn * trace_nmax(t); }
+inline int64_t cell_segments(const rb_trace_opts *t, int batch) { return (int64_t)trace_waves(t) * batch; }
+inline unsigned raster_blocks(const rb_trace_opts *t, int batch) {
+    const int64_t nch = (cell_seg_cap(t) + kRasterChunk - 1) / kRasterChunk;
+    return (unsigned)((cell_segments(t, batch) * nch + 3) / 4);
 }
 
 struct TraceWs {
     double2 *sa, *rxy;
-    double2 *XY, *AB;   // node position (x, y) and (amplitude factor, absorption)
+    double2 *XY;   // node position (x, y)
+    float2 *AB;    // node (amplitude factor, absorption)
     int *L;
-    uint64_t *list_px, *list_rx;  // candidate cells (pixel / ring), one segment per wave
+    uint64_t *list_px, *list_rx;  // candidate cells (pixel / ring), one segment per tracing wave
     int *seg_px, *seg_rx;         // segment lengths
 };
 
 size_t per_emitter_bytes(const rb_geometry *g, const rb_trace_opts *t) {
+    (void)g;
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays;
-    const size_t segs = cell_segments(g, t, 1);
-    return nodes * 2 * sizeof(double2) + (size_t)t->n_rays * sizeof(int) +
-           2 * segs * (cell_seg_cap(t) * sizeof(uint64_t) + sizeof(int)) + 10 * 256;
+    const size_t segs = (size_t)cell_segments(t, 1);
+    return nodes * (sizeof(double2) + sizeof(float2)) + (size_t)t->n_rays * sizeof(int) +
+           2 * segs * ((size_t)cell_seg_cap(t) * sizeof(uint64_t) + sizeof(int)) + 10 * 256;
 }
 
 TraceWs carve_trace(Carver &c, const rb_geometry *g, const rb_trace_opts *t, int batch) {
     TraceWs w;
-    const size_t N = (size_t)g->nx * g->ny;
     const size_t nodes = (size_t)(trace_nmax(t) + 1) * t->n_rays * batch;
     w.sa = c.take<double2>((size_t)(g->nx + 4) * (g->ny + 4));
     w.rxy = c.take<double2>((size_t)g->m);
     w.XY = c.take<double2>(nodes);
-    w.AB = c.take<double2>(nodes);
+    w.AB = c.take<float2>(nodes);
     w.L = c.take<int>((size_t)t->n_rays * batch);
-    const size_t segs = cell_segments(g, t, batch);
-    w.list_px = c.take<uint64_t>(segs * cell_seg_cap(t));
-    w.list_rx = c.take<uint64_t>(segs * cell_seg_cap(t));
+    const size_t segs = (size_t)cell_segments(t, batch);
+    w.list_px = c.take<uint64_t>(segs * (size_t)cell_seg_cap(t));
+    w.list_rx = c.take<uint64_t>(segs * (size_t)cell_seg_cap(t));
     w.seg_px = c.take<int>(segs);
     w.seg_rx = c.take<int>(segs);
     return w;
@@ -714,16 +713,12 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
         uint64_t *akey_rx = reinterpret_cast<uint64_t *>(out->T_rx + (int64_t)e0 * g->m);
         RB_TRY(fill_u64(akey, ~0ull, (int64_t)P.ne * N, st));
         RB_TRY(fill_u64(akey_rx, ~0ull, (int64_t)P.ne * g->m, st));
-        const int waves = (P.nr + kOwn - 1) / kOwn;
-        dim3 gt((waves + 3) / 4, P.ne);
-        k_trace<<<gt, 256, 0, st>>>(P, w.sa, w.XY, w.AB, w.L);
+        const int64_t cap = cell_seg_cap(t);
+        const int64_t nseg = cell_segments(t, P.ne);
+        dim3 gt((trace_waves(t) + 3) / 4, P.ne);
+        k_trace<<<gt, 256, 0, st>>>(P, w.sa, w.XY, w.AB, w.L, cap, w.list_px, w.list_rx, w.seg_px, w.seg_rx);
         RB_LAUNCHED();
-        const int cap = cell_seg_cap(t);
-        const int nseg = (int)cell_segments(g, t, P.ne);
-        const unsigned gc = blocks_for(P.nr - 1, 64) * kCellGroupsY * P.ne;
-        k_cells<<<gc, 256, 0, st>>>(P, w.XY, w.L, cap, w.list_px, w.list_rx, w.seg_px, w.seg_rx);
-        RB_LAUNCHED();
-        const unsigned nbl = blocks_for(nseg, 4);
+        const unsigned nbl = raster_blocks(t, P.ne);
         k_raster_px<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_px, w.seg_px, akey);
         RB_LAUNCHED();
         k_raster_rx<<<nbl, 256, 0, st>>>(P, w.XY, nseg, cap, w.list_rx, w.seg_rx, w.rxy, akey_rx);
@@ -1158,9 +1153,8 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
     k_rx_pos<<<blocks_for(m, 256), 256, 0, st>>>(P, w.tw.rxy);
     RB_LAUNCHED();
     const int64_t npad = (int64_t)(g->nx + 4) * (g->ny + 4);
-    const int waves = (P.nr + kOwn - 1) / kOwn;
-    const int cap = cell_seg_cap(t);
-    const int nseg = (int)cell_segments(g, t, m);
+    const int64_t cap = cell_seg_cap(t);
+    const int64_t nseg = cell_segments(t, m);
     for (int it = 0; it < n_iter; ++it) {
         // rays and first arrivals at the ring elements in the current model
         k_tof_slowness<<<blocks_for(N, 256), 256, 0, st>>>(w.c, N, w.s);
@@ -1168,13 +1162,11 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
         k_pack<<<blocks_for(npad, 256), 256, 0, st>>>(g->nx, g->ny, P.s_bg, w.s, nullptr, w.tw.sa);
         RB_LAUNCHED();
         RB_TRY(fill_u64(w.akey_rx, ~0ull, mm, st));
-        k_trace<<<dim3((waves + 3) / 4, m), 256, 0, st>>>(P, w.tw.sa, w.tw.XY, w.tw.AB, w.tw.L);
+        k_trace<<<dim3((trace_waves(t) + 3) / 4, m), 256, 0, st>>>(P, w.tw.sa, w.tw.XY, w.tw.AB, w.tw.L, cap,
+                                                                 w.tw.list_px, w.tw.list_rx, w.tw.seg_px,
+                                                                 w.tw.seg_rx);
         RB_LAUNCHED();
-        const unsigned gc = blocks_for(P.nr - 1, 64) * kCellGroupsY * m;
-        k_cells<<<gc, 256, 0, st>>>(P, w.tw.XY, w.tw.L, cap, w.tw.list_px, w.tw.list_rx, w.tw.seg_px,
-                                    w.tw.seg_rx);
-        RB_LAUNCHED();
-        k_raster_rx<<<blocks_for(nseg, 4), 256, 0, st>>>(P, w.tw.XY, nseg, cap, w.tw.list_rx, w.tw.seg_rx,
+        k_raster_rx<<<raster_blocks(t, m), 256, 0, st>>>(P, w.tw.XY, nseg, cap, w.tw.list_rx, w.tw.seg_rx,
                                                           w.tw.rxy, w.akey_rx);
         RB_LAUNCHED();
         // linking paths and residuals
