@@ -580,125 +580,7 @@ __global__ void __launch_bounds__(256, HESS ? 2 : 3) k_adjoint_f32(const A args)
 }
 
 
-// ------------------------------------------------------------------ 16-bit, LDS-staged
-// Backprojection with 16-bit tables on the 16x16x32 matrix cores (FP32
-// accumulation; G and A = W.D pre-scaled per frequency).  The workgroup owns
-// 64 pixels and one frequency; its four waves each take 16 EB emitters and
-// all 64 pixels (four column blocks of 16 pixels), and the workgroup walks the
-// emitters in passes of 64 EB.  The MFMA's B operand needs eight consecutive
-// receivers of one pixel per lane, while the tables keep pixels contiguous:
-// each tile of 32 receivers x 64 pixels is copied into LDS by direct
-// global->LDS loads of four bytes per lane (two rows of 128 bytes per
-// instruction, 8 bytes of padding per row pair), and each lane gathers its
-// eight receivers for four pixels at once with 8-byte LDS reads, splitting
-// the 16-bit halves among four fragments.  Three tile buffers keep two tiles
-// in flight.  The A fragments (eight consecutive receivers of one emitter) are
-// single 16-byte loads from L2, one k-step ahead.
-constexpr int kA16NT = 64, kA16KC = 32;
-constexpr int kA16Pair = 264;                      // bytes per pair of tile rows (2 x 128 + 8)
-constexpr int kA16Arr = (kA16KC / 2) * kA16Pair;   // one array (re or im) of a tile
-#ifndef A16_GRAD_WAVES
-#define A16_GRAD_WAVES 4
-#endif
-constexpr int kA16GradWaves = A16_GRAD_WAVES;   // waves per workgroup of the gradient-only kernel
-constexpr int kA16Buf = 3;                         // tiles c, c + 1, c + 2
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-// byte offset of (tile row rl, pixel px) within one array of a tile
-__device__ __forceinline__ int a16_off(int rl, int px) { return (rl >> 1) * kA16Pair + (rl & 1) * 128 + 2 * px; }
-
-// The emitter rows of a pass (16 EB NW of them) are receiver rows of tiles
-// that pass through LDS during the same pass, so the epilogue takes G_e from
-// a copy of those tiles instead of reading the tables again: rows of 64
-// pixels (128 bytes) at a stride of 136 bytes, which puts the rows four
-// apart (the lane groups of the epilogue's reads) on different banks.
-constexpr int kA16ERow = 136;
-
-// Copy tile rows 0..31 (both arrays) to rows el..el + 31 of the emitter
-// store sE (rows ne per array); 8 bytes per thread and instruction.
-template <int NW>
-__device__ __forceinline__ void a16_keep(const unsigned char *sT, unsigned char *sE, int ne, int el) {
-#pragma unroll
-    for (int j = 0; j < 1024 / (64 * NW); ++j) {
-        const int q = threadIdx.x + 64 * NW * j;
-        const int arr = q >> 9, rl = (q >> 4) & 31, u = q & 15;
-        const u32x2 v = *reinterpret_cast<const u32x2 *>(sT + arr * kA16Arr + a16_off(rl, 4 * u));
-        *reinterpret_cast<u32x2 *>(sE + (arr * ne + el + rl) * kA16ERow + 8 * u) = v;
-    }
-}
-
-// Aligned full tiles (m a multiple of 32, so every row exists): wave w of
-// NW fills row pairs (16 / NW) w .. of both arrays, one pair per
-// instruction.  Lane l of an instruction loads pixels 2 (l % 32) and
-// 2 (l % 32) + 1 of row 2 p + l / 32, which is where its four bytes land;
-// `loff` = (l / 32) N + 2 (l % 32) is that lane's fixed offset from the
-// tile's first pixel in row 2 p.
-template <int NW>
-__device__ __forceinline__ void a16_stage_async(const unsigned short *__restrict__ gr,
-                                                const unsigned short *__restrict__ gi, int64_t N, int rc,
-                                                unsigned loff, unsigned char *sT) {
-    constexpr int PW = (kA16KC / 2) / NW;   // row pairs per wave
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-#pragma unroll
-    for (int j = 0; j < PW; ++j) {
-        const int p = PW * wave + j;
-        const int64_t ro = (int64_t)(rc + 2 * p) * N;   // uniform
-        __builtin_amdgcn_global_load_lds(gr + ro + loff, (lds_void_t *)(sT + p * kA16Pair), 4, 0, 0);
-        __builtin_amdgcn_global_load_lds(gi + ro + loff, (lds_void_t *)(sT + kA16Arr + p * kA16Pair), 4, 0, 0);
-    }
-}
-
-// Ragged or odd-width tiles: through registers, zero beyond m and N; the
-// tile is 512 runs of eight pixels ([array][row][run]).
-template <int NW>
-__device__ __forceinline__ void a16_stage_regs(const unsigned short *__restrict__ gr,
-                                               const unsigned short *__restrict__ gi, int m, int64_t N, int rc,
-                                               int64_t x0, unsigned char *sT) {
-    // not unrolled: this rare path must not raise the kernel's register count
-#pragma unroll 1
-    for (int q = threadIdx.x; q < 2 * kA16KC * 8; q += 64 * NW) {
-        const int arr = q >> 8, rl = (q >> 3) & 31, p0 = (q & 7) * 8;
-        const unsigned short *g = arr ? gi : gr;
-        const int r = rc + rl;
-        unsigned short v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t x = x0 + p0 + u;
-            v[u] = (r < m && x < N) ? g[(int64_t)r * N + x] : (unsigned short)0;
-        }
-        unsigned short *d = reinterpret_cast<unsigned short *>(sT + arr * kA16Arr + a16_off(rl, p0));
-#pragma unroll
-        for (int u = 0; u < 8; ++u) d[u] = v[u];
-    }
-}
-
-// B fragments of the four column blocks at once.  Column block q holds the
-// pixels 4 j + q (j = lane % 16), so lane (j, kk) reads pixels 4 j .. 4 j + 3
-// of rows 8 kk .. 8 kk + 7 with eight 8-byte LDS reads and splits the 16-bit
-// halves among the four fragments.  `base` = a16_off(8 kk, 4 j).
-template <typename V>
-__device__ __forceinline__ void a16_frags(const unsigned char *sA, int base, V (&out)[4]) {
-    u32x2 d[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        d[i] = *reinterpret_cast<const u32x2 *>(sA + base + (i >> 1) * kA16Pair + (i & 1) * 128);
-    // byte permutes: the low (0x05040100) or high (0x07060302) halves of
-    // rows 2 h (low half of the result) and 2 h + 1 (high half)
-    u32x4 w[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        const u32x2 a = d[2 * h], b = d[2 * h + 1];
-        w[0][h] = __builtin_amdgcn_perm(b.x, a.x, 0x05040100u);
-        w[1][h] = __builtin_amdgcn_perm(b.x, a.x, 0x07060302u);
-        w[2][h] = __builtin_amdgcn_perm(b.y, a.y, 0x05040100u);
-        w[3][h] = __builtin_amdgcn_perm(b.y, a.y, 0x07060302u);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[q] = __builtin_bit_cast(V, w[q]);
-}
-
+// ------------------------------------------------------------------ 16-bit
 // |G|^2 of a fragment, rounded to the storage type
 template <typename S, typename V>
 __device__ __forceinline__ V a16_abs2(V br, V bi) {
@@ -713,244 +595,6 @@ __device__ __forceinline__ V a16_abs2(V br, V bi) {
 
 template <int I>
 using Idx = std::integral_constant<int, I>;
-
-template <typename S, bool HESS, int EB, int NW, typename A>
-__global__ void __launch_bounds__(64 * NW, (HESS ? 4 : 8) / NW) k_adjoint16_lds(const A args) {
-    typename A::Loc loc;
-    const AdjItem &it = args.locate(loc);
-    const AdjParams &P = it.P;
-    const S *__restrict__ Gr = (const S *)it.Gr;
-    const S *__restrict__ Gi = (const S *)it.Gi;
-    const S *__restrict__ Ar = (const S *)it.Ar;
-    const S *__restrict__ Ai = (const S *)it.Ai;
-    const S *__restrict__ Wt = (const S *)it.Wt;
-    const uint8_t *__restrict__ flags = it.flags;
-    const float *__restrict__ gscale = it.gscale;
-    const float *__restrict__ ascale = it.ascale;
-    double *__restrict__ pg = it.pg;
-    double *__restrict__ ph = it.ph;
-    using V = typename MM16<S>::vec;
-    // Three tile buffers as separate LDS objects, always addressed by a
-    // compile-time index: the compiler can then tell that a direct load into
-    // one buffer does not write the buffer being read, and does not make the
-    // LDS reads wait for it.
-    __shared__ __align__(16) unsigned char sG0[2 * kA16Arr];
-    __shared__ __align__(16) unsigned char sG1[2 * kA16Arr];
-    __shared__ __align__(16) unsigned char sG2[2 * kA16Arr];
-    __shared__ float sred[2][NW][kA16NT];
-    constexpr int NE = 16 * EB * NW;   // emitters per pass
-    __shared__ __align__(16) unsigned char sE[2 * NE * kA16ERow];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int row = lane & 15, kk = lane >> 4;
-    const int64_t N = P.N;
-    const int k = loc.k();
-    const int64_t x0 = (int64_t)loc.tile() * kA16NT;
-    const bool vec = ((N & 1) == 0) && (x0 + kA16NT <= N) && (P.m % kA16KC == 0);   // workgroup-uniform
-    const S *gre = Gr + (int64_t)k * P.m * N;
-    const S *gim = Gi + (int64_t)k * P.m * N;
-    const unsigned short *gr = reinterpret_cast<const unsigned short *>(gre);
-    const unsigned short *gi = reinterpret_cast<const unsigned short *>(gim);
-    const S *ar = Ar + (int64_t)k * P.mp * P.mp;
-    const S *ai = Ai + (int64_t)k * P.mp * P.mp;
-    const S *wt = Wt + (int64_t)k * P.mp * P.mp;
-    const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
-    const int nch = P.mp / kA16KC;
-    const unsigned short *grx = gr + x0, *gix = gi + x0;   // tile origin in row 0
-    const unsigned loff = (unsigned)((lane >> 5) * N + 2 * (lane & 31));
-    const int fbase = a16_off(8 * kk, 4 * row);   // column block q: pixels 4 row + q
-    float gp[4] = {0.0f, 0.0f, 0.0f, 0.0f}, hp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    auto buf = [&](auto itag) -> unsigned char * {
-        constexpr int I = decltype(itag)::value % kA16Buf;
-        return I == 0 ? sG0 : (I == 1 ? sG1 : sG2);
-    };
-
-    // this workgroup's emitter passes: group loc.group() of it.npg
-    const int npass = (P.mp + NE - 1) / NE, npg = it.npg, qg = loc.group();
-    const int pass0 = qg * npass / npg, pass1 = (qg + 1) * npass / npg;
-    for (int ec = pass0 * NE; ec < pass1 * NE; ec += NE) {
-        const int e0 = ec + 16 * EB * wave;
-        f4 yr[EB][4], yn[EB][4], z[EB][4];
-#pragma unroll
-        for (int b = 0; b < EB; ++b)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) yr[b][c] = yn[b][c] = z[b][c] = f4{0, 0, 0, 0};
-        auto stage = [&](int c, unsigned char *dst, auto vtag) {
-            if (decltype(vtag)::value)
-                a16_stage_async<NW>(grx, gix, N, c * kA16KC, loff, dst);
-            else
-                a16_stage_regs<NW>(gr, gi, P.m, N, c * kA16KC, x0, dst);
-        };
-        // A rows beyond mp read row mp - 1 (those blocks are never used), so
-        // every wave issues the same loads whatever its rows; a lane's offset
-        // within a chunk is fixed for the pass
-        unsigned aoff[EB];
-#pragma unroll
-        for (int b = 0; b < EB; ++b) aoff[b] = (unsigned)(min(e0 + 16 * b + row, P.mp - 1) * P.mp + 8 * kk);
-        auto load_a = [&](int c, V (&va)[EB], V (&vi)[EB], V (&vw)[EB]) {
-            const int co = c * kA16KC;   // uniform
-#pragma unroll
-            for (int b = 0; b < EB; ++b) {
-                va[b] = *reinterpret_cast<const V *>(ar + co + aoff[b]);
-                vi[b] = *reinterpret_cast<const V *>(ai + co + aoff[b]);
-                if (HESS) vw[b] = *reinterpret_cast<const V *>(wt + co + aoff[b]);
-            }
-        };
-        // Chunks of 32 receivers in which a 16-row block of this wave has a
-        // nonzero weight, as wave-uniform bit masks (nch <= 128), so that
-        // the k-loop itself issues no flag loads.
-        uint64_t cm[2] = {0, 0};
-#pragma unroll
-        for (int b = 0; b < EB; ++b)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int eb = (e0 >> 4) + b, c = 64 * h + lane;
-                const bool on =
-                    eb < P.nb && c < nch && (fl[eb * P.nb + 2 * c] | fl[eb * P.nb + 2 * c + 1]) != 0;
-                cm[h] |= __ballot(on);
-            }
-        // One k-step on tile c, held in buffer c mod 3: wait for tile c and
-        // A(c), then issue A(c + 1) and tile c + 2, then the MFMAs of tile c.
-        // The issue order per wave is A(c), tile c + 1, A(c + 1), tile
-        // c + 2, ..., so only the direct loads of tile c + 1 may still be
-        // outstanding at the wait.  A block whose weights are zero in this
-        // chunk has A = 0 there, so all blocks are computed when any is on.
-        auto kstep = [&](int c, auto itag, V (&va)[EB], V (&vi)[EB], V (&vw)[EB], V (&na)[EB], V (&ni)[EB],
-                         V (&nw)[EB], auto vtag, auto full) {
-            constexpr int I = decltype(itag)::value;
-            constexpr bool FULL = decltype(full)::value;   // c + 2 < nch
-            if (FULL || c + 1 < nch)
-                __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * (kA16KC / 2) / NW));   // tile c + 1
-            else
-                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-            lds_barrier();
-            load_a(min(c + 1, nch - 1), na, ni, nw);
-            // A(c + 1) is issued before the tile's direct loads: the next
-            // step's vmcnt wait then covers it, and the compiler (which takes
-            // direct loads and register loads as completing out of order)
-            // adds no wait of its own
-            __builtin_amdgcn_sched_barrier(0);
-            if (FULL || c + 2 < nch) stage(c + 2, buf(Idx<I + 2>()), vtag);
-            const unsigned char *sb = buf(Idx<I>());
-            const int el = c * kA16KC - ec;   // workgroup-uniform
-            if (el >= 0 && el < NE) a16_keep<NW>(sb, sE, NE, el);
-            __builtin_amdgcn_sched_barrier(0);   // keep the copy's reads apart from the fragment reads
-            if (!(((c < 64 ? cm[0] : cm[1]) >> (c & 63)) & 1)) return;
-            V brs[4], bis[4];
-            a16_frags<V>(sb, fbase, brs);
-            a16_frags<V>(sb + kA16Arr, fbase, bis);
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const V br = brs[cb], bi = bis[cb];
-                V b2;
-                if (HESS) b2 = a16_abs2<S, V>(br, bi);
-#pragma unroll
-                for (int b = 0; b < EB; ++b) {
-                    yr[b][cb] = MM16<S>::mma(va[b], br, yr[b][cb]);
-                    yr[b][cb] = MM16<S>::mma(vi[b], bi, yr[b][cb]);
-                    yn[b][cb] = MM16<S>::mma(va[b], bi, yn[b][cb]);
-                    yn[b][cb] = MM16<S>::mma(neg(vi[b]), br, yn[b][cb]);
-                    if (HESS) z[b][cb] = MM16<S>::mma(vw[b], b2, z[b][cb]);
-                }
-            }
-        };
-        // The k-loop, specialised on the staging path (workgroup-uniform) and
-        // unrolled by six so that the buffer index (period 3) and the A
-        // registers (period 2) are compile-time at every step.  The steady
-        // state has no conditional steps, which keeps the compiler's own
-        // load-counter waits exact; the last two to seven steps follow.
-        auto kloop = [&](auto vtag) {
-            using F = std::true_type;
-            using T = std::false_type;
-            V va[EB], vi[EB], vw[EB], na[EB], ni[EB], nw[EB];
-            lds_barrier();   // the previous pass is done with the tile buffers
-            stage(0, sG0, vtag);
-            load_a(0, va, vi, vw);
-            if (nch > 1) stage(1, sG1, vtag);
-            int c = 0;
-            for (; c + 8 <= nch; c += 6) {
-                kstep(c, Idx<0>(), va, vi, vw, na, ni, nw, vtag, F());
-                kstep(c + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, F());
-                kstep(c + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, F());
-                kstep(c + 3, Idx<0>(), na, ni, nw, va, vi, vw, vtag, F());
-                kstep(c + 4, Idx<1>(), va, vi, vw, na, ni, nw, vtag, F());
-                kstep(c + 5, Idx<2>(), na, ni, nw, va, vi, vw, vtag, F());
-            }
-            if (c < nch) kstep(c, Idx<0>(), va, vi, vw, na, ni, nw, vtag, T());
-            if (c + 1 < nch) kstep(c + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, T());
-            if (c + 2 < nch) kstep(c + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, T());
-            if (c + 3 < nch) kstep(c + 3, Idx<0>(), na, ni, nw, va, vi, vw, vtag, T());
-            if (c + 4 < nch) kstep(c + 4, Idx<1>(), va, vi, vw, na, ni, nw, vtag, T());
-            if (c + 5 < nch) kstep(c + 5, Idx<2>(), na, ni, nw, va, vi, vw, vtag, T());
-            if (c + 6 < nch) kstep(c + 6, Idx<0>(), va, vi, vw, na, ni, nw, vtag, T());
-        };
-        if (vec)
-            kloop(std::true_type());
-        else
-            kloop(std::false_type());
-        // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e (Y =
-        // A conj(G)), with G_e from the pass's copy of its emitter rows (zero
-        // beyond m and N, like the tiles); a lane's four pixels 4 row .. 4 row
-        // + 3 of a row are one 8-byte read
-        lds_barrier();   // every wave's copies are visible
-#pragma unroll
-        for (int b = 0; b < EB; ++b) {
-            if (e0 + 16 * b >= P.m) continue;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = e0 + 16 * b + 4 * kk + i;
-                const unsigned char *se = sE + (e - ec) * kA16ERow + 8 * row;
-                const u32x2 vr = *reinterpret_cast<const u32x2 *>(se);
-                const u32x2 vi = *reinterpret_cast<const u32x2 *>(se + NE * kA16ERow);
-                const bool ok = e < P.m;
-                float ger[4], gei[4];
-                ger[0] = ok ? MM16<S>::bits_to_f(vr.x) : 0.0f;
-                ger[1] = ok ? MM16<S>::bits_to_f(vr.x >> 16) : 0.0f;
-                ger[2] = ok ? MM16<S>::bits_to_f(vr.y) : 0.0f;
-                ger[3] = ok ? MM16<S>::bits_to_f(vr.y >> 16) : 0.0f;
-                gei[0] = ok ? MM16<S>::bits_to_f(vi.x) : 0.0f;
-                gei[1] = ok ? MM16<S>::bits_to_f(vi.x >> 16) : 0.0f;
-                gei[2] = ok ? MM16<S>::bits_to_f(vi.y) : 0.0f;
-                gei[3] = ok ? MM16<S>::bits_to_f(vi.y >> 16) : 0.0f;
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    gp[cb] += ger[cb] * yr[b][cb][i] - gei[cb] * yn[b][cb][i];
-                    if (HESS) hp[cb] += (ger[cb] * ger[cb] + gei[cb] * gei[cb]) * z[b][cb][i];
-                }
-            }
-        }
-    }
-    // the four lane groups of a column, then the waves, in a fixed order
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        float g = gp[cb], h = hp[cb];
-        g += __shfl_xor(g, 16);
-        h += __shfl_xor(h, 16);
-        g += __shfl_xor(g, 32);
-        h += __shfl_xor(h, 32);
-        if (kk == 0) {
-            sred[0][wave][4 * row + cb] = g;
-            sred[1][wave][4 * row + cb] = h;
-        }
-    }
-    __syncthreads();
-    if (tid < kA16NT) {
-        const int64_t x = x0 + tid;
-        if (x < N) {
-            const double gs = (double)gscale[k], as = ascale[k] > 0.0f ? (double)ascale[k] : 1.0;
-            const double g2 = gs * gs;
-            double g = 0.0, h = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                g += (double)sred[0][w][tid];
-                h += (double)sred[1][w][tid];
-            }
-            pg[((int64_t)k * npg + qg) * N + x] = g * (P.cg[k] * g2 * as);
-            if (HESS) ph[((int64_t)k * npg + qg) * N + x] = h * (P.ch[k] * g2 * g2);
-        }
-    }
-}
-
 
 // ------------------------------------------------------------------------
 // 16-bit backprojection with transposing LDS reads.
@@ -998,6 +642,23 @@ __device__ __forceinline__ t16v4 t16_tr(const unsigned char *p) {
     return __builtin_amdgcn_ds_read_tr16_b64_v4i16((t16lds_v4 *)(p));
 }
 
+// The four transposing reads of one column block (rows r and r + 4 of both
+// arrays: immediate offsets 0, 4 rows, one array, one array + 4 rows), with
+// their wait in the same block.  Written as one asm block so that the
+// compiler, which cannot tell these reads from the direct loads filling
+// other buffers, adds no wait on those loads here; the k-step's own vmcnt
+// wait and barrier order the tile with its reads.
+__device__ __forceinline__ void t16_tr4(unsigned addr, t16v4 &a, t16v4 &b, t16v4 &c, t16v4 &d) {
+    asm volatile(
+        "ds_read_b64_tr_b16 %0, %4\n\t"
+        "ds_read_b64_tr_b16 %1, %4 offset:1024\n\t"
+        "ds_read_b64_tr_b16 %2, %4 offset:8192\n\t"
+        "ds_read_b64_tr_b16 %3, %4 offset:9216\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+        : "v"(addr));
+}
+
 template <typename V>
 __device__ __forceinline__ V t16_join(t16v4 lo, t16v4 hi) {
     typedef short s8v __attribute__((ext_vector_type(8)));
@@ -1005,12 +666,14 @@ __device__ __forceinline__ V t16_join(t16v4 lo, t16v4 hi) {
     return __builtin_bit_cast(V, v);
 }
 
-// Aligned full tiles (N a multiple of 8, m a multiple of 32): wave w issues
-// instructions q = 4 w .. 4 w + 3 of the tile's 16 (array q >> 3, rows
-// 4 (q & 7) .. + 3); `goff[j]` is lane l's element offset from the step's
-// first row and pixel for its j-th instruction.
+// Aligned full tiles (N a multiple of 8, m a multiple of 32, 32 N elements
+// within 32-bit offsets): wave w issues instructions q = 4 w .. 4 w + 3 of
+// the tile's 16 (array q >> 3, rows 4 (q & 7) .. + 3); `goff[j]` is lane l's
+// element offset from the step's first row and pixel (`gr`, `gi`: uniform)
+// for its j-th instruction, so the loads take a scalar base and a 32-bit
+// lane offset.
 __device__ __forceinline__ void t16_stage_async(const unsigned short *__restrict__ gr,
-                                                const unsigned short *__restrict__ gi, const int64_t (&goff)[4],
+                                                const unsigned short *__restrict__ gi, const unsigned (&goff)[4],
                                                 unsigned char *sT) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned short *g = (wave >> 1) ? gi : gr;
@@ -1074,7 +737,7 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
     const int64_t x0 = (int64_t)loc.tile() * kT16NT;
     const unsigned short *gr = reinterpret_cast<const unsigned short *>((const S *)it.Gr + (int64_t)k * P.m * N);
     const unsigned short *gi = reinterpret_cast<const unsigned short *>((const S *)it.Gi + (int64_t)k * P.m * N);
-    const bool vec = ((N & 7) == 0) && (x0 + kT16NT <= N) && (P.m % kT16KC == 0) &&
+    const bool vec = ((N & 7) == 0) && (x0 + kT16NT <= N) && (P.m % kT16KC == 0) && N < ((int64_t)1 << 26) &&
                      ((((uintptr_t)gr) | ((uintptr_t)gi)) & 15) == 0;   // workgroup-uniform
     const S *ar = Ar + (int64_t)k * P.mp * P.mp;
     const S *ai = Ai + (int64_t)k * P.mp * P.mp;
@@ -1082,11 +745,11 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
     const uint8_t *fl = flags + (int64_t)k * P.nb * P.nb;
     const int nch = P.mp / kT16KC;
     // lane's element offsets of its four direct-load chunks within a step
-    int64_t goff[4];
+    unsigned goff[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int rl = 4 * (4 * (wave & 1) + j) + (lane >> 4);
-        goff[j] = (int64_t)rl * N + x0 + 8 * ((lane & 15) ^ (t16_pos(rl, 0)));
+        goff[j] = (unsigned)(rl * N) + 8u * (unsigned)((lane & 15) ^ (t16_pos(rl, 0)));
     }
     // transposing-read offsets: rows 8 kk + 4 h + (row >> 2), pixels
     // 16 cb + 4 (row & 3) (h = 0, 1; cb = 0 .. 7)
@@ -1107,10 +770,15 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
     const int pass0 = qg * npass / npg, pass1 = (qg + 1) * npass / npg;
     for (int ec = pass0 * kT16NE; ec < pass1 * kT16NE; ec += kT16NE) {
         const int e0 = ec + 32 * wave;
-        // the pass's emitter chunks [ce0, ce1) come last
-        const int ce0 = ec / kT16KC, ce1 = min(ce0 + kT16NE / kT16KC, nch);
-        const int nlead = nch - (ce1 - ce0);
-        auto chunk = [&](int s) { return s < nlead ? (s < nch - ce1 ? ce1 + s : s - (nch - ce1)) : ce0 + (s - nlead); };
+        // every pass takes the receiver chunks in the same order, so that the
+        // passes of a tile (adjacent workgroups on one XCD) read each G chunk
+        // at about the same time and share it in L2
+        // (opaque to the compiler, which would otherwise keep a strength-
+        // reduced address per unrolled step live in registers)
+        auto chunk = [&](int s) {
+            asm volatile("" : "+s"(s));
+            return s;
+        };
         f4 yr[EB][8], yn[EB][8], z[EB][8];
 #pragma unroll
         for (int b = 0; b < EB; ++b)
@@ -1141,7 +809,7 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
             }
         auto stage = [&](int c, unsigned char *dst, auto vtag) {
             if (decltype(vtag)::value)
-                t16_stage_async(gr + (int64_t)c * kT16KC * N, gi + (int64_t)c * kT16KC * N, goff, dst);
+                t16_stage_async(gr + ((int64_t)c * kT16KC * N + x0), gi + ((int64_t)c * kT16KC * N + x0), goff, dst);
             else
                 t16_stage_regs(gr, gi, P.m, N, c * kT16KC, x0, dst);
         };
@@ -1174,20 +842,13 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
             V nva[EB];
 #pragma unroll
             for (int b = 0; b < EB; ++b) nva[b] = neg(vi[b]);
-            // B fragments one column block ahead of the MFMAs that use them
-            t16v4 f[2][4];
-            auto frag = [&](int cb, t16v4 (&d)[4]) {
-                d[0] = t16_tr(sb + toff[0][cb]);
-                d[1] = t16_tr(sb + toff[1][cb]);
-                d[2] = t16_tr(sb + kT16Arr + toff[0][cb]);
-                d[3] = t16_tr(sb + kT16Arr + toff[1][cb]);
-            };
-            frag(0, f[0]);
+            const unsigned sba = (unsigned)(uintptr_t)(const __attribute__((address_space(3))) unsigned char *)sb;
 #pragma unroll
             for (int cb = 0; cb < 8; ++cb) {
-                if (cb + 1 < 8) frag(cb + 1, f[(cb + 1) & 1]);
-                const V br = t16_join<V>(f[cb & 1][0], f[cb & 1][1]);
-                const V bi = t16_join<V>(f[cb & 1][2], f[cb & 1][3]);
+                t16v4 r0, r1, i0, i1;
+                t16_tr4(sba + (unsigned)toff[0][cb], r0, r1, i0, i1);
+                const V br = t16_join<V>(r0, r1);
+                const V bi = t16_join<V>(i0, i1);
                 V b2;
                 if (HESS) b2 = a16_abs2<S, V>(br, bi);
 #pragma unroll
@@ -1200,10 +861,10 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
                 }
             }
         };
-        // the k-loop, specialised on the staging path and unrolled by eight
-        // (buffer index period 4, A registers period 2); when four steps
-        // remain (nch a multiple of 4) the last ones are compile-time too,
-        // otherwise the last one to five steps decide at run time
+        // the k-loop, specialised on the staging path and unrolled by four
+        // (buffer index period 4, A registers period 2); the steady state
+        // has no conditional steps, the last two to five follow.  (Making
+        // those compile-time as well spills the accumulators.)
         auto kloop = [&](auto vtag) {
             using M3 = std::integral_constant<int, 3>;
             using M2 = std::integral_constant<int, 2>;
@@ -1213,64 +874,59 @@ __global__ void __launch_bounds__(256, HESS ? 1 : 2) k_adjoint16_tr(const A args
             lds_barrier();   // the previous pass is done with the tile buffers
             stage(chunk(0), sG0, vtag);
             load_a(chunk(0), va, vi, vw);
-            if (nch > 1) stage(chunk(1), sG1, vtag);
+            // unconditional (a one-chunk pass stages its chunk twice), so that
+            // the loop is always entered with the same loads in flight and
+            // the compiler's load-counter waits at its head stay exact
+            stage(chunk(min(1, nch - 1)), sG1, vtag);
             int s = 0;
-            for (; s + 12 <= nch; s += 8) {
+            for (; s + 6 <= nch; s += 4) {
                 kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
                 kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
                 kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
                 kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 7, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
             }
-            if (s + 8 == nch) {
-                kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M2());
-                kstep(s + 7, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M1());
-            } else if (s + 4 == nch) {
-                kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
-                kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
-                kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M2());
-                kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M1());
-            } else {
-                if (s + 8 <= nch) {
-                    kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M3());
-                    kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M3());
-                    kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M3());
-                    kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M3());
-                    s += 4;
-                }
-                if (s < nch) kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
-                if (s + 1 < nch) kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M0());
-                if (s + 2 < nch) kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M0());
-                if (s + 3 < nch) kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M0());
-                if (s + 4 < nch) kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
-                if (s + 5 < nch) kstep(s + 5, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M0());
-                if (s + 6 < nch) kstep(s + 6, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M0());
-            }
+            if (s < nch) kstep(s, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
+            if (s + 1 < nch) kstep(s + 1, Idx<1>(), na, ni, nw, va, vi, vw, vtag, M0());
+            if (s + 2 < nch) kstep(s + 2, Idx<2>(), va, vi, vw, na, ni, nw, vtag, M0());
+            if (s + 3 < nch) kstep(s + 3, Idx<3>(), na, ni, nw, va, vi, vw, vtag, M0());
+            if (s + 4 < nch) kstep(s + 4, Idx<0>(), va, vi, vw, na, ni, nw, vtag, M0());
+            // keep the epilogue's work out of the last k-steps' schedule
+            __builtin_amdgcn_sched_barrier(0);
         };
         if (vec)
             kloop(std::true_type());
         else
             kloop(std::false_type());
-        // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e, G_e
-        // from the pass's own tiles (the last steps; zero beyond m and N).
-        // A transposing read at rows 16 b + 4 kk of the wave's chunk gives
+        // fused epilogue: Re sum_e conj(G_e) Y_e and sum_e |G_e|^2 Z_e.  The
+        // tile buffers are free once every wave is done with the k-loop:
+        // wave w copies the chunk of its 32 emitter rows (both arrays) into
+        // buffer w again, and a transposing read at rows 16 b + 4 kk gives
         // lane (kk, row) emitters 16 b + 4 kk + i (i = 0..3) of pixel
-        // 16 cb + row, the layout of the accumulators.
+        // 16 cb + row, the layout of the accumulators (zero beyond m and N).
         __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        lds_barrier();   // every wave's last tiles are in place
+        lds_barrier();
+        unsigned char *se = wave == 0 ? sG0 : (wave == 1 ? sG1 : (wave == 2 ? sG2 : sG3));
+        if (vec) {
+            if (e0 < P.mp) {
+                const unsigned short *g0 = gr + ((int64_t)e0 * N + x0), *g1 = gi + ((int64_t)e0 * N + x0);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int rl = 4 * (q & 7) + (lane >> 4);
+                    const unsigned go = (unsigned)(rl * N) + 8u * (unsigned)((lane & 15) ^ t16_pos(rl, 0));
+                    __builtin_amdgcn_global_load_lds((q >> 3) ? g1 + go : g0 + go,
+                                                     (lds_void_t *)(se + (q >> 3) * kT16Arr + 4 * (q & 7) * kT16Row),
+                                                     16, 0, 0);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        } else {
+            t16_stage_regs(gr, gi, P.m, N, ec, x0, sG0);
+            t16_stage_regs(gr, gi, P.m, N, ec + kT16KC, x0, sG1);
+            t16_stage_regs(gr, gi, P.m, N, ec + 2 * kT16KC, x0, sG2);
+            t16_stage_regs(gr, gi, P.m, N, ec + 3 * kT16KC, x0, sG3);
+        }
+        lds_barrier();
         if (e0 < P.mp) {
-            const int sidx = nlead + (e0 / kT16KC - ce0);   // step that held this wave's chunk
-            const int bi = sidx & 3;
-            const unsigned char *se = bi == 0 ? sG0 : (bi == 1 ? sG1 : (bi == 2 ? sG2 : sG3));
 #pragma unroll
             for (int b = 0; b < EB; ++b) {
 #pragma unroll
@@ -1382,7 +1038,7 @@ static int adj_groups(const rb_geometry *g, rb_dtype dt) {
         return npass >= 4 ? npass : 1;
     }
     if (dt != RB_BF16 && dt != RB_F16) return 1;
-    const int ne = 16 * 2 * 4;   // emitters per pass of k_adjoint16_lds
+    const int ne = kT16NE;   // emitters per pass of k_adjoint16_tr
     const int npass = (pad_m(g->m) + ne - 1) / ne;
     return npass >= 4 ? npass : 1;
 }
