@@ -43,9 +43,9 @@ __global__ void __launch_bounds__(256) k_green(GreenParams P, const double *__re
     const double inv_amax = SCALED ? 1.0 / (double)amp_max[0] : 1.0;
     for (int k = 0; k < P.nf; ++k) {
         double re = 0.0, im = 0.0;
-        // 16-bit storage holds G / (max(a) omega^-1/2): |stored| <= 1.  Its
-        // magnitude factor is taken in FP32 (the table it is rounded to keeps
-        // 8 or 11 bits); the phase stays FP64.
+        // 16-bit storage holds G / (max(a) omega^-1/2): |stored| <= 1.  The
+        // phase is reduced in FP64; its sine, cosine and the magnitude are
+        // taken in FP32 (the table they are rounded to keeps 8 or 11 bits).
         if (cov) {
             if (SCALED)
                 green_value_mag32(P, k, t, (float)(a * inv_amax), (float)b, re, im);
