@@ -11,6 +11,7 @@
 // B_e is a circular window sum that slides by one receiver per emitter.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "born.h"
 #include "common.h"
@@ -26,6 +27,12 @@ template <>
 __device__ __forceinline__ double to_d<__half>(__half v) { return (double)__half2float(v); }
 
 constexpr int kHbThreads = 256;
+
+// four table values loaded together (8 bytes of a 16-bit type)
+template <typename T>
+struct __attribute__((aligned(4 * sizeof(T)))) Vec4 {
+    T v[4];
+};
 
 struct HbParams {
     int m, nf, pb, dmin, zcap;
@@ -57,8 +64,15 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
     const int m = P.m;
     const int t = threadIdx.x;
     const int px = t % PB, grp = t / PB;
-    const int64_t x = (int64_t)blockIdx.x * PB + px;
+    const int64_t xb = (int64_t)blockIdx.x * PB;   // the block's first pixel
+    const int64_t x = xb + px;
     const bool okx = x < P.N;
+    // 16-bit tables load whole, aligned pixel quads (block-uniform; with
+    // 2-byte loads the load phase was bound by instruction issue: 1024
+    // elements / 1100^2 bf16, 17.8 -> 12.6 ms per 4-frequency launch, while
+    // FP32 tables gained nothing and keep one pixel per thread)
+    constexpr bool VQ = PB % 4 == 0 && sizeof(T) == 2;
+    const bool quads = (P.N % 4 == 0) && (xb + PB <= P.N);
     const L *col = sg + px;
     const int half = P.dmin - 1;              // band: r = e + s, |s| <= half
     const bool none = 2 * half + 1 >= m;      // the band covers the ring: nothing selected
@@ -69,6 +83,39 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
         const T *gi = Gi + (int64_t)k * m * P.N + x;
         const L sc = gscale ? (L)gscale[k] * (L)gscale[k] : (L)1;
         L sp = 0;
+        if (VQ && quads) {
+            // four consecutive pixels of a row per thread (one 16- or 8-byte
+            // load per array), two rows in flight; this pixel's partial sum
+            // over rows grp (mod NG) is then read back from LDS
+            constexpr int PQ = PB >= 4 ? PB / 4 : 1, RGN = NT / PQ;
+            const int pq = t % PQ, rg = t / PQ;
+            const T *qr = Gr + (int64_t)k * m * P.N + xb + 4 * pq;
+            const T *qi = Gi + (int64_t)k * m * P.N + xb + 4 * pq;
+            for (int r0 = rg; r0 < m; r0 += 2 * RGN) {
+                Vec4<T> a[2], b[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int r = r0 + u * RGN;
+                    if (r < m) {
+                        a[u] = *reinterpret_cast<const Vec4<T> *>(qr + (int64_t)r * P.N);
+                        b[u] = *reinterpret_cast<const Vec4<T> *>(qi + (int64_t)r * P.N);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int r = r0 + u * RGN;
+                    if (r < m) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const L va = (L)to_d(a[u].v[q]), vb = (L)to_d(b[u].v[q]);
+                            sg[r * PB + 4 * pq + q] = (va * va + vb * vb) * sc;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int r = grp; r < m; r += NG) sp += col[r * PB];
+        } else
         // eight rows in flight per thread
         for (int r0 = grp; r0 < m; r0 += 8 * NG) {
             T va[8], vb[8];

@@ -232,7 +232,7 @@ def _banded_weights(m, nf, dmin, nzero_each, seed):
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("shape", [(37, 29, 40, 5, 6), (64, 64, 64, 8, 40), (21, 50, 97, 12, 0),
                                    (30, 30, 33, 0, 9), (30, 30, 16, 9, 0), (24, 23, 300, 38, 70),
-                                   (10, 11, 1024, 128, 300)])
+                                   (10, 11, 1024, 128, 300), (12, 12, 1024, 128, 300)])
 def test_hessian_banded_matches_oracle(rb, dtype, shape):
     """The banded Hessian diagonal against the oracle's dense sum with the same
     weights, and against the backprojection's Hessian diagonal (dmin = 0: no
