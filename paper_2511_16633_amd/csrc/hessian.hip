@@ -49,22 +49,33 @@ struct HbParams {
 // The zeroed pairs pass through LDS in chunks of 2 NT, packed as
 // e << 16 | r (0xffffffff for an entry out of range), double-buffered: each
 // thread loads its two entries of the next chunk into registers while the
-// block works on the current one, one barrier per chunk.
+// block works on the current one, one barrier per chunk.  With FP32 sums
+// and PB a multiple of 4 (ZQ) a thread takes four pixels of a zeroed pair
+// at once (one 16-byte LDS read per element instead of four 4-byte ones):
+// the pairs are then packed as row offsets (e PQ) << 16 | r PQ in units of
+// four pixels, an entry out of range pointing at a row of zeros after the
+// m rows of g, and the partial sums of the 4 NG pair groups are combined
+// per pixel in group order through the chunk buffer.  Workgroups go to the
+// XCDs in contiguous pixel ranges, so the table rows of neighbouring
+// workgroups (64 or 128 bytes each) share L2 lines.
 template <typename T, typename L, int PB, int NT = kHbThreads>
 __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restrict__ Gr,
                                                           const T *__restrict__ Gi, const float *__restrict__ gscale,
                                                           const int2 *__restrict__ zeroed,
                                                           const int *__restrict__ nzero, double *__restrict__ hd) {
     constexpr int NG = NT / PB;
+    constexpr bool ZQ = PB % 4 == 0 && sizeof(L) == 4;
+    constexpr int PQ = ZQ ? PB / 4 : 1;       // pixel quads per row
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    L *sg = reinterpret_cast<L *>(lds_raw);   // [m][PB]
+    L *sg = reinterpret_cast<L *>(lds_raw);   // [m][PB], with ZQ one more row of zeros
     __shared__ L spart[NT];
     constexpr int ZC = 2 * NT;                // zeroed pairs per chunk
-    __shared__ unsigned sz[2][ZC];            // two chunks of the zeroed-pair list, packed
+    __shared__ __align__(16) unsigned sz[2][ZC];   // two chunks of the zeroed-pair list, packed
     const int m = P.m;
     const int t = threadIdx.x;
     const int px = t % PB, grp = t / PB;
-    const int64_t xb = (int64_t)blockIdx.x * PB;   // the block's first pixel
+    const int64_t xb = xcd_remap(blockIdx.x, gridDim.x) * PB;   // the block's first pixel
+    if (ZQ && t < PB) sg[m * PB + t] = 0;     // ordered before its readers by the barriers below
     const int64_t x = xb + px;
     const bool okx = x < P.N;
     // 16-bit tables load whole, aligned pixel quads (block-uniform; with
@@ -169,26 +180,54 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
         // zeroed pairs, staged through LDS two chunks at a time
         const int nz = nzero ? min(nzero[k], P.zcap) : 0;   // block-uniform
         const int2 *zk = zeroed + (int64_t)k * P.zcap;
+        // (m PQ < 2^16: PB = 32 only for m <= 1024)
+        const unsigned zoff = ((unsigned)(m * PQ) << 16) | (unsigned)(m * PQ);   // the row of zeros
         auto fetch = [&](int c0, unsigned (&reg)[2]) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int i = c0 + h * NT + t;
-                reg[h] = 0xffffffffu;
+                reg[h] = ZQ ? zoff : 0xffffffffu;
                 if (i < nz) {
                     const int2 q = zk[i];
                     if ((unsigned)q.x < (unsigned)m && (unsigned)q.y < (unsigned)m)
-                        reg[h] = ((unsigned)q.x << 16) | (unsigned)q.y;
+                        reg[h] = ZQ ? (((unsigned)(q.x * PQ) << 16) | (unsigned)(q.y * PQ))
+                                    : (((unsigned)q.x << 16) | (unsigned)q.y);
                 }
             }
         };
         unsigned zr[2];
         if (nz > 0) fetch(0, zr);
+        // ZQ: thread (gz, pq) sums pairs gz (mod 4 NG) for pixels 4 pq .. 4 pq + 3
+        const int pq = t % PQ, gz = t / PQ;
+        const float4 *cq = reinterpret_cast<const float4 *>(sg) + pq;
+        float4 zs = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         for (int c0 = 0, b = 0; c0 < nz; c0 += ZC, b ^= 1) {
             sz[b][t] = zr[0];
             sz[b][NT + t] = zr[1];
             __syncthreads();   // chunk b is in LDS; the chunk read two rounds ago is done
             if (c0 + ZC < nz) fetch(c0 + ZC, zr);   // in flight while chunk b is summed
             const int cn = min(ZC, nz - c0);
+            if constexpr (ZQ) {
+                constexpr int NGZ = NT / PQ;
+                for (int i0 = gz; i0 < cn; i0 += 4 * NGZ) {
+                    float4 va[4], vb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u * NGZ;
+                        const unsigned q = i < cn ? sz[b][i] : zoff;
+                        va[u] = cq[q >> 16];
+                        vb[u] = cq[q & 0xffffu];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        zs.x += va[u].x * vb[u].x;
+                        zs.y += va[u].y * vb[u].y;
+                        zs.z += va[u].z * vb[u].z;
+                        zs.w += va[u].w * vb[u].w;
+                    }
+                }
+                continue;
+            }
             for (int i0 = grp; i0 < cn; i0 += 8 * NG) {
                 L pr[8];
 #pragma unroll
@@ -205,6 +244,17 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
             }
         }
         __syncthreads();   // every thread has read spart, sg and sz
+        if constexpr (ZQ) {
+            // the 4 NG pair groups' partial sums, [gz][PB] in the chunk
+            // buffer; pixel px of group grp takes groups 4 grp .. 4 grp + 3
+            float *zp = reinterpret_cast<float *>(&sz[0][0]);
+            if (nz > 0) {
+                reinterpret_cast<float4 *>(zp)[gz * PQ + pq] = zs;
+                __syncthreads();
+                const float *zc = zp + 4 * grp * PB + px;
+                acc -= ((zc[0] + zc[PB]) + zc[2 * PB]) + zc[3 * PB];
+            }
+        }
         spart[t] = acc;
         __syncthreads();
         if (grp == 0) {
@@ -217,8 +267,10 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
     if (grp == 0 && okx) hd[x] += total;
 }
 
-// LDS of [m][PB] values within 32 KiB
-constexpr size_t kHbLds = 32768;
+// LDS of the [m][PB] values (and the row of zeros): within 40 KiB for
+// blocks of 256 threads, 140 KiB for blocks of 1024 (whose static arrays
+// take 20 KiB more)
+constexpr size_t kHbLds = 40960, kHbLdsWide = 143360;
 
 }  // namespace
 
@@ -231,15 +283,16 @@ rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *
     P.N = (int64_t)g->nx * g->ny;
     P.dmin = dmin;
     P.zcap = zcap;
-    // pixels per block: [m][pb] values within 32 KiB (m <= 4096).  For
-    // 256 < m <= 1024 and 32/16-bit tables a block of 1024 threads keeps 32
-    // pixels (up to 128 KiB of LDS): reads of a table row then span 64 or
-    // 128 bytes instead of 16 or 32.
+    // pixels per block: [m][pb] values within 40 KiB.  For 256 < m <= 1024
+    // and 32/16-bit tables a block of 1024 threads keeps 32 pixels (up to
+    // 128 KiB of LDS): reads of a table row then span 64 or 128 bytes
+    // instead of 16 or 32.
     const bool f64 = dt == RB_F64;
     const bool wide = !f64 && P.m > 256 && P.m <= 1024;
     const int pb = wide ? 32 : (f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2)));
-    const size_t lds = (size_t)P.m * pb * (f64 ? sizeof(double) : sizeof(float));
-    if (lds > (wide ? (size_t)131072 : kHbLds)) {
+    const bool zq = !f64 && pb % 4 == 0;   // the kernel's ZQ: one more row
+    const size_t lds = (size_t)(P.m + (zq ? 1 : 0)) * pb * (f64 ? sizeof(double) : sizeof(float));
+    if (lds > (wide ? kHbLdsWide : kHbLds)) {
         set_error("m = %d is too large for the banded Hessian", P.m);
         return RB_EUNSUPPORTED;
     }

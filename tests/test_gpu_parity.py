@@ -232,11 +232,13 @@ def _banded_weights(m, nf, dmin, nzero_each, seed):
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("shape", [(37, 29, 40, 5, 6), (64, 64, 64, 8, 40), (21, 50, 97, 12, 0),
                                    (30, 30, 33, 0, 9), (30, 30, 16, 9, 0), (24, 23, 300, 38, 70),
-                                   (10, 11, 1024, 128, 300), (12, 12, 1024, 128, 300)])
+                                   (10, 11, 1024, 128, 300), (12, 12, 1024, 128, 300),
+                                   (37, 29, 40, 5, 700), (24, 23, 300, 38, 5000), (12, 12, 1024, 128, 9000)])
 def test_hessian_banded_matches_oracle(rb, dtype, shape):
     """The banded Hessian diagonal against the oracle's dense sum with the same
     weights, and against the backprojection's Hessian diagonal (dmin = 0: no
-    band; dmin = 9 at m = 16: the band covers the ring, so hd = 0)."""
+    band; dmin = 9 at m = 16: the band covers the ring, so hd = 0; the last
+    three shapes pass their zeroed pairs through LDS in two to five chunks)."""
     nx, ny, m, dmin, nz = shape
     geom = W.centred_grid(nx, 0.5e-3, m, 12e-3, 1500.0)
     import dataclasses
