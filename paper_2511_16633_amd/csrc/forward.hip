@@ -183,11 +183,12 @@ __device__ __forceinline__ void fwd_block(const FwdParams &P, int &te, int &tr, 
     tri_tile(t, P.ntl, te, tr);
 }
 
-// Forward.  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
+// Forward, tables whose rows are not 16-byte aligned (N not a multiple of
+// 4).  A 64 x 64 (e, r) output tile per workgroup (upper triangle only)
 // over a split of the pixels; waves are 2 x 2, each 32 e x 32 r.  Pixels are
 // consumed 32 at a time: G_e and G_r delta for the tile's rows are staged in
-// LDS as [row][32 px] (stride 36: conflict-free b128 reads), double
-// buffered; a lane reads its eight k values of a row as two b128 reads.
+// LDS as [row][32 px] (stride 36), double buffered through registers; a
+// lane reads its eight k values of a row as two b128 reads.
 constexpr int kFwdKC = 32, kFwdLD = 36;
 
 // One thread's staging registers: eight pixels of one row of G_e and of
@@ -242,9 +243,10 @@ __device__ __forceinline__ void fwd_stage_load(const float *__restrict__ gr, con
     }
 }
 
-__global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float *__restrict__ Gr,
-                                                        const float *__restrict__ Gi,
-                                                        const double *__restrict__ delta, float *__restrict__ part) {
+__global__ void __launch_bounds__(256, 2) k_forward_f32_regs(FwdParams P, const float *__restrict__ Gr,
+                                                             const float *__restrict__ Gi,
+                                                             const double *__restrict__ delta,
+                                                             float *__restrict__ part) {
     __shared__ float sA[2][2][64][kFwdLD];
     __shared__ float sBm[2][2][64][kFwdLD];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -358,6 +360,137 @@ __global__ void __launch_bounds__(256, 2) k_forward_f32(FwdParams P, const float
         step(c + 1, s0, s1, std::false_type());
     }
     if (c < nch) step(c, s1, s0, std::false_type());
+    float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int r = tr * 64 + 32 * wr + 16 * cb + row;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ee = te * 64 + 32 * we + 16 * b + MM<float>::out_row(kk, i);
+                const int64_t o = ((int64_t)ee * P.mp + r) * 2;
+                pp[o] = p1[b][cb][i] - p2[b][cb][i];
+                pp[o + 1] = (p3[b][cb][i] - p1[b][cb][i]) - p2[b][cb][i];
+            }
+        }
+    }
+}
+
+// Forward, FP32 tables with 16-byte aligned rows (N a multiple of 4).  The
+// same tiles and waves as above, pixels consumed 16 at a time, and no
+// staging registers: the tile rows of G_e and G_r (re, im) go from global
+// memory straight into LDS (global_load_lds, 16 bytes per lane), double
+// buffered, next to delta for the step's 16 pixels (as float, zero beyond
+// N), and each wave scales its own B fragments by delta after reading them.
+// Tile rows are 64 bytes, their four 16-byte chunks XOR-swizzled by
+// (row / 2) mod 4 (a fragment read of 16 rows then meets no bank twice);
+// a lane fills slot l mod 4 of row l / 4 and so loads the global chunk that
+// the swizzle puts there.  Rows beyond m read row m - 1 and pixels beyond N
+// read the row's last chunk: their outputs are never read, or delta is
+// zero there.  With 32 KiB of LDS and about 100 registers a CU holds four
+// workgroups; consecutive workgroups are the tiles of one pixel split
+// on one XCD, which then reads each table row of the split from HBM about
+// once.
+constexpr int kFdKC = 16, kFdArr = 64 * 64, kFdBuf = 4 * kFdArr + 64;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ int fd_off(int row, int ch) { return row * 64 + 16 * (ch ^ ((row >> 1) & 3)); }
+
+// out[x] = (float)delta[x] for x < N, 0 for N <= x < n
+__global__ void k_delta_cast(int64_t N, int64_t n, const double *__restrict__ delta, float *__restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) out[x] = x < N ? (float)delta[x] : 0.0f;
+}
+
+__global__ void __launch_bounds__(256, 4) k_forward_f32(FwdParams P, const float *__restrict__ Gr,
+                                                        const float *__restrict__ Gi, const float *__restrict__ df,
+                                                        float *__restrict__ part) {
+    __shared__ __align__(16) unsigned char sm[2][kFdBuf];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int row = lane & 15, kk = lane >> 4;
+    const int we = wave >> 1, wr = wave & 1;
+    int te, tr, split, k;
+    fwd_block(P, te, tr, split, k);
+    if (P.dmin >= 32 && max_circ_dist(P.m, te * 64, 64, tr * 64, 64) < P.dmin) return;
+    const bool idle = fwd_block_idle(P, te, tr, we, wr);
+    const int64_t N = P.N;
+    const int64_t ks = (int64_t)split * P.kchunk;
+    const int64_t ke = std::min<int64_t>(N, ks + P.kchunk);
+    const int nch = (int)((ke - ks + kFdKC - 1) / kFdKC);
+    // this lane's staging slot: tile row rl of each array, global chunk ch
+    const int rl = 16 * wave + (lane >> 2);
+    const int ch = (lane & 3) ^ ((rl >> 1) & 3);
+    const int64_t go = (int64_t)k * P.m * N;
+    const float *ae = Gr + go + (int64_t)std::min(te * 64 + rl, P.m - 1) * N;
+    const float *ai = Gi + go + (int64_t)std::min(te * 64 + rl, P.m - 1) * N;
+    const float *be = Gr + go + (int64_t)std::min(tr * 64 + rl, P.m - 1) * N;
+    const float *bi = Gi + go + (int64_t)std::min(tr * 64 + rl, P.m - 1) * N;
+    auto stage = [&](int c, int buf) {
+        const int64_t xc = ks + (int64_t)c * kFdKC;
+        const int64_t x = std::min<int64_t>(xc + 4 * ch, N - 4);
+        unsigned char *d = sm[buf] + wave * 16 * 64;   // rows 16 wave .. 16 wave + 15
+        __builtin_amdgcn_global_load_lds(ae + x, (lds_void_t *)d, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(ai + x, (lds_void_t *)(d + kFdArr), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(be + x, (lds_void_t *)(d + 2 * kFdArr), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(bi + x, (lds_void_t *)(d + 3 * kFdArr), 16, 0, 0);
+        if (lane == 0)   // delta at pixels xc + 4 wave .. + 3
+            __builtin_amdgcn_global_load_lds(df + xc + 4 * wave, (lds_void_t *)(sm[buf] + 4 * kFdArr + 16 * wave),
+                                             16, 0, 0);
+    };
+    // (a + ib)(c + id) with three real products: P1 = ac, P2 = bd,
+    // P3 = (a + b)(c + d); re = P1 - P2, im = P3 - P1 - P2
+    f4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) p1[b][c] = p2[b][c] = p3[b][c] = f4{0, 0, 0, 0};
+    if (nch > 0) stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) stage(c + 1, buf ^ 1);
+        if (!idle) {
+            const unsigned char *sb = sm[buf];
+            f4 a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int ra = 32 * we + 16 * b + row, rb = 32 * wr + 16 * b + row;
+                a_r[b] = *reinterpret_cast<const f4 *>(sb + fd_off(ra, kk));
+                a_i[b] = *reinterpret_cast<const f4 *>(sb + kFdArr + fd_off(ra, kk));
+                b_r[b] = *reinterpret_cast<const f4 *>(sb + 2 * kFdArr + fd_off(rb, kk));
+                b_i[b] = *reinterpret_cast<const f4 *>(sb + 3 * kFdArr + fd_off(rb, kk));
+            }
+            const f4 dl = *reinterpret_cast<const f4 *>(sb + 4 * kFdArr + 16 * kk);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                b_r[cb] *= dl;
+                b_i[cb] *= dl;
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                float ys[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) ys[cb] = b_r[cb][s4] + b_i[cb][s4];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const float xr = a_r[b][s4], xi = a_i[b][s4];
+                    const float xs = xr + xi;
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        p1[b][cb] = MM<float>::mma(xr, b_r[cb][s4], p1[b][cb]);
+                        p2[b][cb] = MM<float>::mma(xi, b_i[cb][s4], p2[b][cb]);
+                        p3[b][cb] = MM<float>::mma(xs, ys[cb], p3[b][cb]);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // tile c + 1 has landed in LDS
+        __syncthreads();
+    }
+    if (idle) return;
     float *pp = part + ((int64_t)split * P.nf + k) * P.mp * P.mp * 2;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -587,7 +720,6 @@ __global__ void __launch_bounds__(256, 2) k_forward16_lds(FwdParams P, const S *
 #define RB_FWD16_BIG_M 1024
 #endif
 constexpr int kF16BigM = RB_FWD16_BIG_M;
-typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int kFBT = 128;
 constexpr int kFBArr = kFBT * kF16KC * 2;   // one array of a tile (bytes)
 
@@ -757,6 +889,11 @@ static bool fwd16_big(const rb_geometry *g, rb_dtype dt) {
     return (dt == RB_BF16 || dt == RB_F16) && g->m >= kF16BigM && N % 8 == 0;
 }
 
+// The FP32 kernel with direct loads: rows of whole 16-byte chunks.
+static bool fwd32_direct(const rb_geometry *g, rb_dtype dt) {
+    return dt == RB_F32 && ((int64_t)g->nx * g->ny) % 4 == 0;
+}
+
 static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, rb_dtype dt) {
     FwdParams P;
     const int tile = fwd16_big(g, dt) ? kFBT : 64;
@@ -766,9 +903,9 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
     P.nf = nf;
     P.ntl = P.mp / tile;
     const int ntri = P.ntl * (P.ntl + 1) / 2;
-    // about four rounds of resident workgroups (two per CU), rounded down so
-    // the last round is full
-    const int want = 4 * 2 * device_cus();
+    // about four rounds of resident workgroups (two per CU, four for the
+    // FP32 kernel with direct loads), rounded down so the last round is full
+    const int want = 4 * (fwd32_direct(g, dt) ? 4 : 2) * device_cus();
     int nsplit = std::max(1, want / (ntri * nf));
     const int kq = (dt == RB_BF16 || dt == RB_F16) ? 32 : 16;
     int64_t kchunk = (P.N + nsplit - 1) / nsplit;
@@ -803,7 +940,8 @@ static FwdWs carve_fwd(Carver &c, const FwdParams &P, rb_dtype dt, bool big) {
     w.dmax = c.take<double>(1);
     w.dparts = (dt == RB_BF16 || dt == RB_F16) ? c.take<double>(kReduceBlocks) : nullptr;
     w.part = c.take<char>((size_t)P.nsplit * P.nf * P.mp * P.mp * 2 * es);
-    w.df = (dt == RB_BF16 || dt == RB_F16) ? c.take<float>((size_t)P.N + 8) : nullptr;
+    w.df = (dt == RB_BF16 || dt == RB_F16 || (dt == RB_F32 && P.N % 4 == 0)) ? c.take<float>((size_t)P.N + 16)
+                                                                               : nullptr;
     w.np = (P.N + kF16KC - 1) / kF16KC * kF16KC;
     w.dr = big ? (void *)c.take<uint16_t>((size_t)P.nf * P.m * w.np) : nullptr;
     w.di = big ? (void *)c.take<uint16_t>((size_t)P.nf * P.m * w.np) : nullptr;
@@ -842,8 +980,16 @@ rb_status forward_impl(const rb_geometry *g, const void *G_re, const void *G_im,
             break;
         }
         case RB_F32:
-            k_forward_f32<<<dim3(P.ntri, P.nsplit, nf), 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im,
-                                                                      delta, (float *)w.part);
+            if (fwd32_direct(g, dt)) {
+                k_delta_cast<<<blocks_for(P.N + 16, 256), 256, 0, st>>>(P.N, P.N + 16, delta, w.df);
+                RB_LAUNCHED();
+                k_forward_f32<<<nblk, 256, 0, st>>>(P, (const float *)G_re, (const float *)G_im, w.df,
+                                                    (float *)w.part);
+            } else {
+                k_forward_f32_regs<<<dim3(P.ntri, P.nsplit, nf), 256, 0, st>>>(P, (const float *)G_re,
+                                                                               (const float *)G_im, delta,
+                                                                               (float *)w.part);
+            }
             RB_LAUNCHED();
             k_forward_reduce<float><<<blocks_for(tot, 256), 256, 0, st>>>(P, (const float *)w.part, gscale,
                                                                           nullptr, d_out);
