@@ -81,6 +81,47 @@ __device__ __forceinline__ void field(const double2 *__restrict__ sa, const TP &
     a = a0 + fv * (a1 - a0);
 }
 
+// The same evaluation with the four corner records of the last cell kept in
+// registers: a lane reloads them only when its point has left that cell.
+// The four RK4 stages of a step lie within one step length (less than a
+// cell), so most stages of most lanes reuse the corners, and the gathers -
+// the tracer's bottleneck in the vector-memory path - shrink to the lanes
+// that crossed a cell edge.  The values are those of field().
+struct FieldCache {
+    int i = -1, j = -1;   // padded cell whose corners are held (none yet)
+    double2 c00, c10, c01, c11;
+};
+
+__device__ __forceinline__ void field_cached(const double2 *__restrict__ sa, const TP &P, double x, double y,
+                                             FieldCache &fc, double &s, double &gx, double &gy, double &a) {
+#pragma clang fp contract(fast)
+    double u = (x - P.x0) * P.inv_h;
+    double v = (y - P.y0) * P.inv_h;
+    double fi = floor(u), fj = floor(v);
+    const int i = (int)fmin(fmax(fi, -2.0), (double)P.nx) + 2;
+    const int j = (int)fmin(fmax(fj, -2.0), (double)P.ny) + 2;
+    double fu = u - fi, fv = v - fj;
+    if (i != fc.i || j != fc.j) {
+        const int ld = P.nx + 4;
+        const double2 *q = sa + (j * ld + i);
+        fc.c00 = q[0];
+        fc.c10 = q[1];
+        fc.c01 = q[ld];
+        fc.c11 = q[ld + 1];
+        fc.i = i;
+        fc.j = j;
+    }
+    double dx0 = fc.c10.x - fc.c00.x, dx1 = fc.c11.x - fc.c01.x;
+    double s0 = fc.c00.x + fu * dx0;
+    double s1 = fc.c01.x + fu * dx1;
+    s = s0 + fv * (s1 - s0);
+    gx = (dx0 + fv * (dx1 - dx0)) * P.inv_h;
+    gy = (s1 - s0) * P.inv_h;
+    double a0 = fc.c00.y + fu * (fc.c10.y - fc.c00.y);
+    double a1 = fc.c01.y + fu * (fc.c11.y - fc.c01.y);
+    a = a0 + fv * (a1 - a0);
+}
+
 // 1/s from the hardware reciprocal refined by two Newton steps (to within
 // an ulp of the correctly rounded quotient).
 __device__ __forceinline__ double recip(double s) {
@@ -91,10 +132,10 @@ __device__ __forceinline__ double recip(double s) {
 }
 
 __device__ __forceinline__ void rhs(const double2 *__restrict__ sa, const TP &P, const double st[5],
-                                    double d[5]) {
+                                    FieldCache &fc, double d[5]) {
 #pragma clang fp contract(fast)
     double s, gx, gy, a;
-    field(sa, P, st[0], st[1], s, gx, gy, a);
+    field_cached(sa, P, st[0], st[1], fc, s, gx, gy, a);
     const double is = recip(s);
     const double is2 = is * is;
     d[0] = st[2] * is2;
@@ -184,12 +225,13 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
     int cp = 0, cr = 0;                          // wave-uniform list counts
     double xp = 0.0, yp = 0.0;                   // node n - 1 of this ray
     bool alive = valid;   // alive at the current node n
+    FieldCache fc;
     bool last = false;    // the current node is the ray's last
     for (int n = 0; n <= P.nmax; ++n) {
         if (!__any(alive)) break;
         // field at the node (first RK4 stage of the next step)
         double s0 = 1.0, g0x = 0.0, g0y = 0.0, a0 = 0.0;
-        if (alive) field(sa, P, st[0], st[1], s0, g0x, g0y, a0);
+        if (alive) field_cached(sa, P, st[0], st[1], fc, s0, g0x, g0y, a0);
         // neighbours at equal travel time
         const double xl = __shfl_up(st[0], 1), yl = __shfl_up(st[1], 1);
         const double xr = __shfl_down(st[0], 1), yr = __shfl_down(st[1], 1);
@@ -267,13 +309,13 @@ __global__ void __launch_bounds__(256) k_trace(TP P, const double2 *__restrict__
             }
 #pragma unroll
             for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k1[q];
-            rhs(sa, P, t, k2);
+            rhs(sa, P, t, fc, k2);
 #pragma unroll
             for (int q = 0; q < 5; ++q) t[q] = st[q] + hdt * k2[q];
-            rhs(sa, P, t, k3);
+            rhs(sa, P, t, fc, k3);
 #pragma unroll
             for (int q = 0; q < 5; ++q) t[q] = st[q] + dt * k3[q];
-            rhs(sa, P, t, k4);
+            rhs(sa, P, t, fc, k4);
 #pragma unroll
             for (int q = 0; q < 5; ++q) st[q] = st[q] + sixth * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
             last = st[0] * st[0] + st[1] * st[1] > P.rdie2;
