@@ -83,6 +83,25 @@ def selection_weights(m: int, recv_fraction: float, nf: int) -> np.ndarray:
     return np.repeat((d >= dmin).astype(np.float64)[None], nf, axis=0)
 
 
+def zeroed_pairs(m: int, recv_fraction: float, outlier_fraction: float, nf: int, seed: int = 3):
+    """Per frequency, floor(outlier_fraction x selected pairs) seeded random
+    selected (e, r) pairs: the zeroed-pair list of the step's Hessian
+    diagonal in shape and count (timing input), [nf][zcap][2] and [nf]."""
+    dmin = int(math.ceil((1.0 - recv_fraction) * 0.5 * m - 1e-9))
+    e = np.arange(m)[:, None]
+    r = np.arange(m)[None, :]
+    d = np.minimum(np.abs(e - r), m - np.abs(e - r))
+    idx = np.flatnonzero(d >= dmin)
+    nz = int(math.floor(outlier_fraction * idx.size))
+    rng = np.random.default_rng(seed)
+    zl = np.zeros((nf, max(nz, 1), 2), np.int32)
+    for k in range(nf):
+        z = np.sort(rng.choice(idx, size=nz, replace=False))
+        zl[k, :nz, 0] = z // m
+        zl[k, :nz, 1] = z % m
+    return zl, np.full(nf, nz, np.int32)
+
+
 def adjoint_source_hash() -> str:
     h = hashlib.sha256()
     for name in ADJOINT_SOURCES:
@@ -237,7 +256,7 @@ def backprojection_roofline(sw: Sweep, reps: int, workload: str, stages: bool):
     esize = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[dtype]
     alg_bytes = 2 * nf * g.m * N * esize + nf * N * 8   # G (re, im) once + per-frequency gradient partials
     issued = issued_mfma_flop(Wd.cpu().numpy(), N, 3 if dtype == "f32" else 4) if dtype != "f64" else None
-    kname = {"f32": "k_adjoint_f32", "bf16": "k_adjoint16_lds", "f16": "k_adjoint16_lds", "f64": "k_adjoint"}[dtype]
+    kname = {"f32": "k_adjoint_f32", "bf16": "k_adjoint16_tr", "f16": "k_adjoint16_tr", "f64": "k_adjoint"}[dtype]
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[dtype], 4), "traffic": measured_traffic(dtype, workload),
             "kernel": kname + " (fused complex backprojection, gradient as the step runs it)",
@@ -253,6 +272,8 @@ def backprojection_roofline(sw: Sweep, reps: int, workload: str, stages: bool):
     st = None
     if stages:
         dmin = int(math.ceil((1.0 - prob.inv.recv_fraction) * 0.5 * g.m - 1e-9))
+        zl, nzero = zeroed_pairs(g.m, prob.inv.recv_fraction, prob.inv.outlier_fraction, nf)
+        zl, nzero = torch.as_tensor(zl, device=dev), torch.as_tensor(nzero, device=dev)
         fws = torch.empty(rb.forward_workspace_bytes(g, nf, dtype), dtype=torch.uint8, device=dev)
         dout = torch.empty((nf, g.m, g.m, 2), dtype=torch.float64, device=dev)
         st = {
@@ -264,12 +285,12 @@ def backprojection_roofline(sw: Sweep, reps: int, workload: str, stages: bool):
             "born_adjoint_weighted+hdiag": timed_events(torch, stream, lambda: rb.born_adjoint_weighted(
                 g, Gr, Gi, sc, dtype, fs, sw.pms[0], Wd, grad, hd, ws=aws, stream=stream), reps=2),
             "born_hessian_banded": timed_events(torch, stream, lambda: rb.born_hessian_banded(
-                g, Gr, Gi, sc, dtype, fs, dmin, None, None, hd, stream=stream)),
+                g, Gr, Gi, sc, dtype, fs, dmin, zl, nzero, hd, stream=stream)),
             "born_forward": timed_events(torch, stream, lambda: rb.born_forward(g, Gr, Gi, sc, dtype, fs, grad, dout,
                                                                                 ws=fws, stream=stream), reps=2),
         }
         st = {k: round(v, 3) for k, v in st.items()}
-        del fws, dout
+        del fws, dout, zl, nzero
     del tabs, tws, Gr, Gi, sc, Wd, grad, hd, aws
     torch.cuda.empty_cache()
     return roof, st
@@ -519,7 +540,9 @@ def serving_report(dev, n_jobs):
         jobs = [S.Job(jid=sp["job"], arrival=sp["arrival_s"], geom=p.geom, topts=to, inv=p.inv,
                       dtype=dtypes[sp["size_class"]], c_start=p.c_start, alpha0=p.alpha0, freq_sets=p.freq_sets,
                       p_meas=p.p_meas, size_class=sp["size_class"]) for sp, p, to in probs]
+        torch.cuda.empty_cache()
         srv = S.Server(dev, max_running=4)
+        srv.prewarm(jobs)
         served = srv.run(jobs, realtime=True)
         log(f"serving {name}: p50 {served['p50_latency_s']:.3f} s, p99 {served['p99_latency_s']:.3f} s")
         service, same = [], True
@@ -528,9 +551,11 @@ def serving_report(dev, n_jobs):
             a.result = None
             torch.cuda.synchronize()
             t = time.perf_counter()
-            S.run_job(a, dev)
+            S.run_job(a, dev, srv.pool)   # the served run's workspaces, reused as the server reuses them
             service.append(time.perf_counter() - t)
             same = same and a.result is not None and j.result is not None and bool(np.array_equal(a.result, j.result))
+        srv.pool.release()
+        torch.cuda.empty_cache()
         seq = S.sequential_baseline(jobs, service)
         out[name] = {"dtypes": "/".join(dtypes), "budget_gib": round(srv.budget / 2**30, 1),
                      "max_running": srv.max_running, "served": rnd(served), "one_at_a_time": rnd(seq),
@@ -554,8 +579,9 @@ def serving_report(dev, n_jobs):
 
 def serving_burst(dev, n_jobs=40):
     """A burst of small and medium jobs (64- and 256-element rings, FP32),
-    all present at the start: served with the batch lane's grouped launches,
-    served with one stream per job and no grouping, and one at a time."""
+    all present at the start: served with grouped launches in four batch
+    lanes and in one, served with one stream per job and no grouping, and
+    one at a time."""
     import torch
     import workload as W
     from paper_2511_16633_amd import serving as S
@@ -574,31 +600,35 @@ def serving_burst(dev, n_jobs=40):
                    f"{sum(1 for sp, _, _ in probs if sp['size_class'] == 0)} / "
                    f"{sum(1 for sp, _, _ in probs if sp['size_class'] == 1)}, f32"}
     ref = None
-    for name, grouped in (("grouped", True), ("streams", False)):
+    for name, grouped, lanes in (("grouped", True, 4), ("grouped_one_lane", True, 1), ("streams", False, 1)):
         js = jobs()
-        srv = S.Server(dev, max_running=8, grouped=grouped, lane_max=64)
+        torch.cuda.empty_cache()   # every run starts from the same free memory
+        srv = S.Server(dev, max_running=8, grouped=grouped, lane_max=64, lanes=lanes)
         srv.run(js, realtime=False)   # warm-up run
         js = jobs()
         st = srv.run(js, realtime=False)
+        srv.pool.release()
         res[name] = {"makespan_s": round(st["makespan_s"], 4), "p50_latency_s": round(st["p50_latency_s"], 4),
                      "p99_latency_s": round(st["p99_latency_s"], 4), "errors": st["errors"],
                      "grouped_rounds": st["grouped_rounds"], "max_jobs_per_round": st["max_jobs_per_round"]}
         if ref is None:
             ref = [j.result for j in js]
         else:
-            res["same_grouped_and_streams"] = all(np.array_equal(a, j.result) for a, j in zip(ref, js))
+            res["same_grouped_and_streams"] = (res.get("same_grouped_and_streams", True) and
+                                               all(np.array_equal(a, j.result) for a, j in zip(ref, js)))
     alone = jobs()
-    budget = S.Server(dev).budget
-    for j in alone:
-        S.plan(j, budget // 2)
+    torch.cuda.empty_cache()
+    srv = S.Server(dev)
+    srv.prewarm(alone)   # one workspace of each size, as the served runs had
     torch.cuda.synchronize()
     t = time.perf_counter()
     for j in alone:
-        S.run_job(j, dev)
+        S.run_job(j, dev, srv.pool)
     res["one_at_a_time_s"] = round(time.perf_counter() - t, 4)
+    srv.pool.release()
     res["same_alone_and_grouped"] = all(np.array_equal(a, j.result) for a, j in zip(ref, alone))
-    log(f"burst: grouped {res['grouped']['makespan_s']:.3f} s, streams {res['streams']['makespan_s']:.3f} s, "
-        f"one at a time {res['one_at_a_time_s']:.3f} s")
+    log(f"burst: grouped {res['grouped']['makespan_s']:.3f} s (one lane {res['grouped_one_lane']['makespan_s']:.3f} s), "
+        f"streams {res['streams']['makespan_s']:.3f} s, one at a time {res['one_at_a_time_s']:.3f} s")
     torch.cuda.empty_cache()
     return res
 

@@ -8,16 +8,17 @@ job may start while a large one waits for memory.  Every admitted job runs
 its frequency sets low to high, its workspace (ray tables, Green's
 functions) resident on the device from admission to completion.
 
-Two lanes share the budget:
+Two kinds of lanes share the budget:
 
-* the batch lane (rings of up to `group_max_m` elements): one host thread
-  and one HIP stream run rounds; a round takes the next frequency set of
-  every job in the lane and runs them in one call of the library's grouped
-  single step, whose backprojection contractions share launches - a flat
-  grid of (job, frequency, pixel tile) work items - so that small problems
-  fill the GPU together.  Jobs join the lane between rounds as they are
-  admitted and leave it when their last set is done (iteration-level
-  batching);
+* the batch lanes (rings of up to `group_max_m` elements): each of `lanes`
+  lanes has a host thread and a HIP stream of its own and runs rounds; a
+  round takes the next frequency set of every job in the lane and runs them
+  in one call of the library's grouped single step, whose backprojection
+  contractions share launches - a flat grid of (job, frequency, pixel tile)
+  work items - so that small problems fill the GPU together, while the
+  lanes' other kernels (tracing, forward, update) overlap on the device.
+  An admitted job joins the lane with the fewest jobs between rounds and
+  leaves it when its last set is done (iteration-level batching);
 * large rings, which fill the GPU alone, run on a HIP stream and host
   thread of their own each, overlapping with the batch lane and with each
   other on the device.
@@ -79,9 +80,19 @@ class Job:
         return self.t_done - self.arrival
 
 
+def round_workspace(nbytes: int) -> int:
+    """A workspace size rounded up to a multiple of 1/8 of its power of two
+    (at least 64 MiB): jobs of one size class then ask for the same few
+    sizes, so PyTorch's caching allocator hands a finished job's block to
+    the next job instead of allocating and mapping gigabytes anew."""
+    g = max(64 << 20, 1 << max(0, int(nbytes).bit_length() - 4))
+    return -(-int(nbytes) // g) * g
+
+
 def plan(job: Job, cap_bytes: int) -> None:
     """Emitter batch and footprint: the largest batch whose workspace fits
-    `cap_bytes` (all emitters if they fit)."""
+    `cap_bytes` (all emitters if they fit); the workspace size is rounded
+    (round_workspace)."""
     nf = max(len(f) for f in job.freq_sets)
     m = job.geom.m
     batch = 0
@@ -94,39 +105,108 @@ def plan(job: Job, cap_bytes: int) -> None:
     N = job.geom.nx * job.geom.ny
     io = 8 * N * 3 + sum(16 * len(f) * m * m for f in job.freq_sets)
     job.emitter_batch = batch
-    job.ws_bytes = ws
+    job.ws_bytes = round_workspace(ws)
+    ws = job.ws_bytes
     job.footprint = ws + io + (64 << 20)
 
 
-def run_job(job: Job, device: str) -> None:
-    """The whole sweep of one job on a stream of its own (blocking)."""
+class WorkspacePool:
+    """Device workspaces kept from job to job.  A job takes the smallest idle
+    buffer that holds its (rounded) workspace - the library uses what it
+    needs of a larger one - or a new buffer, and gives it back when it
+    finishes.  The pool's buffers, in use or idle, stay within
+    `limit_bytes`: a new buffer that would pass it first frees idle ones
+    (smallest first) back to the device.  So the blocks of large jobs are
+    reused whole instead of being split by small jobs' allocations in
+    PyTorch's caching allocator, and a new allocation does not find the
+    device filled with idle blocks (which makes the allocator free its whole
+    cache and retry, a few hundred milliseconds each time)."""
+
+    def __init__(self, device: str, limit_bytes: int):
+        self.device = device
+        self.limit = int(limit_bytes)
+        self.total = 0        # bytes of the pool's buffers, in use or idle
+        self.idle_bytes = 0
+        self._idle: List[torch.Tensor] = []
+        self._lock = threading.Lock()
+
+    def take(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        freed = False
+        with self._lock:
+            fits = [i for i, b in enumerate(self._idle) if b.numel() >= nbytes]
+            if fits:
+                i = min(fits, key=lambda i: self._idle[i].numel())
+                buf = self._idle.pop(i)
+                self.idle_bytes -= buf.numel()
+                return buf
+            self._idle.sort(key=lambda b: b.numel())
+            while self._idle and self.total + nbytes > self.limit:
+                n = self._idle.pop(0).numel()
+                self.idle_bytes -= n
+                self.total -= n
+                freed = True
+            self.total += nbytes
+        try:
+            if freed:
+                torch.cuda.empty_cache()   # the freed buffers go back to the device
+            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        except torch.cuda.OutOfMemoryError:
+            self.release()
+            torch.cuda.empty_cache()
+            try:
+                return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            except torch.cuda.OutOfMemoryError:
+                with self._lock:
+                    self.total -= nbytes
+                raise
+
+    def give(self, buf: torch.Tensor) -> None:
+        with self._lock:
+            self._idle.append(buf)
+            self.idle_bytes += buf.numel()
+
+    def release(self) -> None:
+        """Drop every idle buffer (PyTorch's cache keeps their blocks)."""
+        with self._lock:
+            self.total -= self.idle_bytes
+            self._idle.clear()
+            self.idle_bytes = 0
+
+
+def run_job(job: Job, device: str, pool: Optional[WorkspacePool] = None) -> None:
+    """The whole sweep of one job on a stream of its own (blocking); the
+    workspace comes from `pool` when one is given."""
     st = torch.cuda.Stream(device=device)   # default priority
     with torch.cuda.stream(st):
         c = torch.as_tensor(job.c_start.reshape(-1), dtype=torch.float64).to(device, non_blocking=False)
         al = None if job.alpha0 is None else torch.as_tensor(job.alpha0.reshape(-1), dtype=torch.float64).to(device)
         pms = [torch.as_tensor(np.stack([p.real, p.imag], -1), dtype=torch.float64).to(device) for p in job.p_meas]
-        ws = torch.empty(max(job.ws_bytes, 256), dtype=torch.uint8, device=device)
+        ws = pool.take(job.ws_bytes) if pool is not None else torch.empty(max(job.ws_bytes, 256),
+                                                                          dtype=torch.uint8, device=device)
         norms = []
         for fs, pm in zip(job.freq_sets, pms):
             norms.append(B.invert_frequency_set(job.geom, job.topts, job.inv, job.dtype, c, al, fs, pm, c, ws=ws,
                                                 stream=st))
         job.result = c.cpu().numpy()
         job.norms = norms
+        st.synchronize()   # the workspace is free for the next job
+        if pool is not None:
+            pool.give(ws)
         del ws, pms, c, al
-    st.synchronize()
 
 
 class _LaneJob:
     """A job in the batch lane: its device inputs and next frequency set."""
 
-    def __init__(self, job: Job, device: str):
+    def __init__(self, job: Job, device: str, pool: WorkspacePool):
         self.job = job
         self.c = torch.as_tensor(job.c_start.reshape(-1), dtype=torch.float64).to(device)
         self.al = (None if job.alpha0 is None
                    else torch.as_tensor(job.alpha0.reshape(-1), dtype=torch.float64).to(device))
         self.pms = [torch.as_tensor(np.stack([p.real, p.imag], -1), dtype=torch.float64).to(device)
                     for p in job.p_meas]
-        self.ws = torch.empty(max(job.ws_bytes, 256), dtype=torch.uint8, device=device)
+        self.ws = pool.take(job.ws_bytes)
         self.k = 0
         self.norms: List[float] = []
 
@@ -137,24 +217,39 @@ class _LaneJob:
 
 
 class Server:
-    """Admission by device-memory footprint; the batch lane for small rings
-    (grouped rounds on one stream), one stream and host thread per large
+    """Admission by device-memory footprint; batch lanes for small rings
+    (grouped rounds, one stream each), one stream and host thread per large
     running job."""
 
     def __init__(self, device: str = "cuda:0", budget_bytes: Optional[int] = None, max_running: int = 4,
-                 grouped: bool = True, group_max_m: int = 256, lane_max: int = 16):
+                 grouped: bool = True, group_max_m: int = 256, lane_max: int = 16, lanes: int = 4):
         self.device = device
         if budget_bytes is None:
-            free, _ = torch.cuda.mem_get_info(torch.device(device))
-            budget_bytes = int(0.75 * free)
+            # free device memory, counting blocks PyTorch holds cached but unused
+            dev = torch.device(device)
+            free, _ = torch.cuda.mem_get_info(dev)
+            cached = torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev)
+            budget_bytes = int(0.75 * (free + cached))
         self.budget = int(budget_bytes)
         self.max_running = int(max_running)
         self.grouped = bool(grouped)
         self.group_max_m = int(group_max_m)
-        self.lane_max = int(lane_max)
+        self.lane_max = int(lane_max)   # jobs in all batch lanes together
+        self.lanes = max(1, int(lanes))
+        # workspaces kept between jobs, within the budget
+        self.pool = WorkspacePool(device, self.budget)
         self.rounds = 0            # grouped calls made by the last run
         self.round_sizes: List[int] = []
         self.round_rings: List[int] = []   # distinct ring sizes per round
+
+    def prewarm(self, jobs: List[Job]) -> None:
+        """Plan `jobs` and allocate one idle workspace of each of their sizes
+        (a server started ahead of its traffic)."""
+        for j in jobs:
+            if not j.footprint:
+                plan(j, self.budget // 2)
+        for n in sorted({j.ws_bytes for j in jobs}):
+            self.pool.give(self.pool.take(n))
 
     def in_lane(self, job: Job) -> bool:
         return self.grouped and job.geom.m <= self.group_max_m
@@ -171,7 +266,9 @@ class Server:
         pending = sorted(jobs, key=lambda j: (j.arrival, j.jid))
         waiting: List[Job] = []
         running = {}
-        lane_new: List[Job] = []   # admitted to the batch lane, not yet in a round
+        lane_new: List[List[Job]] = [[] for _ in range(self.lanes)]   # admitted, not yet in a round
+        lane_jobs = [0] * self.lanes   # jobs in each lane
+        lane_of = {}
         lane_count = 0
         used = 0
         stop = False
@@ -189,36 +286,38 @@ class Server:
             with cond:
                 job.t_done = now()
                 used -= job.footprint
-                if self.in_lane(job):
+                if job.jid in lane_of:
                     lane_count -= 1
+                    lane_jobs[lane_of.pop(job.jid)] -= 1
                 running.pop(job.jid, None)
                 cond.notify_all()
 
-        def batcher():
-            """Rounds of the batch lane: the next set of every job in it, in
+        def batcher(li: int):
+            """Rounds of batch lane li: the next set of every job in it, in
             one grouped call on the lane's stream."""
             st = torch.cuda.Stream(device=self.device)   # default priority
             active: List[_LaneJob] = []
             with torch.cuda.stream(st):
                 while True:
                     with cond:
-                        while not lane_new and not active and not stop:
+                        while not lane_new[li] and not active and not stop:
                             cond.wait()
-                        if not lane_new and not active and stop:
+                        if not lane_new[li] and not active and stop:
                             return
-                        fresh = list(lane_new)
-                        lane_new.clear()
+                        fresh = list(lane_new[li])
+                        lane_new[li].clear()
                     for job in fresh:
                         try:
-                            active.append(_LaneJob(job, self.device))
+                            active.append(_LaneJob(job, self.device, self.pool))
                         except Exception as exc:  # recorded; the stream goes on
                             job.error = f"{type(exc).__name__}: {exc}"
                             finish(job)
                     if not active:
                         continue
-                    self.rounds += 1
-                    self.round_sizes.append(len(active))
-                    self.round_rings.append(len({a.job.geom.m for a in active}))
+                    with cond:
+                        self.rounds += 1
+                        self.round_sizes.append(len(active))
+                        self.round_rings.append(len({a.job.geom.m for a in active}))
                     try:
                         norms = B.invert_frequency_sets_grouped([a.call() for a in active], stream=st)
                         err = None
@@ -237,21 +336,25 @@ class Server:
                     for a in done:
                         active.remove(a)
                         if a.job.error is None:
-                            a.job.result = a.c.cpu().numpy()
+                            a.job.result = a.c.cpu().numpy()   # synchronises the lane's stream
                             a.job.norms = a.norms
+                        else:
+                            st.synchronize()
+                        self.pool.give(a.ws)
                         del a.ws, a.pms, a.c, a.al
                         finish(a.job)
 
         def worker(job: Job):
             try:
-                run_job(job, self.device)
+                run_job(job, self.device, self.pool)
             except Exception as exc:  # recorded; the stream goes on
                 job.error = f"{type(exc).__name__}: {exc}"
             finish(job)
 
         threads = []
-        lane = threading.Thread(target=batcher, daemon=True)
-        lane.start()
+        lane_threads = [threading.Thread(target=batcher, args=(li,), daemon=True) for li in range(self.lanes)]
+        for th in lane_threads:
+            th.start()
         with cond:
             while pending or waiting or running:
                 t = now()
@@ -271,7 +374,10 @@ class Server:
                         running[job.jid] = job
                         if lane_job:
                             lane_count += 1
-                            lane_new.append(job)
+                            li = min(range(self.lanes), key=lambda i: (lane_jobs[i], i))
+                            lane_jobs[li] += 1
+                            lane_of[job.jid] = li
+                            lane_new[li].append(job)
                             cond.notify_all()
                         else:
                             th = threading.Thread(target=worker, args=(job,), daemon=True)
@@ -284,7 +390,8 @@ class Server:
                     cond.wait(timeout=timeout if timeout is not None else 1.0)
             stop = True
             cond.notify_all()
-        lane.join()
+        for th in lane_threads:
+            th.join()
         for th in threads:
             th.join()
         out = summarize(jobs, now())

@@ -1,7 +1,8 @@
 """Serving loop on the GPU: jobs of different ring sizes and contraction
 types are served together - the small rings in grouped rounds of the batch
-lane (their backprojections in shared launches), the large ring on its own
-stream - and every result is bit-for-bit the one the job gives alone.  The mix holds a 16-bit job of the
+lanes (their backprojections in shared launches), the large ring on its own
+stream - and every result is bit-for-bit the one the job gives alone, with
+one batch lane and with four.  The mix holds a 16-bit job of the
 large-ring class (1040 elements around a small grid, BF16 contractions with
 the 128 x 128-tile forward), whose served image is also checked against the
 FP64 oracle at equal accuracy (rel-L2 <= 1e-2, max |dc| <= 1 m/s)."""
@@ -56,7 +57,7 @@ def test_mixed_results_equal_alone(serving):
     S = serving
     print("[gpu-case] serving: 7 jobs alone, then mixed", flush=True)
     alone = _jobs(S)
-    srv = S.Server(DEV, max_running=4)
+    srv = S.Server(DEV, max_running=4, lanes=1)   # one batch lane: the 64- and 256-element rings share rounds
     for j in alone:
         S.plan(j, srv.budget // 2)
         S.run_job(j, DEV)
@@ -72,6 +73,13 @@ def test_mixed_results_equal_alone(serving):
         assert np.array_equal(a.result, b.result), f"job {a.jid} differs alone and mixed"
         assert a.norms == b.norms
         assert not np.array_equal(b.result, b.c_start.reshape(-1))   # the model was updated
+    # the same stream with four batch lanes: still bitwise the jobs' alone results
+    print("[gpu-case] serving: mixed, four batch lanes", flush=True)
+    mixed4 = _jobs(S)
+    stats4 = S.Server(DEV, max_running=4, lanes=4).run(mixed4, realtime=False)
+    assert stats4["errors"] == 0, [j.error for j in mixed4]
+    for a, b in zip(alone, mixed4):
+        assert np.array_equal(a.result, b.result), f"job {a.jid} differs alone and with four lanes"
     # several jobs were on the device at once
     spans = sorted((j.t_admit, j.t_done) for j in mixed)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
