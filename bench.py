@@ -579,9 +579,10 @@ def serving_report(dev, n_jobs):
 
 def serving_burst(dev, n_jobs=40):
     """A burst of small and medium jobs (64- and 256-element rings, FP32),
-    all present at the start: served with grouped launches in four batch
-    lanes and in one, served with one stream per job and no grouping, and
-    one at a time."""
+    all present at the start: served as the server does by default (the
+    64-element rings in four batch lanes of grouped rounds, the 256-element
+    rings on streams of their own), with every job in one lane of grouped
+    rounds, with one stream per job and no grouping, and one at a time."""
     import torch
     import workload as W
     from paper_2511_16633_amd import serving as S
@@ -600,21 +601,23 @@ def serving_burst(dev, n_jobs=40):
                    f"{sum(1 for sp, _, _ in probs if sp['size_class'] == 0)} / "
                    f"{sum(1 for sp, _, _ in probs if sp['size_class'] == 1)}, f32"}
     ref = None
-    for name, grouped, lanes in (("grouped", True, 4), ("grouped_one_lane", True, 1), ("streams", False, 1)):
+    for name, kw in (("served", {}), ("grouped_up_to_256", dict(group_max_m=256, lanes=1)),
+                     ("streams", dict(grouped=False))):
         js = jobs()
         torch.cuda.empty_cache()   # every run starts from the same free memory
-        srv = S.Server(dev, max_running=8, grouped=grouped, lane_max=64, lanes=lanes)
+        srv = S.Server(dev, max_running=8, lane_max=64, **kw)
         srv.run(js, realtime=False)   # warm-up run
         js = jobs()
         st = srv.run(js, realtime=False)
         srv.pool.release()
         res[name] = {"makespan_s": round(st["makespan_s"], 4), "p50_latency_s": round(st["p50_latency_s"], 4),
                      "p99_latency_s": round(st["p99_latency_s"], 4), "errors": st["errors"],
+                     "first_error": st["first_error"],
                      "grouped_rounds": st["grouped_rounds"], "max_jobs_per_round": st["max_jobs_per_round"]}
         if ref is None:
             ref = [j.result for j in js]
         else:
-            res["same_grouped_and_streams"] = (res.get("same_grouped_and_streams", True) and
+            res["same_in_every_mode"] = (res.get("same_in_every_mode", True) and
                                                all(np.array_equal(a, j.result) for a, j in zip(ref, js)))
     alone = jobs()
     torch.cuda.empty_cache()
@@ -627,8 +630,9 @@ def serving_burst(dev, n_jobs=40):
     res["one_at_a_time_s"] = round(time.perf_counter() - t, 4)
     srv.pool.release()
     res["same_alone_and_grouped"] = all(np.array_equal(a, j.result) for a, j in zip(ref, alone))
-    log(f"burst: grouped {res['grouped']['makespan_s']:.3f} s (one lane {res['grouped_one_lane']['makespan_s']:.3f} s), "
-        f"streams {res['streams']['makespan_s']:.3f} s, one at a time {res['one_at_a_time_s']:.3f} s")
+    log(f"burst: served {res['served']['makespan_s']:.3f} s (p50 {res['served']['p50_latency_s']:.3f} s), "
+        f"all grouped {res['grouped_up_to_256']['makespan_s']:.3f} s, streams {res['streams']['makespan_s']:.3f} s "
+        f"(p50 {res['streams']['p50_latency_s']:.3f} s), one at a time {res['one_at_a_time_s']:.3f} s")
     torch.cuda.empty_cache()
     return res
 

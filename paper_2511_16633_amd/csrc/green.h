@@ -43,10 +43,11 @@ __device__ __forceinline__ void green_value_mag32(const GreenParams &P, int k, d
 }
 
 // Green's tables written by the rasteriser's write pass in place of the
-// T/amp/att tables (32/64-bit storage): G [nf][m][N].
+// T/amp/att tables: G [nf][m][N] in FP64, FP32 (scale 1) or BF16 (G /
+// omega^-1/2, scale omega^-1/2 per frequency).
 struct GreenOut {
     GreenParams P;
-    rb_dtype dt;   // RB_F32 or RB_F64
+    rb_dtype dt;   // RB_F32, RB_F64 or RB_BF16
     void *Gr, *Gi;
 };
 size_t green_workspace_bytes();

@@ -767,6 +767,13 @@ static rb_status set_open(SetCtx &S, const rb_geometry *g, const rb_trace_opts *
 
 // 1-2. rays, tables and Green's functions in the current model; residual,
 // data weights and the list of zeroed pairs
+// scale[k] = omega_k^-1/2: the per-frequency scale of BF16 Green's tables
+// written as G / omega^-1/2
+__global__ void k_rsq_scales(GreenParams P, float *__restrict__ scale) {
+    const int k = threadIdx.x;
+    if (k < P.nf) scale[k] = (float)P.rsq[k];
+}
+
 static rb_status set_linearise(SetCtx &S, hipStream_t st) {
     const rb_geometry *g = S.g;
     const rb_invert_opts *o = S.o;
@@ -781,11 +788,20 @@ static rb_status set_linearise(SetCtx &S, hipStream_t st) {
     k_support_disc<<<blocks_for(N, 256), 256, 0, st>>>(g->nx, g->ny, g->h, g->x0, g->y0, rs, w.S);
     RB_LAUNCHED();
     rb_tables tab{w.T, w.amp, w.att, w.Trx, w.amp_rx, w.att_rx};
-    if (o->dtype == RB_F32 || o->dtype == RB_F64) {
-        // 32/64-bit G needs no global scale: the rasteriser writes it directly
-        GreenOut gout{green_params(S.freqs, nf, o->y_pow), o->dtype, w.Gr, w.Gi};
+    if (o->dtype != RB_F16) {
+        // 32/64-bit and BF16 G need no global scale: the rasteriser writes it
+        // directly (BF16 as G / omega^-1/2, whose range BF16 holds); FP16,
+        // with its 5-bit exponent, is normalised by the largest amplitude
+        // in a pass of its own
+        const GreenParams GP = green_params(S.freqs, nf, o->y_pow);
+        GreenOut gout{GP, o->dtype, w.Gr, w.Gi};
         RB_TRY(trace_rays_impl(g, S.t, w.s, S.alpha0, &tab, S.scratch, S.scratch_bytes, st, w.S, &gout));
-        RB_TRY(fill_f32(w.gscale, 1.0f, nf, st));
+        if (o->dtype == RB_BF16) {
+            k_rsq_scales<<<1, RB_MAX_NF, 0, st>>>(GP, w.gscale);
+            RB_LAUNCHED();
+        } else {
+            RB_TRY(fill_f32(w.gscale, 1.0f, nf, st));
+        }
     } else {
         RB_TRY(trace_rays_impl(g, S.t, w.s, S.alpha0, &tab, S.scratch, S.scratch_bytes, st, w.S, nullptr));
         Carver gc(S.scratch, S.scratch_bytes);

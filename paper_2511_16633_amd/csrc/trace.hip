@@ -572,8 +572,8 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const float
         auto uncovered = [&]() {
             if constexpr (GREEN) {
                 for (int k = 0; k < GP.nf; ++k) {
-                    Gr[k * gstride + gofs + idx] = (GS)0;
-                    Gi[k * gstride + gofs + idx] = (GS)0;
+                    Gr[k * gstride + gofs + idx] = GS(0.0f);
+                    Gi[k * gstride + gofs + idx] = GS(0.0f);
                 }
             } else {
                 Tout[idx] = __longlong_as_double(0x7ff8000000000000ll);
@@ -621,9 +621,18 @@ __global__ void k_raster_write(TP P, const double2 *__restrict__ XY, const float
         if constexpr (GREEN) {
             for (int k = 0; k < GP.nf; ++k) {
                 double re, im;
-                green_value(GP, k, tv, (double)av * GP.rsq[k], (double)bv, re, im);
-                Gr[k * gstride + gofs + idx] = (GS)re;
-                Gi[k * gstride + gofs + idx] = (GS)im;
+                if constexpr (std::is_same<GS, __hip_bfloat16>::value) {
+                    // BF16 tables hold G / omega^-1/2 (scale rsq per
+                    // frequency): BF16 keeps FP32's exponent range, so no
+                    // normalisation by the largest amplitude is needed
+                    green_value_mag32(GP, k, tv, av, bv, re, im);
+                    Gr[k * gstride + gofs + idx] = __float2bfloat16((float)re);
+                    Gi[k * gstride + gofs + idx] = __float2bfloat16((float)im);
+                } else {
+                    green_value(GP, k, tv, (double)av * GP.rsq[k], (double)bv, re, im);
+                    Gr[k * gstride + gofs + idx] = (GS)re;
+                    Gi[k * gstride + gofs + idx] = (GS)im;
+                }
             }
         } else {
             Tout[idx] = tv;
@@ -770,6 +779,10 @@ rb_status trace_rays_impl(const rb_geometry *g, const rb_trace_opts *t, const do
             k_raster_write<false, float><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, nullptr, nullptr, cover,
                                                              gout->P, (float *)gout->Gr, (float *)gout->Gi,
                                                              (int64_t)e0 * N);
+        else if (gout && gout->dt == RB_BF16)
+            k_raster_write<false, __hip_bfloat16><<<gw, 256, 0, st>>>(
+                P, w.XY, w.AB, w.rxy, akey, nullptr, nullptr, cover, gout->P, (__hip_bfloat16 *)gout->Gr,
+                (__hip_bfloat16 *)gout->Gi, (int64_t)e0 * N);
         else if (gout)
             k_raster_write<false, double><<<gw, 256, 0, st>>>(P, w.XY, w.AB, w.rxy, akey, nullptr, nullptr, cover,
                                                               gout->P, (double *)gout->Gr, (double *)gout->Gi,

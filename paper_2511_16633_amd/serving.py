@@ -10,18 +10,19 @@ functions) resident on the device from admission to completion.
 
 Two kinds of lanes share the budget:
 
-* the batch lanes (rings of up to `group_max_m` elements): each of `lanes`
-  lanes has a host thread and a HIP stream of its own and runs rounds; a
-  round takes the next frequency set of every job in the lane and runs them
+* the batch lanes (rings of up to `group_max_m` elements, 64 by default:
+  larger rings fill the GPU well enough alone that overlapping them on
+  streams of their own serves a burst faster than grouping them): each of
+  `lanes` lanes has a host thread and a HIP stream of its own and runs
+  rounds; a round takes the next frequency set of every job in the lane and runs them
   in one call of the library's grouped single step, whose backprojection
   contractions share launches - a flat grid of (job, frequency, pixel tile)
   work items - so that small problems fill the GPU together, while the
   lanes' other kernels (tracing, forward, update) overlap on the device.
   An admitted job joins the lane with the fewest jobs between rounds and
   leaves it when its last set is done (iteration-level batching);
-* large rings, which fill the GPU alone, run on a HIP stream and host
-  thread of their own each, overlapping with the batch lane and with each
-  other on the device.
+* larger rings run on a HIP stream and host thread of their own each,
+  overlapping with the batch lanes and with each other on the device.
 
 A job's result depends only on its own inputs (private workspace; the
 grouped launches compute each work item as the single-job launch does, and
@@ -112,9 +113,9 @@ def plan(job: Job, cap_bytes: int) -> None:
 
 class WorkspacePool:
     """Device workspaces kept from job to job.  A job takes the smallest idle
-    buffer that holds its (rounded) workspace - the library uses what it
-    needs of a larger one - or a new buffer, and gives it back when it
-    finishes.  The pool's buffers, in use or idle, stay within
+    buffer that holds its (rounded) workspace and is at most 1/4 larger -
+    the library uses what it needs of a larger one - or a new buffer, and
+    gives it back when it finishes.  The pool's buffers, in use or idle, stay within
     `limit_bytes`: a new buffer that would pass it first frees idle ones
     (smallest first) back to the device.  So the blocks of large jobs are
     reused whole instead of being split by small jobs' allocations in
@@ -134,7 +135,9 @@ class WorkspacePool:
         nbytes = max(int(nbytes), 256)
         freed = False
         with self._lock:
-            fits = [i for i, b in enumerate(self._idle) if b.numel() >= nbytes]
+            # at most 1/4 larger than asked: admission counts the job's own
+            # workspace size, so a small job must not hold a large block
+            fits = [i for i, b in enumerate(self._idle) if nbytes <= b.numel() <= nbytes + nbytes // 4]
             if fits:
                 i = min(fits, key=lambda i: self._idle[i].numel())
                 buf = self._idle.pop(i)
@@ -222,7 +225,7 @@ class Server:
     running job."""
 
     def __init__(self, device: str = "cuda:0", budget_bytes: Optional[int] = None, max_running: int = 4,
-                 grouped: bool = True, group_max_m: int = 256, lane_max: int = 16, lanes: int = 4):
+                 grouped: bool = True, group_max_m: int = 64, lane_max: int = 16, lanes: int = 4):
         self.device = device
         if budget_bytes is None:
             # free device memory, counting blocks PyTorch holds cached but unused
@@ -404,7 +407,8 @@ class Server:
 def summarize(jobs: List[Job], makespan: float) -> dict:
     lat = np.array([j.latency for j in jobs])
     units = sum(j.units for j in jobs)
-    return {"jobs": len(jobs), "errors": sum(1 for j in jobs if j.error),
+    errs = [f"job {j.jid}: {j.error}" for j in jobs if j.error]
+    return {"jobs": len(jobs), "errors": len(errs), "first_error": errs[0] if errs else None,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(lat.mean()), "makespan_s": float(makespan),
             "jobs_per_s": len(jobs) / makespan, "gpixel_pair_freq_per_s": units / makespan / 1e9}

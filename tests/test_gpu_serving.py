@@ -57,7 +57,7 @@ def test_mixed_results_equal_alone(serving):
     S = serving
     print("[gpu-case] serving: 7 jobs alone, then mixed", flush=True)
     alone = _jobs(S)
-    srv = S.Server(DEV, max_running=4, lanes=1)   # one batch lane: the 64- and 256-element rings share rounds
+    srv = S.Server(DEV, max_running=4, lanes=1, group_max_m=256)   # one batch lane: 64- and 256-element rings share rounds
     for j in alone:
         S.plan(j, srv.budget // 2)
         S.run_job(j, DEV)
@@ -76,7 +76,7 @@ def test_mixed_results_equal_alone(serving):
     # the same stream with four batch lanes: still bitwise the jobs' alone results
     print("[gpu-case] serving: mixed, four batch lanes", flush=True)
     mixed4 = _jobs(S)
-    stats4 = S.Server(DEV, max_running=4, lanes=4).run(mixed4, realtime=False)
+    stats4 = S.Server(DEV, max_running=4, lanes=4, group_max_m=256).run(mixed4, realtime=False)
     assert stats4["errors"] == 0, [j.error for j in mixed4]
     for a, b in zip(alone, mixed4):
         assert np.array_equal(a.result, b.result), f"job {a.jid} differs alone and with four lanes"
