@@ -4,7 +4,9 @@ grid at 0.2 mm, four frequencies per set) in the launch configuration
 pixels (bf16 and f32 tables) and the bf16 forward at sampled pairs (the
 128 x 128-tile kernel), against the oracle computed for those outputs one by
 one.  The tables are seeded random draws made on the host in blocks of
-emitters (the oracle keeps the columns and rows it needs)."""
+emitters (the oracle keeps the columns and rows it needs).  Then the ray
+tables at sampled emitters, and one whole frequency set in FP32 and BF16
+against the same set in FP64."""
 import math
 import sys
 
@@ -160,3 +162,41 @@ def test_large_tables_sampled_emitters(rb):
         msk = invert.receiver_mask(g.m)[e]
         assert np.all(np.isfinite(Trg[msk])) and np.all(np.isfinite(Tr[0][msk]))
         assert np.max(np.abs(Trg[msk] - Tr[0][msk])) <= 1e-9
+
+
+def test_large_frequency_set_fp32_and_bf16_against_fp64(rb):
+    """One whole linearised frequency set of the large instance (set 0 of the
+    breast phantom with straight-ray data, the launch configuration the bench
+    times: 128 emitters per tracing batch): the FP32 and BF16 steps against
+    the FP64 step, whose contractions run on the FP64 matrix cores and which
+    matches the oracle at the smaller sizes (test_gpu_fullsize,
+    test_gpu_parity).  The FP64 oracle itself would need about five minutes
+    of 16 CPU threads for this set.  Bounds: the contraction types' image
+    tolerances (FP32 rel-L2 1e-4 and max |dc| 0.01 m/s; BF16 1e-2 and
+    1 m/s)."""
+    prob = W.breast_ring1024(with_data=False)
+    g = prob.geom
+    fs = prob.freq_sets[0]
+    _say("large frequency set: straight-ray data of set 0 (1024 elements, 1100^2)")
+    pm = W.data_for_sets(g, prob.c_true, prob.alpha0, [fs])[0]
+    topts = W.resolve_trace_opts(g, prob.c_start, prob.trace.n_rays)
+    c_in = torch.as_tensor(prob.c_start.reshape(-1), dtype=torch.float64, device=DEV)
+    al = torch.as_tensor(prob.alpha0.reshape(-1), dtype=torch.float64, device=DEV)
+    pmt = torch.as_tensor(np.stack([pm.real, pm.imag], -1), dtype=torch.float64, device=DEV)
+    dc = {}
+    for dt in ("f64", "f32", "bf16"):
+        _say(f"large frequency set {dt}")
+        ws = torch.empty(rb.invert_workspace_bytes(g, topts, len(fs), dt, 128), dtype=torch.uint8, device=DEV)
+        c_out = torch.empty_like(c_in)
+        rb.invert_frequency_set(g, topts, prob.inv, dt, c_in, al, fs, pmt, c_out, ws=ws)
+        dc[dt] = (c_out - c_in).cpu().numpy()
+        del ws, c_out
+        torch.cuda.empty_cache()
+    ref = dc["f64"]
+    assert np.all(np.isfinite(ref)) and np.linalg.norm(ref) > 0.0
+    for dt, (rel_b, max_b) in (("f32", (1e-4, 0.01)), ("bf16", (1e-2, 1.0))):
+        d = dc[dt] - ref
+        rel = float(np.linalg.norm(d) / np.linalg.norm(ref))
+        mx = float(np.abs(d).max())
+        _say(f"large frequency set {dt} vs f64: rel-L2 {rel:.3e}, max |dc diff| {mx:.3e} m/s")
+        assert rel <= rel_b and mx <= max_b, (dt, rel, mx)
