@@ -433,43 +433,44 @@ def ring256_leg(args, dev):
     sw.ws = None
     torch.cuda.empty_cache()
 
-    # the linear subproblem of set 0 solved by CG instead of the single step
-    cws = torch.empty(max(rb.invert_cg_workspace_bytes(g, topts, nf, "f32", 0), ws_bytes), dtype=torch.uint8,
-                      device=dev)
-    ccg = torch.empty_like(c_start)
+    if args.cg_iters > 0:   # --cg-iters 0 skips the CG and asymptotic-weight measurements
+        # the linear subproblem of set 0 solved by CG instead of the single step
+        cws = torch.empty(max(rb.invert_cg_workspace_bytes(g, topts, nf, "f32", 0), ws_bytes), dtype=torch.uint8,
+                          device=dev)
+        ccg = torch.empty_like(c_start)
 
-    def cg_set(k):
-        ccg.copy_(c_start)
-        return rb.invert_frequency_set_cg(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, k, ccg, ws=cws,
-                                          stream=stream)
+        def cg_set(k):
+            ccg.copy_(c_start)
+            return rb.invert_frequency_set_cg(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, k, ccg, ws=cws,
+                                              stream=stream)
 
-    def one_set():
-        ccg.copy_(c_start)
-        return rb.invert_frequency_set(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, ccg, ws=cws, stream=stream)
+        def one_set():
+            ccg.copy_(c_start)
+            return rb.invert_frequency_set(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, ccg, ws=cws, stream=stream)
 
-    t_one = timed_events(torch, stream, one_set)
-    t_1 = timed_events(torch, stream, lambda: cg_set(1))
-    t_k = timed_events(torch, stream, lambda: cg_set(args.cg_iters))
-    _, alphas, rzs = cg_set(args.cg_iters)
-    t_it = (t_k - t_1) / max(args.cg_iters - 1, 1)
-    it_flop = 12.0 * N * P * nf
-    cg = {"iters": args.cg_iters, "ms_per_set": round(t_k, 3), "ms_per_set_one_iteration": round(t_1, 3),
-          "ms_per_set_single_step": round(t_one, 3), "ms_per_extra_iteration": round(t_it, 3),
-          "iteration_tflops": round(it_flop / (t_it * 1e-3) / 1e12, 3),
-          "iteration_frac": round(it_flop / (t_it * 1e-3) / 1e12 / PEAK["f32"], 4),
-          "rz_first_last": [rzs[0], rzs[-1]]}
-    del cws
-    asws = torch.empty(rb.invert_asymptotic_workspace_bytes(g, topts, nf, "f32", 0), dtype=torch.uint8, device=dev)
+        t_one = timed_events(torch, stream, one_set)
+        t_1 = timed_events(torch, stream, lambda: cg_set(1))
+        t_k = timed_events(torch, stream, lambda: cg_set(args.cg_iters))
+        _, alphas, rzs = cg_set(args.cg_iters)
+        t_it = (t_k - t_1) / max(args.cg_iters - 1, 1)
+        it_flop = 12.0 * N * P * nf
+        cg = {"iters": args.cg_iters, "ms_per_set": round(t_k, 3), "ms_per_set_one_iteration": round(t_1, 3),
+              "ms_per_set_single_step": round(t_one, 3), "ms_per_extra_iteration": round(t_it, 3),
+              "iteration_tflops": round(it_flop / (t_it * 1e-3) / 1e12, 3),
+              "iteration_frac": round(it_flop / (t_it * 1e-3) / 1e12 / PEAK["f32"], 4),
+              "rz_first_last": [rzs[0], rzs[-1]]}
+        del cws
+        asws = torch.empty(rb.invert_asymptotic_workspace_bytes(g, topts, nf, "f32", 0), dtype=torch.uint8, device=dev)
 
-    def asym_set():
-        ccg.copy_(c_start)
-        return rb.invert_frequency_set_asymptotic(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, ccg, ws=asws,
-                                                  stream=stream)
+        def asym_set():
+            ccg.copy_(c_start)
+            return rb.invert_frequency_set_asymptotic(g, topts, prob.inv, "f32", ccg, alpha, fs, pm0, ccg, ws=asws,
+                                                      stream=stream)
 
-    cg["asymptotic_weights_ms_per_set"] = round(timed_events(torch, stream, asym_set), 3)
-    del asws, ccg
-    out["cg"] = cg
-    log(f"CG set 0: {args.cg_iters} iterations {t_k:.2f} ms, single step {t_one:.2f} ms")
+        cg["asymptotic_weights_ms_per_set"] = round(timed_events(torch, stream, asym_set), 3)
+        del asws, ccg
+        out["cg"] = cg
+        log(f"CG set 0: {args.cg_iters} iterations {t_k:.2f} ms, single step {t_one:.2f} ms")
 
     # the ToF starting model from water against straight-chord ToFs of the phantom
     T_meas = torch.as_tensor(W.straight_ray_tof(g, prob.c_true), device=dev)
