@@ -376,9 +376,10 @@ rb_status rb_invert_frequency_set_asymptotic(const rb_geometry *g, const rb_trac
  * per iteration.  The call synchronises `stream` once per iteration.
  * Every emitter's fan stays resident: ws: rb_tof_workspace_bytes() (about
  * the trace workspace of one batch of all m emitters).  The back-projection
- * uses floating-point atomics, so repeated calls agree to rounding, not
- * bitwise.  Returns RB_ENUMERIC, leaving c_out unwritten, if an update would
- * make s <= 0 somewhere.
+ * sums in 64-bit fixed point (integer atomics, exact and order-independent;
+ * contributions rounded to 2^-60 of a bound on a pixel's total), so
+ * repeated calls give bitwise-identical results.  Returns RB_ENUMERIC,
+ * leaving c_out unwritten, if an update would make s <= 0 somewhere.
  */
 size_t rb_tof_workspace_bytes(const rb_geometry *g, const rb_trace_opts *t);
 rb_status rb_tof_invert(const rb_geometry *g, const rb_trace_opts *t, const rb_invert_opts *o,

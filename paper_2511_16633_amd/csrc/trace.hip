@@ -877,8 +877,8 @@ __device__ __forceinline__ double2 tof_point(const double2 *__restrict__ XY, int
     return make_double2(a.x + fr * (b.x - a.x), a.y + fr * (b.y - a.y));
 }
 
-// One wave per pair.  SCATTER: g += L^T dT and C += L^T 1 (atomics);
-// otherwise Lv[pair] = L v (fixed-order wave sum).  Every lane walks one
+// One wave per pair.  SCATTER: g += L^T dT and C += L^T 1 in fixed point
+// (below); otherwise Lv[pair] = L v (fixed-order wave sum).  Every lane walks one
 // contiguous run of point indices on both rays of the path at once; the
 // points go into two register accumulators keyed by grid cell, so the
 // points that share a cell (two to three consecutive ones at a step of
@@ -890,12 +890,22 @@ struct TofAcc {
     double ag[4], ac[4];
 };
 
-__device__ __forceinline__ void tof_acc_flush(TofAcc &a, double *__restrict__ g, double *__restrict__ C) {
+// The back-projection sums in 64-bit fixed point: each contribution is
+// rounded to a multiple of 1 / scale (scale a power of two set from a bound
+// on a pixel's total, the residuals taken relative to max |dT|) and added
+// with an integer atomic.  Integer sums are exact and independent of their
+// order, so g and C are bitwise the same on every call.
+__device__ __forceinline__ void tof_fix_add(long long *__restrict__ q, double x, double scale) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(q), (unsigned long long)llrint(x * scale));
+}
+
+__device__ __forceinline__ void tof_acc_flush(TofAcc &a, long long *__restrict__ gq, long long *__restrict__ Cq,
+                                              double scale) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         if (a.idx[c] < 0) continue;
-        unsafeAtomicAdd(&g[a.idx[c]], a.ag[c]);
-        unsafeAtomicAdd(&C[a.idx[c]], a.ac[c]);
+        tof_fix_add(&gq[a.idx[c]], a.ag[c], scale);
+        tof_fix_add(&Cq[a.idx[c]], a.ac[c], scale);
     }
 }
 
@@ -914,7 +924,8 @@ __device__ __forceinline__ void tof_acc_open(const TP &P, TofAcc &a, int ci, int
 template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restrict__ XY, const int *__restrict__ lj,
                                                   const double2 *__restrict__ luw, const double *__restrict__ dT,
-                                                  double *__restrict__ g, double *__restrict__ C,
+                                                  const double *__restrict__ dTmax, double scale,
+                                                  long long *__restrict__ gq, long long *__restrict__ Cq,
                                                   const double *__restrict__ v, double *__restrict__ Lv) {
     const int lane = threadIdx.x & 63;
     const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -932,7 +943,8 @@ __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restric
     const double fr = u - (double)K;
     const int npts = K + 1 + (fr > 0.0 ? 1 : 0);
     const int64_t base = (int64_t)e * (P.nmax + 1) * P.nr;
-    const double res = SCATTER ? dT[pr] : 0.0;
+    // the residual relative to max |dT| (|res| <= 1)
+    const double res = SCATTER ? (dTmax[0] > 0.0 ? dT[pr] / dTmax[0] : 0.0) : 0.0;
     const int per = (npts + 63) >> 6;
     const int i0 = lane * per, i1 = min(npts, i0 + per);
     const double wq[2] = {1.0 - uw.y, uw.y};
@@ -983,10 +995,10 @@ __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restric
                     } else {
                         use1 = victim1;
                         if (use1) {
-                            tof_acc_flush(A1, g, C);
+                            tof_acc_flush(A1, gq, Cq, scale);
                             tof_acc_open(P, A1, ci, cj);
                         } else {
-                            tof_acc_flush(A0, g, C);
+                            tof_acc_flush(A0, gq, Cq, scale);
                             tof_acc_open(P, A0, ci, cj);
                         }
                     }
@@ -1012,13 +1024,24 @@ __global__ void __launch_bounds__(256) k_tof_path(TP P, const double2 *__restric
         }
     }
     if (SCATTER) {
-        tof_acc_flush(A0, g, C);
-        tof_acc_flush(A1, g, C);
+        tof_acc_flush(A0, gq, Cq, scale);
+        tof_acc_flush(A1, gq, Cq, scale);
     } else {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
         if (lane == 0) Lv[pr] = acc;
     }
+}
+
+// g = gq / scale * max |dT|, C = Cq / scale (scale a power of two: exact
+// divisions).
+__global__ void k_tof_unfix(int64_t N, const long long *__restrict__ gq, const long long *__restrict__ Cq,
+                            const double *__restrict__ dTmax, double scale, double *__restrict__ g,
+                            double *__restrict__ C) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    g[x] = (double)gq[x] / scale * dTmax[0];
+    C[x] = (double)Cq[x] / scale;
 }
 
 // Support: inside |x| < R - margin and crossed by some used path (C > 0).
@@ -1146,7 +1169,8 @@ __global__ void k_tof_update_write(int64_t n, const double *__restrict__ s, cons
 }
 
 struct TofWs {
-    double *c, *s, *g, *C, *v, *dT, *used, *Lv, *part, *res, *cmax;
+    double *c, *s, *g, *C, *v, *dT, *used, *Lv, *part, *res, *cmax, *dTmax;
+    long long *gq, *Cq;   // g, C in fixed point
     double2 *luw;
     int *lj;
     uint8_t *S;
@@ -1172,6 +1196,9 @@ TofWs carve_tof(Carver &c, const rb_geometry *g, const rb_trace_opts *t) {
     w.part = c.take<double>(3 * kTofRB);
     w.res = c.take<double>(8);
     w.cmax = c.take<double>(1);
+    w.dTmax = c.take<double>(1);
+    w.gq = c.take<long long>(N);
+    w.Cq = c.take<long long>(N);
     w.tw = carve_trace(c, g, t, g->m);   // every emitter's fan stays resident
     return w;
 }
@@ -1204,6 +1231,12 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
     const int64_t mm = (int64_t)m * m;
     const int dmin = (int)std::ceil((1.0 - o->recv_fraction) * 0.5 * m - 1e-9);
     const double rs = g->ring_radius - g->support_margin;
+    // fixed-point scale of the back-projection: a used pair adds at most
+    // about 4h of weighted path length to a pixel (two rays, weights summing
+    // to 1, the path's length inside the pixel's bilinear support plus half
+    // a step at either end), and |dT / max|dT|| <= 1, so |g|, |C| <= 4 h m^2
+    // in those units; twice that stays below 2^60 / scale
+    const double fix_scale = std::ldexp(1.0, 60 - (int)std::ceil(std::log2(8.0 * g->h * (double)mm)));
     RB_HIP(hipMemcpyAsync(w.c, c_in, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     k_rx_pos<<<blocks_for(m, 256), 256, 0, st>>>(P, w.tw.rxy);
     RB_LAUNCHED();
@@ -1232,11 +1265,15 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
         RB_LAUNCHED();
         k_tof_sums_final<<<1, 256, 0, st>>>(w.part, kTofRB, w.res, 0);   // res[1] sum dT^2, [2] used pairs
         RB_LAUNCHED();
-        // back-projection of the residuals and the ray density
-        RB_TRY(fill_f64(w.g, 0.0, N, st));
-        RB_TRY(fill_f64(w.C, 0.0, N, st));
+        // back-projection of the residuals and the ray density, in fixed point
+        RB_TRY(reduce_absmax_f64(w.dT, mm, w.part, w.dTmax, st));
+        RB_TRY(fill_u64(reinterpret_cast<uint64_t *>(w.gq), 0ull, N, st));
+        RB_TRY(fill_u64(reinterpret_cast<uint64_t *>(w.Cq), 0ull, N, st));
         const unsigned gp = (unsigned)((mm + 3) / 4);
-        k_tof_path<true><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, w.dT, w.g, w.C, nullptr, nullptr);
+        k_tof_path<true><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, w.dT, w.dTmax, fix_scale, w.gq, w.Cq,
+                                              nullptr, nullptr);
+        RB_LAUNCHED();
+        k_tof_unfix<<<blocks_for(N, 256), 256, 0, st>>>(N, w.gq, w.Cq, w.dTmax, fix_scale, w.g, w.C);
         RB_LAUNCHED();
         k_tof_support<<<blocks_for(N, 256), 256, 0, st>>>(P, rs, w.C, w.S);
         RB_LAUNCHED();
@@ -1244,7 +1281,8 @@ rb_status tof_invert_impl(const rb_geometry *g, const rb_trace_opts *t, const rb
         k_tof_direction<<<blocks_for(N, 256), 256, 0, st>>>(N, w.g, w.C, w.S, w.cmax, o->eps, w.v);
         RB_LAUNCHED();
         // exact step along v
-        k_tof_path<false><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, nullptr, nullptr, nullptr, w.v, w.Lv);
+        k_tof_path<false><<<gp, 256, 0, st>>>(P, w.tw.XY, w.lj, w.luw, nullptr, nullptr, 0.0, nullptr, nullptr,
+                                               w.v, w.Lv);
         RB_LAUNCHED();
         k_tof_sums<<<kTofRB, 256, 0, st>>>(mm, w.Lv, w.dT, w.part);
         RB_LAUNCHED();
