@@ -908,12 +908,14 @@ static FwdParams fwd_params(const rb_geometry *g, const double *freqs, int nf, r
     // FP32 kernel with direct loads), rounded down so the last round is full
     const int want = 4 * (fwd32_direct(g, dt) ? 4 : 2) * device_cus();
     int nsplit = std::max(1, want / (ntri * nf));
-    // the FP32 kernel with direct loads also keeps a split to at most
-    // kFdSplitPx pixels: the tiles of a split share its table rows in L2
-    // only while they stay within a few k-steps of each other, and long
-    // workgroups drift apart (1024 elements / 1100^2: 7 splits 144.4 ms,
-    // 30 splits 138.1 ms, 60 splits 135.0 ms for the public call)
-    if (fwd32_direct(g, dt)) nsplit = std::max<int64_t>(nsplit, (P.N + kFdSplitPx - 1) / kFdSplitPx);
+    // the kernels with direct loads (FP32, and 16-bit for large rings) also
+    // keep a split to at most kFdSplitPx pixels: the tiles of a split share
+    // its table rows in L2 only while they stay within a few k-steps of each
+    // other, and long workgroups drift apart (FP32, 1024 elements / 1100^2:
+    // 7 splits 144.4 ms, 30 splits 138.1 ms, 60 splits 135.0 ms for the
+    // public call)
+    if (fwd32_direct(g, dt) || fwd16_big(g, dt))
+        nsplit = std::max<int64_t>(nsplit, (P.N + kFdSplitPx - 1) / kFdSplitPx);
     const int kq = (dt == RB_BF16 || dt == RB_F16) ? 32 : 16;
     int64_t kchunk = (P.N + nsplit - 1) / nsplit;
     kchunk = (kchunk + kq - 1) / kq * kq;
