@@ -614,10 +614,11 @@ using Idx = std::integral_constant<int, I>;
 // A fragments (eight receivers of one emitter) come from L2 as 16-byte
 // loads, one step ahead.
 //
-// The k-steps of a pass run in rotated order, the pass's own emitter rows
-// last: those tiles are then still in the four buffers when the loop ends,
-// and the epilogue takes G_e from them with the same transposing read (four
-// emitters of one pixel per lane), without reading G again.
+// Every pass takes the k-steps in the same order, so the passes of a tile
+// (adjacent workgroups on one XCD) read each G chunk at about the same time
+// and share it in L2.  The epilogue then loads the pass's own emitter rows
+// into the freed tile buffers once more and takes G_e from them with the
+// same transposing read (four emitters of one pixel per lane).
 constexpr int kT16NT = 128;                   // pixels per tile
 constexpr int kT16KC = 32;                    // receivers per k-step
 constexpr int kT16Row = 2 * kT16NT;           // bytes per tile row
