@@ -268,9 +268,11 @@ __global__ void __launch_bounds__(NT) k_hess_band(HbParams P, const T *__restric
 }
 
 // LDS of the [m][PB] values (and the row of zeros): within 40 KiB for
-// blocks of 256 threads, 140 KiB for blocks of 1024 (whose static arrays
-// take 20 KiB more)
+// blocks of 256 threads, 140 KiB for the wide blocks (whose static arrays
+// take up to 20 KiB more)
 constexpr size_t kHbLds = 40960, kHbLdsWide = 143360;
+// the wide blocks: pixels and threads
+constexpr int kHbWidePB = 32, kHbWideNT = 1024;
 
 }  // namespace
 
@@ -289,7 +291,7 @@ rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *
     // instead of 16 or 32.
     const bool f64 = dt == RB_F64;
     const bool wide = !f64 && P.m > 256 && P.m <= 1024;
-    const int pb = wide ? 32 : (f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2)));
+    const int pb = wide ? kHbWidePB : (f64 ? (P.m <= 256 ? 16 : (P.m <= 1024 ? 4 : 1)) : (P.m <= 256 ? 32 : (P.m <= 1024 ? 8 : 2)));
     const bool zq = !f64 && pb % 4 == 0;   // the kernel's ZQ: one more row
     const size_t lds = (size_t)(P.m + (zq ? 1 : 0)) * pb * (f64 ? sizeof(double) : sizeof(float));
     if (lds > (wide ? kHbLdsWide : kHbLds)) {
@@ -311,10 +313,10 @@ rb_status hessian_band_impl(const rb_geometry *g, const void *G_re, const void *
         using L = decltype(ltag);
         const T *gr = static_cast<const T *>(G_re), *gi = static_cast<const T *>(G_im);
         if (wide) {
-            auto kfn = k_hess_band<T, L, 32, 1024>;
+            auto kfn = k_hess_band<T, L, kHbWidePB, kHbWideNT>;
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kfn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            kfn<<<nb, 1024, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag);
+            kfn<<<nb, kHbWideNT, lds, st>>>(P, gr, gi, gs, z, nzero, hdiag);
             return;
         }
         switch (pb) {
