@@ -1032,7 +1032,10 @@ struct AdjWs {
 // 1024 elements / 1100^2: 221.6 -> 209.6 ms per 4-frequency launch; 16-bit:
 // 51.9 -> 47.6 ms).  Ordering the split workgroups pass-major instead (all
 // workgroups in flight on one pass, sharing its W.D rows) was slower: 224.7
-// and 60.0 ms.  One workgroup per tile otherwise.
+// and 60.0 ms; so was nothing in between: dealing a tile's groups into 2
+// or 4 subsets on their own XCDs (each L2 then holds a half or a quarter of
+// W.D) left the launches at 211.8 / 212.3 ms (FP32, from 211.5) and 33.2 /
+// 33.4 ms (16-bit, from 33.5).  One workgroup per tile otherwise.
 static int adj_groups(const rb_geometry *g, rb_dtype dt) {
     if (dt == RB_F32) {
         const int npass = (pad_m(g->m) + 63) / 64;   // 64 emitters per pass of k_adjoint_f32
