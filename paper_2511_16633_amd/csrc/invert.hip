@@ -77,12 +77,62 @@ __device__ __forceinline__ bool selected_er(int e, int r, int m, int dmin) {
     return d >= dmin;
 }
 
-constexpr int kWThreads = 1024;
+// Data weights: receiver selection, then the kzero selected pairs with the
+// largest |p_meas|^2 of a frequency are zeroed (ties to the smaller flat
+// index).  The kzero-th largest is found by a radix select on the IEEE bits
+// of |p|^2 (non-negative doubles order like their bit patterns), stored as
+// key = bits + 1 for a selected pair and 0 for the others, so the passes
+// need no selection test and key 0 never reaches the threshold.  Digits are
+// the 12 sign/exponent bits, then 13 mantissa bits at a time (five passes).
+// The keys are parked in W, which receives the weights at the end.
+//
+// A frequency's m^2 flat indices are split into contiguous block ranges
+// (thread t owns indices lo + t, lo + t + T, ... of its block's range, so
+// every access is coalesced), and the steps are launches over all blocks of
+// all frequencies:
+//   k_wkeys   keys, and the histogram of the first digit;
+//   k_wsel    (one block per frequency) the digit at which the count of
+//             larger keys reaches the number still to zero, appended to the
+//             threshold's prefix;
+//   k_whist   the next digit's histogram among keys with that prefix;
+//   k_wties   keys equal to the threshold, per block;
+//   k_wfinal  the weights (ties ranked in flat-index order across blocks
+//             only when the threshold splits them), and per block the
+//             number of zeroed selected pairs;
+//   k_zlist   the zeroed selected pairs as (e, r) in flat-index order, for
+//             the banded Hessian diagonal.
+// Histograms are integer counts (their atomics commute), so the result does
+// not depend on scheduling.  A wave whose active lanes share a digit adds
+// them with one LDS atomic.
+constexpr int kWT = 256;            // threads per block
+constexpr int kWBins = 1 << 13;     // digit bins (the first digit uses 4096)
+constexpr int kWMaxBlocks = 64;     // blocks per frequency
+constexpr int kWU = 4;              // stripes loaded together
 
-// Exclusive prefix sum of v over the kWThreads threads of the block, in
-// thread order (wave scans by shuffles, then the 16 wave totals); `total`
-// receives the block sum.  Every thread of the block must call it.
-__device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t *s_w, int64_t &total) {
+// Blocks per frequency: about 32 stripes each, at most kWMaxBlocks.
+inline int w_blocks(int64_t mm) {
+    return (int)std::min<int64_t>(kWMaxBlocks, std::max<int64_t>(1, (mm + 32 * kWT - 1) / (32 * kWT)));
+}
+
+// The flat range [lo, hi) of block b of nb (a multiple of kWT long) and its
+// number of stripes of kWT indices.
+struct WRange {
+    int64_t lo, hi, ns;
+};
+__device__ __forceinline__ WRange w_range(int64_t mm, int nb, int b) {
+    const int64_t span = ((mm + nb - 1) / nb + kWT - 1) / kWT * kWT;
+    WRange r;
+    r.lo = min(mm, (int64_t)b * span);
+    r.hi = min(mm, r.lo + span);
+    r.ns = (r.hi - r.lo + kWT - 1) / kWT;
+    return r;
+}
+
+// Exclusive prefix sum of v over the kWT threads of the block in thread
+// order (wave scans by shuffles, then the wave totals); `total` receives the
+// block sum.  Every thread of the block must call it.
+__device__ __forceinline__ int64_t w_exscan(int64_t v, int64_t *s_w, int64_t &total) {
+    constexpr int NW = kWT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int64_t x = v;
 #pragma unroll
@@ -92,227 +142,249 @@ __device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t *s_w, int64_t
     }
     if (lane == 63) s_w[w] = x;
     __syncthreads();
-    if (w == 0) {
-        int64_t t = lane < kWThreads / 64 ? s_w[lane] : 0;
+    int64_t base = 0, tot = 0;
 #pragma unroll
-        for (int o = 1; o < kWThreads / 64; o <<= 1) {
-            const int64_t y = __shfl_up(t, o);
-            if (lane >= o) t += y;
-        }
-        if (lane < kWThreads / 64) s_w[lane] = t;   // inclusive wave prefixes
+    for (int q = 0; q < NW; ++q) {
+        const int64_t t = s_w[q];
+        if (q < w) base += t;
+        tot += t;
     }
-    __syncthreads();
-    const int64_t base = w > 0 ? s_w[w - 1] : 0;
-    total = s_w[kWThreads / 64 - 1];
+    total = tot;
     __syncthreads();   // s_w may be reused
     return base + x - v;
 }
 
-// Data weights for one frequency per block: receiver selection, then zero the
-// kzero selected pairs with the largest |p_meas|^2 (ties to the smaller flat
-// index).  The k-th largest is found by a radix select on the IEEE bits of
-// |p|^2 (non-negative doubles order like their bit patterns), stored as
-// key = bits + 1 for a selected pair and 0 for the others, so the passes
-// need no selection test and key 0 never reaches the threshold.  Digits are
-// the 12 sign/exponent bits, then 13 mantissa bits at a time (five passes).
-// Thread t owns the flat indices t, t + T, t + 2T, ... (T = kWThreads), so
-// every access is coalesced; the keys of eight stripes are loaded together.
-// The keys are parked in W, which receives the weights at the end.  A wave
-// whose active lanes share a digit adds them with one LDS atomic.  Ranks
-// among keys equal to the threshold are needed only when the threshold
-// splits them; then the ties are ranked in flat-index order by block scans
-// over the stripes.
-constexpr int kWBins = 1 << 13;
+// Adds digit dg of the lanes with `on` to an LDS histogram.  Every lane of
+// the wave calls it.
+__device__ __forceinline__ void w_hist_add(unsigned *hist, bool on, unsigned dg) {
+    const uint64_t act = __ballot(on);
+    if (act == 0) return;   // wave-uniform
+    const int first = __ffsll((unsigned long long)act) - 1;
+    const unsigned d0 = __shfl(dg, first);
+    if (__ballot(on && dg != d0) == 0) {
+        if ((int)(threadIdx.x & 63) == first) atomicAdd(&hist[d0], (unsigned)__popcll(act));
+    } else if (on) {
+        atomicAdd(&hist[dg], 1u);
+    }
+}
 
-__global__ void __launch_bounds__(kWThreads) k_weights(int m, int dmin, int64_t kzero,
-                                                       const double *__restrict__ pmeas,
-                                                       double *__restrict__ W) {
-    __shared__ unsigned hist[kWBins];
-    __shared__ int64_t s_w[kWThreads / 64];
-    __shared__ uint64_t s_pref;
-    __shared__ int64_t s_rem;
-    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+// Adds the block's LDS histogram to the frequency's global one.
+__device__ __forceinline__ void w_hist_flush(const unsigned *hist, int nbins, unsigned *gh) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < nbins; q += kWT) {
+        const unsigned c = hist[q];
+        if (c) atomicAdd(&gh[q], c);
+    }
+}
+
+// Keys (or, with kzero <= 0, the selection weights themselves) and the
+// first digit's histogram.  Grid (nb, nf).
+__global__ void __launch_bounds__(kWT) k_wkeys(int m, int dmin, int nb, int64_t kzero,
+                                               const double *__restrict__ pmeas, double *__restrict__ W,
+                                               unsigned *__restrict__ whist) {
+    __shared__ unsigned hist[1 << 12];
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
     const int64_t mm = (int64_t)m * m;
+    const WRange R = w_range(mm, nb, b);
     const double *pk = pmeas + 2 * (int64_t)k * mm;
     double *wk = W + (int64_t)k * mm;
     uint64_t *keys = reinterpret_cast<uint64_t *>(wk);
-    const int64_t ns = (mm + kWThreads - 1) / kWThreads;   // stripes of kWThreads indices
-    constexpr int kB = 8;
-    // (flat index, key) of this thread in stripe order, eight stripes' keys
-    // loaded together
-    auto walk = [&](auto f) {
-        for (int64_t s0 = 0; s0 < ns; s0 += kB) {
-            uint64_t kv[kB];
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                const int64_t i = (s0 + u) * kWThreads + tid;
-                kv[u] = (s0 + u < ns && i < mm) ? keys[i] : 0ull;
-            }
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (s0 + u >= ns) break;
-                f((s0 + u) * kWThreads + tid, kv[u]);
-            }
-        }
-    };
-    if (kzero <= 0) {   // selection only
-        const int dq = kWThreads / m, dr = kWThreads % m;
-        int e = tid / m, r = tid % m;
-        for (int64_t sidx = 0; sidx < ns; ++sidx) {
-            const int64_t i = sidx * kWThreads + tid;
-            if (i < mm) wk[i] = selected_er(e, r, m, dmin) ? 1.0 : 0.0;
-            e += dq;
-            r += dr;
-            if (r >= m) {
-                r -= m;
-                ++e;
-            }
-        }
-        return;
+    const bool sel_only = kzero <= 0;   // kernel-uniform
+    if (!sel_only) {
+        for (int q = t; q < (1 << 12); q += kWT) hist[q] = 0;
+        __syncthreads();
     }
-    {
-        const int dq = kWThreads / m, dr = kWThreads % m;
-        int e = tid / m, r = tid % m;
-        for (int64_t s0 = 0; s0 < ns; s0 += kB) {
-            double re[kB], im[kB];
+    for (int64_t s0 = 0; s0 < R.ns; s0 += kWU) {
+        double re[kWU], im[kWU];
+        bool sel[kWU];
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                const int64_t i = (s0 + u) * kWThreads + tid;
-                const bool ok = s0 + u < ns && i < mm;
-                re[u] = ok ? pk[2 * i] : 0.0;
-                im[u] = ok ? pk[2 * i + 1] : 0.0;
-            }
+        for (int u = 0; u < kWU; ++u) {
+            const int64_t i = R.lo + (s0 + u) * kWT + t;
+            const bool ok = s0 + u < R.ns && i < R.hi;
+            const int e = ok ? (int)(i / m) : 0, r = ok ? (int)(i - (int64_t)e * m) : 0;
+            sel[u] = ok && selected_er(e, r, m, dmin);
+            re[u] = (sel[u] && !sel_only) ? pk[2 * i] : 0.0;
+            im[u] = (sel[u] && !sel_only) ? pk[2 * i + 1] : 0.0;
+        }
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (s0 + u >= ns) break;
-                const int64_t i = (s0 + u) * kWThreads + tid;
-                if (i < mm)
-                    keys[i] = selected_er(e, r, m, dmin)
-                                  ? (uint64_t)__double_as_longlong(re[u] * re[u] + im[u] * im[u]) + 1ull
-                                  : 0ull;
-                e += dq;
-                r += dr;
-                if (r >= m) {
-                    r -= m;
-                    ++e;
-                }
+        for (int u = 0; u < kWU; ++u) {
+            const int64_t i = R.lo + (s0 + u) * kWT + t;
+            const bool ok = s0 + u < R.ns && i < R.hi;
+            if (sel_only) {
+                if (ok) wk[i] = sel[u] ? 1.0 : 0.0;
+                continue;
             }
+            const uint64_t key =
+                sel[u] ? (uint64_t)__double_as_longlong(re[u] * re[u] + im[u] * im[u]) + 1ull : 0ull;
+            if (ok) keys[i] = key;
+            w_hist_add(hist, key != 0, (unsigned)(key >> 52));
         }
     }
-    if (tid == 0) {
-        s_pref = 0;
-        s_rem = kzero;
+    if (sel_only) return;
+    w_hist_flush(hist, 1 << 12, whist + (int64_t)k * kWBins);
+}
+
+// Digit `pass` of the threshold (one block per frequency): the largest digit
+// value at which the count of keys with larger digits (and the prefix so
+// far) reaches the number still to zero.  State per frequency: the
+// threshold's prefix and that number.  Clears the histogram for the next
+// pass once every thread has read its bins.
+__global__ void __launch_bounds__(kWT) k_wsel(int pass, int64_t kzero, unsigned *__restrict__ whist,
+                                              uint64_t *__restrict__ wstate) {
+    __shared__ int64_t s_w[kWT / 64];
+    constexpr int D = kWBins / kWT;
+    const int k = blockIdx.x, t = threadIdx.x;
+    const int width = pass == 0 ? 12 : 13;
+    const int shift = 52 - 13 * pass;   // 52, 39, 26, 13, 0
+    const int nbins = 1 << width, dpt = nbins / kWT;
+    unsigned *gh = whist + (int64_t)k * kWBins;
+    const uint64_t pref = pass == 0 ? 0ull : wstate[2 * k];
+    const int64_t rem = pass == 0 ? kzero : (int64_t)wstate[2 * k + 1];
+    if (pass == 0 && t == 0) {   // ordered before the choice below by the scan's barriers
+        wstate[2 * k] = 0ull;
+        wstate[2 * k + 1] = (uint64_t)kzero;
     }
+    // thread t holds the digits nbins - 1 - (dpt t + u), u < dpt (descending)
+    unsigned c[D];
+    int64_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        c[u] = u < dpt ? gh[nbins - 1 - (dpt * t + u)] : 0u;
+        cnt += c[u];
+    }
+    int64_t tot;
+    int64_t ex = w_exscan(cnt, s_w, tot);
+    if (cnt > 0 && ex < rem && ex + cnt >= rem) {
+        for (int u = 0; u < dpt; ++u) {
+            if (c[u] > 0 && ex + (int64_t)c[u] >= rem) {
+                wstate[2 * k] = pref | ((uint64_t)(nbins - 1 - (dpt * t + u)) << shift);
+                wstate[2 * k + 1] = (uint64_t)(rem - ex);
+                break;
+            }
+            ex += c[u];
+        }
+    }
+    for (int q = t; q < kWBins; q += kWT) gh[q] = 0;
+}
+
+// Histogram of digit `pass` (1..4) among the keys that carry the threshold's
+// prefix.  Grid (nb, nf).
+__global__ void __launch_bounds__(kWT) k_whist(int pass, int m, int nb, const double *__restrict__ W,
+                                               const uint64_t *__restrict__ wstate, unsigned *__restrict__ whist) {
+    __shared__ unsigned hist[kWBins];
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    const WRange R = w_range(mm, nb, b);
+    const uint64_t *keys = reinterpret_cast<const uint64_t *>(W + (int64_t)k * mm);
+    for (int q = t; q < kWBins; q += kWT) hist[q] = 0;
     __syncthreads();
-    for (int pass = 0; pass < 5; ++pass) {
-        const int width = pass == 0 ? 12 : 13;
-        const int shift = 52 - 13 * pass;   // 52, 39, 26, 13, 0
-        const int nbins = 1 << width;
-        for (int q = tid; q < nbins; q += kWThreads) hist[q] = 0;
-        __syncthreads();
-        const uint64_t pref = s_pref;
-        const uint64_t hmask = pass == 0 ? 0ull : ~0ull << (shift + width);
-        const unsigned dmask = (unsigned)nbins - 1u;
-        walk([&](int64_t, uint64_t key) {
-            if (key == 0 || (key & hmask) != (pref & hmask)) return;
-            const unsigned dg = (unsigned)(key >> shift) & dmask;
-            const uint64_t act = __ballot(1);
-            const int first = __ffsll((unsigned long long)act) - 1;
-            const unsigned d0 = __shfl(dg, first);
-            if (__ballot(dg == d0) == act) {
-                if (lane == first) atomicAdd(&hist[d0], (unsigned)__popcll(act));
-            } else {
-                atomicAdd(&hist[dg], 1u);
-            }
-        });
-        __syncthreads();
-        // digits in descending order, eight per thread: thread q holds the
-        // digits nbins - 1 - 8 q - u; the chosen digit is where the running
-        // count first reaches rem
-        const int64_t rem = s_rem;
-        int64_t cnt = 0;
+    const int shift = 52 - 13 * pass;
+    const uint64_t hmask = ~0ull << (shift + 13);
+    const uint64_t pref = wstate[2 * k] & hmask;
+    for (int64_t s0 = 0; s0 < R.ns; s0 += kWU) {
+        uint64_t kv[kWU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = 8 * tid + u;
-            if (j < nbins) cnt += hist[nbins - 1 - j];
+        for (int u = 0; u < kWU; ++u) {
+            const int64_t i = R.lo + (s0 + u) * kWT + t;
+            kv[u] = (s0 + u < R.ns && i < R.hi) ? keys[i] : 0ull;
         }
-        int64_t tot;
-        int64_t ex = block_exscan(cnt, s_w, tot);
-        if (cnt > 0 && ex < rem && ex + cnt >= rem) {
-            for (int u = 0; u < 8; ++u) {
-                const int j = 8 * tid + u;
-                const int64_t c = j < nbins ? (int64_t)hist[nbins - 1 - j] : 0;
-                if (c > 0 && ex + c >= rem) {
-                    s_pref = pref | ((uint64_t)(nbins - 1 - j) << shift);
-                    s_rem = rem - ex;
-                    break;
-                }
-                ex += c;
-            }
-        }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kWU; ++u)
+            w_hist_add(hist, kv[u] != 0 && (kv[u] & hmask) == pref, (unsigned)(kv[u] >> shift) & (kWBins - 1u));
     }
-    const uint64_t kstar = s_pref;   // a selected key (>= 1)
-    const int64_t need = s_rem;      // keys equal to kstar to zero, lowest flat index first
-    int64_t ties = 0;
-    walk([&](int64_t, uint64_t key) {
-        if (key == kstar) ++ties;
-    });
-    int64_t nties;
-    (void)block_exscan(ties, s_w, nties);
+    w_hist_flush(hist, kWBins, whist + (int64_t)k * kWBins);
+}
+
+// Keys equal to the threshold, per block.  Grid (nb, nf).
+__global__ void __launch_bounds__(kWT) k_wties(int m, int nb, const double *__restrict__ W,
+                                               const uint64_t *__restrict__ wstate, int64_t *__restrict__ wcnt) {
+    __shared__ int64_t s_w[kWT / 64];
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    const WRange R = w_range(mm, nb, b);
+    const uint64_t *keys = reinterpret_cast<const uint64_t *>(W + (int64_t)k * mm);
+    const uint64_t kstar = wstate[2 * k];
+    int64_t n = 0;
+    for (int64_t s = 0; s < R.ns; ++s) {
+        const int64_t i = R.lo + s * kWT + t;
+        if (i < R.hi && keys[i] == kstar) ++n;
+    }
+    int64_t tot;
+    (void)w_exscan(n, s_w, tot);
+    if (t == 0) wcnt[(int64_t)k * kWMaxBlocks + b] = tot;
+}
+
+// The weights in place of the keys; per block, the number of zeroed
+// selected pairs.  Grid (nb, nf).
+__global__ void __launch_bounds__(kWT) k_wfinal(int m, int nb, double *__restrict__ W,
+                                                const uint64_t *__restrict__ wstate, const int64_t *__restrict__ wcnt,
+                                                int64_t *__restrict__ zcnt) {
+    __shared__ int64_t s_w[kWT / 64];
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    const WRange R = w_range(mm, nb, b);
+    double *wk = W + (int64_t)k * mm;
+    const uint64_t *keys = reinterpret_cast<const uint64_t *>(wk);
+    const uint64_t kstar = wstate[2 * k];          // a selected key (>= 1)
+    const int64_t need = (int64_t)wstate[2 * k + 1];   // keys equal to kstar to zero, lowest flat index first
+    int64_t nties = 0, base = 0;   // all ties; ties in earlier blocks
+    for (int q = 0; q < nb; ++q) {
+        const int64_t c = wcnt[(int64_t)k * kWMaxBlocks + q];
+        nties += c;
+        if (q < b) base += c;
+    }
     // all ties zeroed (need == nties) or none (need == 0) needs no ranks
-    const bool ranked = need > 0 && need < nties;
-    int64_t base = 0;   // ties in earlier stripes
-    walk([&](int64_t i, uint64_t key) {
+    const bool ranked = need > 0 && need < nties;   // kernel-uniform
+    int64_t zc = 0;
+    for (int64_t s = 0; s < R.ns; ++s) {
+        const int64_t i = R.lo + s * kWT + t;
+        const bool ok = i < R.hi;
+        const uint64_t key = ok ? keys[i] : 0ull;
         double w = (key == 0 || key > kstar) ? 0.0 : 1.0;
         const bool tie = key == kstar;
         if (tie && !ranked && need > 0) w = 0.0;
-        if (ranked) {   // block-uniform
+        if (ranked) {
             int64_t st;
-            const int64_t ex = block_exscan(tie ? 1 : 0, s_w, st);
+            const int64_t ex = w_exscan(tie ? 1 : 0, s_w, st);
             if (tie && base + ex < need) w = 0.0;
             base += st;
         }
-        if (i < mm) wk[i] = w;   // replaces this thread's own key
-    });
-}
-
-// The zeroed selected pairs of one frequency per block, as (e, r) in flat
-// index order (for the banded Hessian diagonal): per-thread counts over
-// contiguous chunks, an exclusive scan in thread order, then the writes.
-__global__ void __launch_bounds__(kWThreads) k_zero_list(int m, int dmin, const double *__restrict__ W, int zcap,
-                                                         int2 *__restrict__ zl, int *__restrict__ nz) {
-    __shared__ int64_t s_w[kWThreads / 64];
-    const int k = blockIdx.x, tid = threadIdx.x;
-    const int64_t mm = (int64_t)m * m;
-    const double *wk = W + (int64_t)k * mm;
-    const int64_t chunk = (mm + kWThreads - 1) / kWThreads;
-    const int64_t lo = std::min<int64_t>(mm, (int64_t)tid * chunk), hi = std::min<int64_t>(mm, lo + chunk);
-    const int e_lo = (int)(lo / m), r_lo = (int)(lo - (int64_t)e_lo * m);
-    int64_t cnt = 0;
-    {
-        int e = e_lo, r = r_lo;
-        for (int64_t i = lo; i < hi; ++i) {
-            if (selected_er(e, r, m, dmin) && wk[i] == 0.0) ++cnt;
-            if (++r == m) {
-                r = 0;
-                ++e;
-            }
+        if (ok) {
+            wk[i] = w;   // replaces this thread's own key
+            if (key != 0 && w == 0.0) ++zc;
         }
     }
-    int64_t total;
-    int64_t pos = block_exscan(cnt, s_w, total);
-    if (tid == 0) nz[k] = (int)std::min<int64_t>(total, zcap);
-    int e = e_lo, r = r_lo;
-    for (int64_t i = lo; i < hi && pos < zcap; ++i) {
-        if (selected_er(e, r, m, dmin) && wk[i] == 0.0) {
-            zl[(int64_t)k * zcap + pos] = make_int2(e, r);
-            ++pos;
-        }
-        if (++r == m) {
-            r = 0;
-            ++e;
-        }
+    int64_t tot;
+    (void)w_exscan(zc, s_w, tot);
+    if (t == 0) zcnt[(int64_t)k * kWMaxBlocks + b] = tot;
+}
+
+// The zeroed selected pairs of each frequency as (e, r) in flat-index order,
+// at most zcap of them, and their count.  Grid (nb, nf).
+__global__ void __launch_bounds__(kWT) k_zlist(int m, int dmin, int nb, const double *__restrict__ W,
+                                               const int64_t *__restrict__ zcnt, int zcap, int2 *__restrict__ zl,
+                                               int *__restrict__ nz) {
+    __shared__ int64_t s_w[kWT / 64];
+    const int b = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    const WRange R = w_range(mm, nb, b);
+    const double *wk = W + (int64_t)k * mm;
+    int64_t total = 0, pos = 0;   // all zeroed pairs; those in earlier blocks
+    for (int q = 0; q < nb; ++q) {
+        const int64_t c = zcnt[(int64_t)k * kWMaxBlocks + q];
+        total += c;
+        if (q < b) pos += c;
+    }
+    if (b == 0 && t == 0) nz[k] = (int)min(total, (int64_t)zcap);
+    for (int64_t s = 0; s < R.ns && pos < zcap; ++s) {   // block-uniform
+        const int64_t i = R.lo + s * kWT + t;
+        const bool ok = i < R.hi;
+        const int e = ok ? (int)(i / m) : 0, r = ok ? (int)(i - (int64_t)e * m) : 0;
+        const bool z = ok && selected_er(e, r, m, dmin) && wk[i] == 0.0;
+        int64_t st;
+        const int64_t ex = w_exscan(z ? 1 : 0, s_w, st);
+        if (z && pos + ex < zcap) zl[(int64_t)k * zcap + pos + ex] = make_int2(e, r);
+        pos += st;
     }
 }
 
@@ -638,6 +710,9 @@ struct InvWs {
     uint8_t *S;
     int2 *zl;   // zeroed pairs [nf][m m]
     int *nz;    // their counts [nf]
+    unsigned *whist;        // outlier selection: digit histograms [nf][kWBins]
+    uint64_t *wstate;       // threshold prefix and count still to zero [nf][2]
+    int64_t *wcnt, *zcnt;   // per-block ties and zeroed pairs [nf][kWMaxBlocks]
     double *x, *r, *z, *p, *q, *cg, *hist;   // CG only
     void *Hr, *Hi, *C, *C0;                   // asymptotic weights only
     double *gk, *nk, *gA, *nA;
@@ -670,6 +745,10 @@ InvWs carve_inv(Carver &c, const rb_geometry *g, int nf, rb_dtype dt, bool cg, b
     w.hmax = c.take<double>(1);
     w.zl = c.take<int2>((size_t)nf * mm);
     w.nz = c.take<int>(RB_MAX_NF);
+    w.whist = c.take<unsigned>((size_t)nf * kWBins);
+    w.wstate = c.take<uint64_t>((size_t)2 * nf);
+    w.wcnt = c.take<int64_t>((size_t)nf * kWMaxBlocks);
+    w.zcnt = c.take<int64_t>((size_t)nf * kWMaxBlocks);
     w.x = w.r = w.z = w.p = w.q = w.cg = w.hist = nullptr;
     if (cg) {
         w.x = c.take<double>(N);
@@ -815,11 +894,31 @@ static rb_status set_linearise(SetCtx &S, hipStream_t st) {
     RB_LAUNCHED();
     const int64_t n_valid = (int64_t)m * selected_count(m, S.dmin);
     const int64_t kzero = (int64_t)std::floor(o->outlier_fraction * (double)n_valid);
-    k_weights<<<nf, kWThreads, 0, st>>>(m, S.dmin, kzero, S.p_meas, w.W);
+    const int nbw = w_blocks(mm);
+    const dim3 gw(nbw, nf);
+    if (kzero <= 0) {   // selection only: no pair is zeroed
+        k_wkeys<<<gw, kWT, 0, st>>>(m, S.dmin, nbw, kzero, S.p_meas, w.W, w.whist);
+        RB_LAUNCHED();
+        return fill_f32(reinterpret_cast<float *>(w.nz), 0.0f, nf, st);   // zero bits: count 0
+    }
+    RB_TRY(fill_u64(reinterpret_cast<uint64_t *>(w.whist), 0ull, (int64_t)nf * kWBins / 2, st));
+    k_wkeys<<<gw, kWT, 0, st>>>(m, S.dmin, nbw, kzero, S.p_meas, w.W, w.whist);
+    RB_LAUNCHED();
+    for (int pass = 0; pass < 5; ++pass) {
+        k_wsel<<<nf, kWT, 0, st>>>(pass, kzero, w.whist, w.wstate);
+        RB_LAUNCHED();
+        if (pass < 4) {
+            k_whist<<<gw, kWT, 0, st>>>(pass + 1, m, nbw, w.W, w.wstate, w.whist);
+            RB_LAUNCHED();
+        }
+    }
+    k_wties<<<gw, kWT, 0, st>>>(m, nbw, w.W, w.wstate, w.wcnt);
+    RB_LAUNCHED();
+    k_wfinal<<<gw, kWT, 0, st>>>(m, nbw, w.W, w.wstate, w.wcnt, w.zcnt);
     RB_LAUNCHED();
     // the Hessian diagonal comes from the band structure of W: the
     // backprojection computes the gradient only
-    k_zero_list<<<nf, kWThreads, 0, st>>>(m, S.dmin, w.W, m * m, w.zl, w.nz);
+    k_zlist<<<gw, kWT, 0, st>>>(m, S.dmin, nbw, w.W, w.zcnt, m * m, w.zl, w.nz);
     RB_LAUNCHED();
     return RB_OK;
 }
